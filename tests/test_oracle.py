@@ -1,0 +1,356 @@
+"""Pins for the CPU oracle: every check here compares it with something other than itself.
+
+* the paper's own figure data for beta_* (Sec. 3.2, figure "fig:bucketassign"),
+* the closed form beta_eps (Theorem 2, App. C.1) against the tabulated bucket function,
+* exact bucket probabilities of beta_eps against bucket frequencies,
+* brute force: bijection onto [0, n) (the MPHF definition, Sec. 1) and minimality of every pilot
+  (the smallest p = s m + d, Sec. 4 "Hash Function" and Sec. 4.2),
+* Kiely's Rice parameter against the exact optimum of the expected code length,
+* inverses of the two 64-bit mixers and a published SplitMix64 output,
+* the space lower bound log2(e) (Sec. 1) and the paper's bits/key band for interleaved Rice coding
+  (Table 1), and the work bounds of Sec. 3.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from paper_2404_18497_amd import synth
+
+MASK = (1 << 64) - 1
+
+
+# --------------------------------------------------------------------------------------------------
+# hashing
+# --------------------------------------------------------------------------------------------------
+def _inv_xorshift(y, k):
+    x = y
+    for _ in range(64 // k + 1):
+        x = y ^ (x >> k)
+    return x & MASK
+
+
+def _inv_mix_a(z):
+    z = _inv_xorshift(z, 31)
+    z = (z * pow(0x94D049BB133111EB, -1, 1 << 64)) & MASK
+    z = _inv_xorshift(z, 27)
+    z = (z * pow(0xBF58476D1CE4E5B9, -1, 1 << 64)) & MASK
+    return _inv_xorshift(z, 30)
+
+
+def _inv_mix_b(k):
+    k = _inv_xorshift(k, 33)
+    k = (k * pow(0xC4CEB9FE1A85EC53, -1, 1 << 64)) & MASK
+    k = _inv_xorshift(k, 33)
+    k = (k * pow(0xFF51AFD7ED558CCD, -1, 1 << 64)) & MASK
+    return _inv_xorshift(k, 33)
+
+
+def test_mixers_are_bijections(ref):
+    rng = np.random.default_rng(7)
+    for v in [0, 1, MASK, 0x8000000000000000] + [int(x) for x in rng.bit_generator.random_raw(200)]:
+        assert _inv_mix_a(ref.mix_a(v)) == v
+        assert _inv_mix_b(ref.mix_b(v)) == v
+
+
+def test_splitmix64_published_output(ref):
+    # SplitMix64 seeded with 0: the state advances by the golden-ratio increment, then the output
+    # function is applied; its first two outputs are 0xE220A8397B1DCDAF and 0x6E789E6AA1B965F4.
+    assert ref.mix_a(0x9E3779B97F4A7C15) == 0xE220A8397B1DCDAF
+    assert ref.mix_a((2 * 0x9E3779B97F4A7C15) & MASK) == 0x6E789E6AA1B965F4
+
+
+def test_u64_hash_hi_is_injective_and_partitions_uniform(ref):
+    keys = np.arange(200_000, dtype=np.uint64)  # sequential keys: the worst case for a weak mixer
+    hi, lo = ref.hash_u64(keys, 0x5EED)
+    assert np.unique(hi).size == keys.size
+    K = 80
+    part = np.array([ref.partition_of(int(h), K) for h in hi[:40_000]])
+    counts = np.bincount(part, minlength=K)
+    chi2 = ((counts - 500.0) ** 2 / 500.0).sum()
+    assert chi2 < 79 + 6 * math.sqrt(2 * 79)
+    # the bucket bits (top 43 bits of lo) must look uniform as well
+    top = (lo >> np.uint64(56)).astype(np.int64)
+    c2 = np.bincount(top, minlength=256)
+    chi2 = ((c2 - keys.size / 256) ** 2 / (keys.size / 256)).sum()
+    assert chi2 < 255 + 6 * math.sqrt(2 * 255)
+
+
+def test_string_hash_distinguishes_length_and_content(ref):
+    strs = [b"", b"a", b"a\x00", b"ab", b"ba", b"abcdefgh", b"abcdefgh\x00", b"abcdefghi", b"x" * 50]
+    buf = np.frombuffer(b"".join(strs), dtype=np.uint8)
+    offs = np.zeros(len(strs) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(s) for s in strs])
+    hi, lo = ref.hash_str(buf, offs, 1)
+    pairs = set(zip(hi.tolist(), lo.tolist()))
+    assert len(pairs) == len(strs)
+
+
+# --------------------------------------------------------------------------------------------------
+# bucket assignment function
+# --------------------------------------------------------------------------------------------------
+def _golden_beta_star():
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "beta_star_figure.txt")
+    pts = [tuple(map(float, ln.split())) for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    return np.array(pts)
+
+
+def test_beta_star_matches_paper_figure(ref):
+    pts = _golden_beta_star()
+    assert len(pts) == 500
+    err = max(abs(ref.beta_star(x) - y) for x, y in pts)
+    assert err < 2e-6  # the figure prints six significant digits
+
+
+def test_table_is_beta_eps(ref):
+    # T[k] = round(2^32 beta_eps(k / 2048)) with eps = lambda / (5 sqrt(P)) (App. C.1)
+    for lam, P in [(5, 2500), (7, 2500), (9, 2500), (3.5, 100), (14, 2500)]:
+        eps = lam / (5 * math.sqrt(P))
+        assert ref.epsilon(lam, P) == pytest.approx(eps, rel=1e-15)
+        T = ref.bucket_table(lam, P)
+        assert T[0] == 0 and T[2048] == 1 << 32
+        assert np.all(np.diff(T.astype(np.int64)) >= math.floor(eps * 2**32 / 2048) - 1)
+        for k in range(1, 2048, 37):
+            x = k / 2048
+            b = eps * x + (1 - eps) * (x + (1 - x) * math.log1p(-x))
+            assert abs(int(T[k]) - b * 2**32) <= 0.5 + 1e-6 * 2**32 * 1e-6
+
+
+def test_table_nonminimal_is_rescaled(ref):
+    # gamma_alpha(x) = gamma(alpha x) / gamma(alpha) (App. B)
+    lam, P, a = 7.0, 2500, 0.99
+    eps = lam / (5 * math.sqrt(P))
+
+    def beps(x):
+        return eps * x + (1 - eps) * (x + (1 - x) * math.log1p(-x))
+
+    T = ref.bucket_table(lam, P, (99, 100))
+    for k in range(0, 2049, 64):
+        assert abs(int(T[k]) - beps(a * k / 2048) / beps(a) * 2**32) <= 0.5 + 1e-3
+
+
+def test_bucket_equals_closed_form(ref):
+    # floor(B gamma(x)) from the closed form equals the tabulated bucket, except that linear
+    # interpolation of a convex function lies above it (chord): by at most h^2/8 max gamma'' on an
+    # inner interval (gamma'' = (1 - eps) / (1 - x)) and (1 - eps) h / e on the last one, h = 1/2048
+    lam, P = 7.0, 2500
+    B = ref.num_buckets(P, lam)
+    assert B == 358
+    eps = lam / (5 * math.sqrt(P))
+    T = ref.bucket_table(lam, P)
+    lo = np.random.default_rng(3).bit_generator.random_raw(200_000).astype(np.uint64)
+    got = ref.buckets(lo, T, B).astype(np.int64)
+    x = lo.astype(np.float64) / 2.0**64
+    exact = B * (eps * x + (1 - eps) * (x + (1 - x) * np.log1p(-x)))
+    want = np.minimum(np.floor(exact), B - 1).astype(np.int64)
+    h = 1.0 / 2048
+    k = (lo >> np.uint64(53)).astype(np.int64)
+    right = (k + 1) * h
+    chord = np.where(k < 2047, h * h / 8 * (1 - eps) / np.maximum(1 - right, 1e-300), (1 - eps) * h / math.e)
+    slack = B * chord + 1e-6
+    assert np.all((got == want) | ((got == want + 1) & (np.ceil(exact) - exact <= slack))
+                  | (np.abs(exact - np.rint(exact)) < 1e-6))
+    assert (got == want).mean() > 0.999
+
+
+def test_bucket_frequencies_match_beta_eps(ref):
+    # P(bucket = i) = gamma^-1((i+1)/B) - gamma^-1(i/B) for a uniform hash (Sec. 3.1)
+    from scipy.optimize import brentq
+
+    lam, P = 7.0, 2500
+    B = ref.num_buckets(P, lam)
+    eps = lam / (5 * math.sqrt(P))
+
+    def beps(x):
+        return eps * x + (1 - eps) * (x + (1 - x) * math.log1p(-x)) if x < 1 else 1.0
+
+    inv = [0.0] + [brentq(lambda t, y=i / B: beps(t) - y, 0, 1) for i in range(1, B)] + [1.0]
+    prob = np.diff(inv)
+    N = 4_000_000
+    lo = np.random.default_rng(11).bit_generator.random_raw(N).astype(np.uint64)
+    cnt = np.bincount(ref.buckets(lo, ref.bucket_table(lam, P), B), minlength=B)
+    z = (cnt - N * prob) / np.sqrt(N * prob * (1 - prob))
+    assert np.abs(z).max() < 5.5
+    # expected sizes in a partition of P keys: largest first, capped near lambda / eps = 5 sqrt(P)
+    sizes = P * prob
+    assert np.all(np.diff(sizes) <= 1e-9)
+    assert sizes[0] == pytest.approx(130, abs=1.5)
+    assert sizes.max() <= lam / eps
+
+
+# --------------------------------------------------------------------------------------------------
+# whole-MPHF properties by brute force
+# --------------------------------------------------------------------------------------------------
+def _is_perm(pos, n):
+    return pos.size == n and np.array_equal(np.sort(pos), np.arange(n, dtype=np.uint64))
+
+
+@pytest.mark.parametrize("coding", ["rice", "compact"])
+def test_bijection_tiny_inputs(ref, coding):
+    for n in list(range(0, 40)) + [63, 64, 65, 99, 100, 101, 257, 300]:
+        for seed in (1, 2):
+            keys = synth.u64_keys(n, 1000 + 7 * n + seed)
+            for lam, P in [(1.0, 10), (3.0, 4), (5.0, 100), (7.0, 2500), (9.0, 33), (2.5, 1)]:
+                h = ref.build_u64(keys, ref.params(partition_size=P, lam=lam, coding=coding, hash_seed=seed))
+                assert _is_perm(h.query_u64(keys), n), (n, seed, lam, P)
+
+
+@pytest.mark.parametrize("alpha", [(99, 100), (9, 10), (1, 2), (1, 1)])
+def test_bijection_nonminimal_remap(ref, alpha):
+    for n in [1, 2, 5, 17, 100, 1000, 6000]:
+        keys = synth.u64_keys(n, 77 + n)
+        for P in (10, 2500):
+            h = ref.build_u64(keys, ref.params(partition_size=P, lam=5.0, alpha=alpha))
+            assert _is_perm(h.query_u64(keys), n), (n, P, alpha)
+
+
+def _replay_and_check_minimal(ref, keys, prm):
+    """Re-derive every bucket's processing order and taken set, and check by brute force over all
+    p' <= p that the oracle's pilot p is the smallest admissible one."""
+    h = ref.build_u64(keys, prm)
+    K, B = h.K, h.B
+    pil = h.pilots()
+    off = h.offsets()
+    hi, lo = ref.hash_u64(keys, prm.hash_seed)
+    part = np.array([ref.partition_of(int(x), K) for x in hi], dtype=np.int64)
+    T = ref.bucket_table(prm.lambda_, prm.partition_size, (prm.alpha_num, prm.alpha_den))
+    bk = ref.buckets(lo, T, B)
+    for j in range(K):
+        idx = np.nonzero(part == j)[0]
+        m = int(off[j + 1] - off[j])
+        assert m == idx.size
+        members = {}
+        for i in idx:
+            members.setdefault(int(bk[i]), []).append(int(i))
+        order = sorted(members, key=lambda b: (-len(members[b]), -b))
+        taken = set()
+        for b in order:
+            p = int(pil[j, b])
+            ks = members[b]
+
+            def positions(pp):
+                return [(ref.pos_hash(int(hi[i]), int(lo[i]), pp // m, m) + pp) % m for i in ks]
+
+            def ok(pp):
+                ps = positions(pp)
+                return len(set(ps)) == len(ps) and not (set(ps) & taken)
+
+            assert ok(p), (j, b, p)
+            for q in range(p):
+                assert not ok(q), (j, b, p, q)
+            if len(ks) == 1:
+                assert p < m  # size-1 buckets always land at s = 0 (Sec. 3.2, coupon term)
+            taken |= set(positions(p))
+        for b in range(B):
+            if b not in members:
+                assert pil[j, b] == 0
+        assert taken == set(range(m))
+
+
+def test_pilots_are_minimal_bruteforce(ref):
+    _replay_and_check_minimal(ref, synth.u64_keys(60, 5), ref.params(partition_size=30, lam=3.0))
+    _replay_and_check_minimal(ref, synth.u64_keys(200, 6), ref.params(partition_size=100, lam=5.0))
+    _replay_and_check_minimal(ref, synth.u64_keys(150, 8), ref.params(partition_size=150, lam=7.0))
+
+
+def test_order_independence_and_determinism(ref):
+    keys = synth.u64_keys(30_000, 12)
+    prm = ref.params(partition_size=2500, lam=7.0)
+    a = ref.build_u64(keys, prm).image()
+    b = ref.build_u64(keys[synth.permutation(keys.size, 3)], prm).image()
+    c = ref.build_u64(keys, prm, threads=4).image()
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_errors(ref):
+    keys = synth.u64_keys(1000, 4)
+    dup = np.concatenate([keys, keys[17:18]])
+    with pytest.raises(ref.OracleError) as e:
+        ref.build_u64(dup, ref.params())
+    assert e.value.code == 2
+    for bad in [dict(partition_size=0), dict(lam=0.0), dict(lam=float("nan")), dict(alpha=(2, 1)),
+                dict(alpha=(0, 1)), dict(lam=0.01)]:
+        with pytest.raises(ref.OracleError) as e:
+            ref.build_u64(keys, ref.params(**bad))
+        assert e.value.code == 1
+    with pytest.raises(ref.OracleError) as e:
+        ref.build_u64(keys, ref.params(lam=9.0, pilot_limit=3))
+    assert e.value.code == 4
+
+
+# --------------------------------------------------------------------------------------------------
+# encoders
+# --------------------------------------------------------------------------------------------------
+def test_rice_parameter_is_kiely_optimum(ref):
+    # Kiely's rule picks the Rice parameter minimising the expected code length of a geometric
+    # source: E[len] = b + 1 + t / (1 - t), t = theta^(2^b), theta = mu / (mu + 1).
+    def length(b, th):
+        t = th ** (2**b)
+        return b + 1 + t / (1 - t)
+
+    assert ref.rice_param(0, 100) == 0
+    for s in list(range(1, 3000, 3)) + list(range(3000, 5_000_000, 9973)):
+        mu = s / 1000
+        th = mu / (1 + mu)
+        L = [length(b, th) for b in range(40)]
+        best = int(np.argmin(L))
+        k = ref.rice_param(s, 1000)
+        assert k == best or abs(L[k] - L[best]) < 1e-9, (mu, k, best)
+
+
+def _header(img):
+    names = ["magic", "n", "K", "B", "P", "lambda", "alpha", "coding", "seed", "total", "dmin", "woff",
+             "sec_off", "sec_enc", "sec_data", "sec_unary", "sec_sel", "sec_remap", "wremap", "nremap",
+             "ubits", "words", "R"]
+    return dict(zip(names, [int(v) for v in img[: len(names)]]))
+
+
+@pytest.mark.parametrize("coding", ["rice", "compact"])
+def test_encoder_parameters(ref, coding):
+    keys = synth.u64_keys(50_000, 21)
+    h = ref.build_u64(keys, ref.params(lam=6.0, coding=coding))
+    img = h.image()
+    H = _header(img)
+    pil = h.pilots().astype(np.uint64)
+    K, B = H["K"], H["B"]
+    enc = img[H["sec_enc"]: H["sec_enc"] + B]
+    widths = (enc & np.uint64(0xFF)).astype(np.int64)
+    for i in range(B):
+        col = pil[:, i]
+        if coding == "compact":
+            assert widths[i] == int(col.max()).bit_length()
+        else:
+            assert widths[i] == ref.rice_param(int(col.sum()), K)
+    assert H["words"] == img.size and H["magic"] == int.from_bytes(b"PHOBIC01", "little")
+
+
+# --------------------------------------------------------------------------------------------------
+# space and work versus the paper
+# --------------------------------------------------------------------------------------------------
+def test_space_and_work_bands(ref):
+    keys = synth.u64_keys(400_000, 31)
+    # interleaved Rice coding, Table 1: 2.11 bits/key at lambda 4.5, 1.85 at 6.5, 1.74 at 9.0
+    for lam, paper in [(4.5, 2.11), (6.5, 1.85), (9.0, 1.74)]:
+        h = ref.build_u64(keys, ref.params(lam=lam), threads=8)
+        bpk = h.size_bits() / keys.size
+        assert bpk >= math.log2(math.e)
+        assert abs(bpk - paper) < 0.1, (lam, bpk)
+        probes = h.counters()["slot_probes"] / keys.size
+        # at least e^lambda / lambda per key (Prop. 2) and at most e^(lambda (1 + O(eps))) (Thm. 2)
+        eps = lam / (5 * math.sqrt(2500))
+        assert math.exp(lam) / lam < probes < 4 * math.exp(lam * (1 + 4 * eps)), (lam, probes)
+
+
+def test_offsets_are_prefix_sums(ref):
+    keys = synth.u64_keys(20_000, 41)
+    prm = ref.params(partition_size=500, lam=5.0)
+    h = ref.build_u64(keys, prm)
+    hi, _ = ref.hash_u64(keys, prm.hash_seed)
+    K = h.K
+    assert K == 40
+    part = np.array([(int(x) * K) >> 64 for x in hi])
+    want = np.concatenate([[0], np.cumsum(np.bincount(part, minlength=K))]).astype(np.uint64)
+    assert np.array_equal(h.offsets(), want)
