@@ -1,0 +1,132 @@
+/*
+ * phobic.h -- C ABI of the MI355X PHOBIC library (libphobic.so).
+ *
+ * PHOBIC (Hermann, Lehmann, Pibiri, Sanders, Walzer: "PHOBIC: Perfect Hashing with Optimized Bucket
+ * Sizes and Interleaved Coding", arXiv 2404.18497) builds a minimal perfect hash function: a
+ * bijection from a key set S onto [0, n), n = |S|, that may map keys outside S anywhere (Sec. 1).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named d_* are device pointers (HBM of the current HIP device); h_* are host pointers.
+ *    The caller owns all of them; the library never frees or retains them past the call.
+ *  - `hip_stream` is a hipStream_t (NULL = the default stream). All device work of a call is
+ *    enqueued on it.
+ *  - The library owns every phobic_mphf and its device memory until phobic_free().  A handle is
+ *    immutable after it is returned, so concurrent queries on one handle are safe.
+ *  - No exception crosses the ABI.  On failure a call returns a status other than PHOBIC_OK, sets
+ *    *out to NULL where it has one, frees what it allocated, and leaves a message for
+ *    phobic_last_error() (per thread).
+ *  - The device that is current when a handle is built or deserialized is the handle's device;
+ *    queries must run with that device current.
+ */
+#ifndef PHOBIC_H
+#define PHOBIC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PHOBIC_OK = 0,
+  PHOBIC_E_INVALID = 1,        /* bad argument or parameter */
+  PHOBIC_E_DUPLICATE = 2,      /* two keys share their 128-bit master hash code (equal keys) */
+  PHOBIC_E_OOM = 3,            /* device or host allocation failed */
+  PHOBIC_E_PILOT_OVERFLOW = 4, /* a bucket needs a pilot above params.pilot_limit */
+  PHOBIC_E_DEVICE = 5,         /* a HIP runtime call failed */
+  PHOBIC_E_FORMAT = 6,         /* a serialized image is malformed */
+  PHOBIC_E_CAPACITY = 7        /* a partition or bucket exceeds what one workgroup holds in LDS */
+} phobic_status;
+
+enum { PHOBIC_IC_RICE = 0, PHOBIC_IC_COMPACT = 1 };
+enum { PHOBIC_FLAG_KEEP_PILOTS = 1u }; /* keep the raw pilot array for phobic_get_pilots() */
+
+/* Construction parameters (Sec. 4, Sec. 4.1, Sec. 5; App. B for alpha). */
+typedef struct {
+  uint32_t partition_size; /* P: expected keys per partition; default 2500 (Sec. 5 setup) */
+  uint32_t coding;         /* PHOBIC_IC_RICE (interleaved Golomb-Rice) or PHOBIC_IC_COMPACT */
+  double lambda;           /* average bucket size; B = ceil(P / lambda) buckets per partition */
+  uint32_t alpha_num;      /* load factor alpha = alpha_num / alpha_den in (0, 1]; 1/1 = minimal; */
+  uint32_t alpha_den;      /*   alpha < 1 builds a table of ceil(n_j / alpha) slots and remaps */
+  uint64_t hash_seed;      /* seed of the 128-bit key hash */
+  uint64_t pilot_limit;    /* largest admissible pilot; 0 = 2^32 - 1 */
+  uint32_t n_compact;      /* reserved: must be 0 or B */
+  uint32_t flags;          /* PHOBIC_FLAG_* */
+} phobic_params;
+
+typedef struct phobic_mphf phobic_mphf;
+
+/* Per-phase device times of one build, in milliseconds, from HIP events on the build stream. */
+typedef struct {
+  double hash_count_ms;  /* hash + partition histogram (a1, a2) */
+  double scan_ms;        /* partition offsets (a2) */
+  double scatter_ms;     /* hash + scatter into partitions (a1, a2) */
+  double bucket_sort_ms; /* bucket mapping and ordering (a3, a4) */
+  double search_ms;      /* pilot search (a5) */
+  double encode_ms;      /* statistics, packing, remap (a6, a8) */
+  double total_ms;       /* first kernel to last, host round trips included */
+  uint64_t max_partition_keys;
+  uint32_t max_bucket_keys;
+  uint32_t reserved;
+} phobic_build_info;
+
+/* Fills *p with the defaults: P = 2500, lambda = 7, alpha = 1, interleaved Rice, seed 0x5EED. */
+void phobic_params_default(phobic_params* p);
+
+/* Builds the MPHF of the n distinct 64-bit keys d_keys[0..n) (device, 8-byte aligned).
+ * Steps: hash, partition, bucket by beta_eps, order, pilot search, interleaved coding (Sec. 3,
+ * Sec. 4, Sec. 4.1, Sec. 4.2).  Returns when the work on hip_stream is complete.  n = 0 gives a
+ * valid empty handle.  Equal keys give PHOBIC_E_DUPLICATE. */
+phobic_status phobic_build_u64(const uint64_t* d_keys, uint64_t n, const phobic_params* params,
+                               void* hip_stream, phobic_mphf** out);
+
+/* As phobic_build_u64 for n byte strings: string i is d_bytes[d_offsets[i] .. d_offsets[i+1]);
+ * d_offsets has n + 1 entries (device, non-decreasing). */
+phobic_status phobic_build_str(const uint8_t* d_bytes, const uint64_t* d_offsets, uint64_t n,
+                               const phobic_params* params, void* hip_stream, phobic_mphf** out);
+
+/* Evaluates the MPHF for n keys: d_pos[i] = position of d_keys[i] (Sec. 4, "Hash Function":
+ * (h(x, floor(p / m)) + p) mod m plus the partition offset).  Keys of the build set get distinct
+ * positions in [0, n); other keys get an arbitrary position in [0, n).  Asynchronous on
+ * hip_stream. */
+phobic_status phobic_query_u64(const phobic_mphf* h, const uint64_t* d_keys, uint64_t n, uint64_t* d_pos,
+                               void* hip_stream);
+
+/* As phobic_query_u64 for byte strings laid out as in phobic_build_str. */
+phobic_status phobic_query_str(const phobic_mphf* h, const uint8_t* d_bytes, const uint64_t* d_offsets,
+                               uint64_t n, uint64_t* d_pos, void* hip_stream);
+
+/* Size of the structure in bits = 8 x serialized bytes (header and tables included). */
+uint64_t phobic_size_bits(const phobic_mphf* h);
+uint64_t phobic_num_keys(const phobic_mphf* h);
+uint64_t phobic_num_partitions(const phobic_mphf* h);
+uint32_t phobic_num_buckets(const phobic_mphf* h);
+
+/* Copies the pilots, partition-major (h_out[j * B + i] = pilot of bucket i of partition j), into
+ * h_out (host, cap entries).  Needs PHOBIC_FLAG_KEEP_PILOTS at build time. */
+phobic_status phobic_get_pilots(const phobic_mphf* h, uint32_t* h_out, uint64_t cap);
+
+/* Per-phase times of the build that produced h (zeros for deserialized handles). */
+phobic_status phobic_get_build_info(const phobic_mphf* h, phobic_build_info* out);
+
+/* Serializes h into h_buf (host).  *inout_bytes holds the capacity on entry and the image size on
+ * return; with h_buf = NULL only the size is returned. */
+phobic_status phobic_serialize(const phobic_mphf* h, void* h_buf, uint64_t* inout_bytes);
+
+/* Rebuilds a handle on the current device from an image made by phobic_serialize. */
+phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, void* hip_stream, phobic_mphf** out);
+
+/* Stages a1-a2 alone, for parity checks: hashes and partitions the keys.  d_offsets gets K + 1
+ * key offsets, d_codes gets 2 n words: partition j's codes (hi, lo) at [2 d_offsets[j], 2
+ * d_offsets[j+1]) in unspecified order.  K = max(1, ceil(n / P)). */
+phobic_status phobic_partition_u64(const uint64_t* d_keys, uint64_t n, const phobic_params* params,
+                                   void* hip_stream, uint64_t* d_offsets, uint64_t* d_codes);
+
+void phobic_free(phobic_mphf* h);
+const char* phobic_status_str(phobic_status s);
+const char* phobic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHOBIC_H */

@@ -37,7 +37,7 @@ def build_library(force: bool = False) -> str:
     """Compile the oracle with gcc (it is plain C11 + pthreads)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-Wall", "-shared", "-fPIC", "-o", tmp, SRC,
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-Wall", "-shared", "-fPIC", "-o", tmp, SRC,
                                "-lm", "-lpthread"])
         os.replace(tmp, LIB)
     return LIB
@@ -90,6 +90,8 @@ def lib():
         L.phobic_ref_bucket_of.argtypes = [C.c_uint64, u64p, C.c_uint32]
         L.phobic_ref_bucket_of.restype = C.c_uint32
         L.phobic_ref_buckets.argtypes = [u64p, C.c_uint64, u64p, C.c_uint32, u32p]
+        L.phobic_ref_search_partition.argtypes = [u64p, u64p, C.c_uint64, C.c_uint64, C.POINTER(RefParams), u32p,
+                                                  u64p]
         L.phobic_ref_rice_param.argtypes = [C.c_uint64, C.c_uint64]
         L.phobic_ref_rice_param.restype = C.c_uint32
         L.phobic_ref_num_partitions_for.argtypes = [C.c_uint64, C.c_uint32]
@@ -196,6 +198,20 @@ def build_hashes(hi: np.ndarray, lo: np.ndarray, prm: RefParams, threads: int = 
     st = lib().phobic_ref_build_hashes(_p(hi, C.c_uint64), _p(lo, C.c_uint64), hi.size, C.byref(prm), threads,
                                        C.byref(h))
     return _finish(st, h)
+
+
+def search_partition(hi: np.ndarray, lo: np.ndarray, m: int, prm: RefParams):
+    """Pilots (B entries) of one partition with codes (hi, lo) and table size m, plus counters."""
+    hi = np.ascontiguousarray(hi, dtype=np.uint64)
+    lo = np.ascontiguousarray(lo, dtype=np.uint64)
+    B = num_buckets(prm.partition_size, prm.lambda_)
+    out = np.zeros(B, dtype=np.uint32)
+    cnt = np.zeros(4, dtype=np.uint64)
+    st = lib().phobic_ref_search_partition(_p(hi, C.c_uint64), _p(lo, C.c_uint64), hi.size, m, C.byref(prm),
+                                           _p(out, C.c_uint32), _p(cnt, C.c_uint64))
+    if st != 0:
+        raise OracleError(st)
+    return out, cnt
 
 
 def query_image_u64(image: np.ndarray, keys: np.ndarray) -> np.ndarray:

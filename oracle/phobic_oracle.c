@@ -295,7 +295,7 @@ static int order_cmp(const void *a, const void *b) {
   return 0;
 }
 
-static int build_partition(part_job *job, uint64_t j, uint64_t *stamp_buf, uint8_t *taken,
+static int build_partition(part_job *job, uint64_t j, int dup_only, uint64_t *stamp_buf, uint8_t *taken,
                            uint64_t *r, uint32_t *kb, uint32_t *cnt, uint32_t *start, uint32_t *keyidx,
                            bucket_ref *order) {
   const uint32_t B = job->B;
@@ -325,6 +325,7 @@ static int build_partition(part_job *job, uint64_t j, uint64_t *stamp_buf, uint8
         uint32_t u = keyidx[start[b] + x], v = keyidx[start[b] + y];
         if (hi[u] == hi[v] && lo[u] == lo[v]) return REF_E_DUPLICATE;
       }
+  if (dup_only) return REF_OK;
 
   /* processing order of the non-empty buckets */
   uint32_t nb = 0;
@@ -406,11 +407,35 @@ static void *part_worker(void *arg) {
   if (!stamp || !taken || !r || !kb || !keyidx || !cnt || !start || !order) {
     job->status = REF_E_OOM;
   } else {
+    /* equal codes anywhere are reported as duplicates, before any search */
     for (uint64_t j = job->j0; j < job->j1 && job->status == REF_OK; j++)
-      job->status = build_partition(job, j, stamp, taken, r, kb, cnt, start, keyidx, order);
+      job->status = build_partition(job, j, 1, stamp, taken, r, kb, cnt, start, keyidx, order);
+    for (uint64_t j = job->j0; j < job->j1 && job->status == REF_OK; j++)
+      job->status = build_partition(job, j, 0, stamp, taken, r, kb, cnt, start, keyidx, order);
   }
   free(stamp); free(taken); free(r); free(kb); free(keyidx); free(cnt); free(start); free(order);
   return NULL;
+}
+
+/* Steps 3-5 for one partition given its codes and table size m: pilots[0..B) of that partition. */
+int phobic_ref_search_partition(const uint64_t *hi, const uint64_t *lo, uint64_t nj, uint64_t m,
+                                const ref_params *prm, uint32_t *pilots, uint64_t *counters) {
+  uint32_t B;
+  int st = validate(prm, &B);
+  if (st) return st;
+  if (m < nj) return REF_E_INVALID;
+  uint64_t T[TABLE_SIZE + 1];
+  phobic_ref_bucket_table(prm->lambda, prm->partition_size, prm->alpha_num, prm->alpha_den, T);
+  uint64_t kbeg[2] = {0, nj}, toff[2] = {0, m};
+  part_job job;
+  memset(&job, 0, sizeof(job));
+  job.hi = hi; job.lo = lo; job.kbeg = kbeg; job.toff = toff; job.K = 1; job.j0 = 0; job.j1 = 1;
+  job.B = B; job.T = T; job.pilot_limit = prm->pilot_limit ? prm->pilot_limit : 0xFFFFFFFFULL;
+  job.pilots = pilots; job.status = REF_OK;
+  memset(pilots, 0, sizeof(uint32_t) * B);
+  part_worker(&job);
+  if (counters) memcpy(counters, job.counters, sizeof(job.counters));
+  return job.status;
 }
 
 /* ----------------------------------------------------------------------------------------------

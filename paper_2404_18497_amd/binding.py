@@ -1,0 +1,216 @@
+"""ctypes binding of ``libphobic.so`` (declared in ``include/phobic.h``).
+
+Argument marshalling only: torch supplies device memory and the current HIP stream; every step of
+building and querying runs in the library's HIP kernels. There is no fallback: if the library is not
+built, loading it raises.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libphobic.so")
+
+OK, E_INVALID, E_DUPLICATE, E_OOM, E_PILOT_OVERFLOW, E_DEVICE, E_FORMAT, E_CAPACITY = range(8)
+RICE, COMPACT = 0, 1
+FLAG_KEEP_PILOTS = 1
+
+EXPORTS = [
+    "phobic_params_default", "phobic_build_u64", "phobic_build_str", "phobic_query_u64", "phobic_query_str",
+    "phobic_size_bits", "phobic_num_keys", "phobic_num_partitions", "phobic_num_buckets", "phobic_get_pilots",
+    "phobic_get_build_info", "phobic_serialize", "phobic_deserialize", "phobic_partition_u64", "phobic_free",
+    "phobic_status_str", "phobic_last_error",
+]
+
+
+class PhobicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"phobic status {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("partition_size", C.c_uint32), ("coding", C.c_uint32), ("lambda_", C.c_double),
+                ("alpha_num", C.c_uint32), ("alpha_den", C.c_uint32), ("hash_seed", C.c_uint64),
+                ("pilot_limit", C.c_uint64), ("n_compact", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class BuildInfo(C.Structure):
+    _fields_ = [("hash_count_ms", C.c_double), ("scan_ms", C.c_double), ("scatter_ms", C.c_double),
+                ("bucket_sort_ms", C.c_double), ("search_ms", C.c_double), ("encode_ms", C.c_double),
+                ("total_ms", C.c_double), ("max_partition_keys", C.c_uint64), ("max_bucket_keys", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                               "python -m paper_2404_18497_amd.build_lib")
+        L = C.CDLL(LIB_PATH)
+        vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
+        P = C.POINTER(Params)
+        L.phobic_params_default.argtypes = [P]
+        L.phobic_params_default.restype = None
+        L.phobic_build_u64.argtypes = [vp, u64, P, vp, C.POINTER(vp)]
+        L.phobic_build_str.argtypes = [vp, vp, u64, P, vp, C.POINTER(vp)]
+        L.phobic_query_u64.argtypes = [vp, vp, u64, vp, vp]
+        L.phobic_query_str.argtypes = [vp, vp, vp, u64, vp, vp]
+        for name, rt in [("phobic_size_bits", u64), ("phobic_num_keys", u64), ("phobic_num_partitions", u64),
+                         ("phobic_num_buckets", u32)]:
+            getattr(L, name).argtypes = [vp]
+            getattr(L, name).restype = rt
+        L.phobic_get_pilots.argtypes = [vp, vp, u64]
+        L.phobic_get_build_info.argtypes = [vp, C.POINTER(BuildInfo)]
+        L.phobic_serialize.argtypes = [vp, vp, C.POINTER(u64)]
+        L.phobic_deserialize.argtypes = [vp, u64, vp, C.POINTER(vp)]
+        L.phobic_partition_u64.argtypes = [vp, u64, P, vp, vp, vp]
+        L.phobic_free.argtypes = [vp]
+        L.phobic_free.restype = None
+        L.phobic_status_str.argtypes = [C.c_int]
+        L.phobic_status_str.restype = C.c_char_p
+        L.phobic_last_error.argtypes = []
+        L.phobic_last_error.restype = C.c_char_p
+        for name in ["phobic_build_u64", "phobic_build_str", "phobic_query_u64", "phobic_query_str",
+                     "phobic_get_pilots", "phobic_get_build_info", "phobic_serialize", "phobic_deserialize",
+                     "phobic_partition_u64"]:
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != OK:
+        raise PhobicError(code, lib().phobic_last_error().decode(errors="replace"))
+
+
+def params(partition_size=2500, lam=7.0, alpha=(1, 1), coding="rice", hash_seed=0x5EED, pilot_limit=0,
+           keep_pilots=False) -> Params:
+    p = Params()
+    lib().phobic_params_default(C.byref(p))
+    p.partition_size = partition_size
+    p.lambda_ = float(lam)
+    p.alpha_num, p.alpha_den = alpha
+    p.coding = RICE if coding == "rice" else COMPACT
+    p.hash_seed = hash_seed
+    p.pilot_limit = pilot_limit
+    p.flags = FLAG_KEEP_PILOTS if keep_pilots else 0
+    return p
+
+
+def _stream(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t) -> C.c_void_p:
+    import torch
+
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA/HIP tensors"
+    assert t.dtype in (torch.int64, torch.uint64, torch.uint8), t.dtype
+    return C.c_void_p(t.data_ptr())
+
+
+class MPHF:
+    """A device-resident PHOBIC MPHF (owns the library handle)."""
+
+    def __init__(self, handle: C.c_void_p):
+        self.h = handle
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().phobic_free(self.h)
+            self.h = None
+
+    __del__ = close
+
+    @property
+    def n(self) -> int:
+        return lib().phobic_num_keys(self.h)
+
+    @property
+    def K(self) -> int:
+        return lib().phobic_num_partitions(self.h)
+
+    @property
+    def B(self) -> int:
+        return lib().phobic_num_buckets(self.h)
+
+    def size_bits(self) -> int:
+        return lib().phobic_size_bits(self.h)
+
+    def query_u64(self, keys, out=None, stream=None):
+        import torch
+
+        if out is None:
+            out = torch.empty(keys.numel(), dtype=torch.int64, device=keys.device)
+        _check(lib().phobic_query_u64(self.h, _dptr(keys), keys.numel(), _dptr(out), _stream(stream)))
+        return out
+
+    def query_str(self, data, offsets, out=None, stream=None):
+        import torch
+
+        n = offsets.numel() - 1
+        if out is None:
+            out = torch.empty(n, dtype=torch.int64, device=data.device)
+        _check(lib().phobic_query_str(self.h, _dptr(data), _dptr(offsets), n, _dptr(out), _stream(stream)))
+        return out
+
+    def pilots(self) -> np.ndarray:
+        out = np.zeros(self.K * self.B, dtype=np.uint32)
+        _check(lib().phobic_get_pilots(self.h, out.ctypes.data_as(C.c_void_p), out.size))
+        return out.reshape(self.K, self.B)
+
+    def build_info(self) -> dict:
+        bi = BuildInfo()
+        _check(lib().phobic_get_build_info(self.h, C.byref(bi)))
+        return {f: getattr(bi, f) for f, _ in BuildInfo._fields_ if f != "reserved"}
+
+    def serialize(self) -> np.ndarray:
+        size = C.c_uint64(0)
+        _check(lib().phobic_serialize(self.h, None, C.byref(size)))
+        buf = np.zeros(size.value // 8, dtype=np.uint64)
+        _check(lib().phobic_serialize(self.h, buf.ctypes.data_as(C.c_void_p), C.byref(size)))
+        return buf
+
+
+def build_u64(keys, prm: Params, stream=None) -> MPHF:
+    h = C.c_void_p()
+    _check(lib().phobic_build_u64(_dptr(keys), keys.numel(), C.byref(prm), _stream(stream), C.byref(h)))
+    return MPHF(h)
+
+
+def build_str(data, offsets, prm: Params, stream=None) -> MPHF:
+    h = C.c_void_p()
+    n = offsets.numel() - 1
+    _check(lib().phobic_build_str(_dptr(data), _dptr(offsets), n, C.byref(prm), _stream(stream), C.byref(h)))
+    return MPHF(h)
+
+
+def deserialize(image: np.ndarray, stream=None) -> MPHF:
+    image = np.ascontiguousarray(image, dtype=np.uint64)
+    h = C.c_void_p()
+    _check(lib().phobic_deserialize(image.ctypes.data_as(C.c_void_p), image.nbytes, _stream(stream), C.byref(h)))
+    return MPHF(h)
+
+
+def partition_u64(keys, prm: Params, stream=None):
+    """Stages a1-a2 only: (offsets[K+1], codes[n, 2]) as device tensors."""
+    import torch
+
+    n = keys.numel()
+    K = max(1, -(-n // prm.partition_size))
+    offs = torch.empty(K + 1, dtype=torch.int64, device=keys.device)
+    codes = torch.empty(max(n, 1), 2, dtype=torch.int64, device=keys.device)
+    _check(lib().phobic_partition_u64(_dptr(keys), n, C.byref(prm), _stream(stream), _dptr(offs), _dptr(codes)))
+    return offs, codes[:n]

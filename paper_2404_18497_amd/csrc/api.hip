@@ -1,0 +1,299 @@
+// Host side of the C ABI: parameters, planning (bucket-function table, Rice parameter), handles,
+// serialization and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "phobic_internal.h"
+
+namespace phobic {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+phobic_status fail(phobic_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+uint64_t num_partitions(uint64_t n, uint32_t P) {
+  uint64_t K = (n + P - 1) / P;  // expected partition size P (Sec. 4)
+  return K ? K : 1;
+}
+
+phobic_status validate_params(const phobic_params* p, uint32_t* B) {
+  if (!p) return fail(PHOBIC_E_INVALID, "params is null");
+  if (p->partition_size < 1) return fail(PHOBIC_E_INVALID, "partition_size must be >= 1");
+  if (!(p->lambda > 0.0) || !std::isfinite(p->lambda)) return fail(PHOBIC_E_INVALID, "lambda must be > 0");
+  if (p->alpha_den == 0 || p->alpha_num == 0 || p->alpha_num > p->alpha_den)
+    return fail(PHOBIC_E_INVALID, "alpha must be in (0, 1]");
+  if (p->coding > 1) return fail(PHOBIC_E_INVALID, "unknown coding");
+  if (p->pilot_limit > 0xFFFFFFFFULL) return fail(PHOBIC_E_INVALID, "pilot_limit exceeds 2^32 - 1");
+  double b = std::ceil((double)p->partition_size / p->lambda);  // B = P / lambda (Sec. 4.1)
+  if (b < 1.0 || b > 65535.0) return fail(PHOBIC_E_INVALID, "B = ceil(P / lambda) must be in [1, 65535]");
+  *B = (uint32_t)b;
+  if (p->n_compact != 0 && p->n_compact != *B) return fail(PHOBIC_E_INVALID, "n_compact must be 0 or B");
+  return PHOBIC_OK;
+}
+
+// beta_* (Sec. 3.2), beta_eps with eps = lambda / (5 sqrt(P)) (Thm. 2, App. C.1), rescaled to
+// gamma_alpha for alpha < 1 (App. B); tabulated at 2049 points as round(2^32 gamma(k / 2048)).
+static double beta_star(double x) { return x >= 1.0 ? 1.0 : x + (1.0 - x) * std::log1p(-x); }
+
+void bucket_table(double lambda, uint32_t P, uint32_t an, uint32_t ad, uint64_t* T) {
+  double eps = lambda / (5.0 * std::sqrt((double)P));
+  if (eps > 1.0) eps = 1.0;
+  auto beps = [eps](double x) { return eps * x + (1.0 - eps) * beta_star(x); };
+  const double alpha = (double)an / (double)ad;
+  const double norm = beps(alpha);
+  for (uint32_t k = 0; k <= kTableIntervals; k++) {
+    const double x = (double)k / kTableIntervals;
+    const double g = an == ad ? beps(x) : beps(alpha * x) / norm;
+    T[k] = (uint64_t)std::llround(std::ldexp(g, 32));
+  }
+  T[0] = 0;
+  T[kTableIntervals] = 1ULL << 32;
+}
+
+// Golomb-Rice parameter by Kiely's rule for a geometric source of mean mu (Sec. 4.1):
+// b = max(0, 1 + floor(log2(ln(phi - 1) / ln(mu / (mu + 1))))).
+uint32_t rice_parameter(uint64_t sum, uint64_t count) {
+  if (sum == 0 || count == 0) return 0;
+  const double mu = (double)sum / (double)count;
+  const double phi = (1.0 + std::sqrt(5.0)) / 2.0;
+  double b = 1.0 + std::floor(std::log2(std::log(phi - 1.0) / std::log(mu / (mu + 1.0))));
+  if (b < 0.0) b = 0.0;
+  if (b > 32.0) b = 32.0;
+  return (uint32_t)b;
+}
+
+phobic_status upload_table(phobic_mphf* h, hipStream_t st) {
+  std::vector<uint64_t> T(kTableIntervals + 1);
+  bucket_table(h->prm.lambda, h->prm.partition_size, h->prm.alpha_num, h->prm.alpha_den, T.data());
+  PHOBIC_HIP(hipMalloc(&h->d_table, T.size() * sizeof(uint64_t)));
+  PHOBIC_HIP(hipMemcpyAsync(h->d_table, T.data(), T.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipStreamSynchronize(st));  // T is a stack vector
+  return PHOBIC_OK;
+}
+
+void fill_query_args(phobic_mphf* h) {
+  const std::vector<uint64_t>& H = h->header;
+  QueryArgs& a = h->qa;
+  a.img = h->d_image;
+  a.table = h->d_table;
+  a.n = H[kHN];
+  a.K = H[kHK];
+  a.R = H[kHR];
+  a.total = H[kHTotal];
+  a.dmin = (int64_t)H[kHDmin];
+  a.sec_off = H[kHSecOff];
+  a.sec_enc = H[kHSecEnc];
+  a.sec_data = H[kHSecData];
+  a.sec_unary = H[kHSecUnary];
+  a.sec_sel = H[kHSecSel];
+  a.sec_remap = H[kHSecRemap];
+  a.seed = H[kHSeed];
+  a.B = (uint32_t)H[kHB];
+  a.woff = (uint32_t)H[kHWoff];
+  a.coding = (uint32_t)H[kHCoding];
+  a.wremap = (uint32_t)H[kHWremap];
+}
+
+static uint64_t host_bits(const uint64_t* w, uint64_t pos, uint32_t width) {
+  if (width == 0) return 0;
+  uint64_t idx = pos >> 6;
+  uint32_t sh = (uint32_t)(pos & 63);
+  uint64_t v = w[idx] >> sh;
+  if (sh + width > 64) v |= w[idx + 1] << (64 - sh);
+  return width == 64 ? v : (v & ((1ULL << width) - 1));
+}
+
+static uint32_t host_bit_length(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
+
+// Checks that an image is internally consistent, so the query kernel never reads outside it.
+static phobic_status check_image(const uint64_t* w, uint64_t nwords) {
+  auto bad = [](const char* what) { return fail(PHOBIC_E_FORMAT, std::string("malformed image: ") + what); };
+  if (nwords < kHeaderWords || w[kHMagic] != kMagic) return bad("magic");
+  if (w[kHWords] != nwords) return bad("length");
+  const uint64_t n = w[kHN], K = w[kHK], B = w[kHB], total = w[kHTotal];
+  if (K == 0 || B == 0 || B > 65535 || w[kHCoding] > 1 || total < n) return bad("sizes");
+  const uint32_t an = (uint32_t)w[kHAlpha], ad = (uint32_t)(w[kHAlpha] >> 32);
+  if (an == 0 || ad == 0 || an > ad || w[kHP] == 0 || w[kHP] > 0xFFFFFFFFULL) return bad("parameters");
+  double lambda;
+  std::memcpy(&lambda, &w[kHLambda], 8);
+  if (!(lambda > 0.0) || !std::isfinite(lambda) || (uint64_t)std::ceil((double)w[kHP] / lambda) != B)
+    return bad("lambda");
+  if (K != num_partitions(n, (uint32_t)w[kHP])) return bad("partition count");
+  if (w[kHWoff] > 64 || w[kHWremap] > 64) return bad("widths");
+  const uint64_t so = w[kHSecOff], se = w[kHSecEnc], sd = w[kHSecData], su = w[kHSecUnary], ss = w[kHSecSel],
+                 sr = w[kHSecRemap];
+  if (so != kHeaderWords) return bad("section order");
+  if (se != so + ((K + 1) * w[kHWoff] + 63) / 64 + 1 || sd != se + B + 1 || su < sd || ss < su || sr < ss ||
+      sr > nwords)
+    return bad("section layout");
+  // offsets: 0 first, total last, non-decreasing
+  uint64_t prev = 0;
+  for (uint64_t j = 0; j <= K; j++) {
+    uint64_t o = phobic::expected_offset_host(j, w[kHR]) + w[kHDmin] + host_bits(w + so, j * w[kHWoff], (uint32_t)w[kHWoff]);
+    if ((j == 0 && o != 0) || o < prev || (j == K && o != total)) return bad("offsets");
+    prev = o;
+  }
+  // encoders: payload inside the data section
+  const uint64_t data_bits = (su - sd - 1) * 64;
+  for (uint64_t i = 0; i < B; i++) {
+    const uint64_t e = w[se + i];
+    const uint32_t wd = (uint32_t)(e & 0xFF);
+    if (wd > 32 || (e >> 8) + (uint64_t)wd * K > data_bits) return bad("encoder table");
+  }
+  const uint64_t nvals = K * B;
+  if (w[kHCoding] == PHOBIC_IC_RICE) {
+    const uint64_t ubits = w[kHUbits];
+    if (su + (ubits + 63) / 64 + 1 != ss) return bad("unary length");
+    uint64_t ones = 0;
+    for (uint64_t i = 0; i < (ubits + 63) / 64; i++) ones += __builtin_popcountll(w[su + i]);
+    if (ones != nvals || w[ss - 1] != 0) return bad("unary stream");
+    const uint64_t nsel = (nvals + kSelEvery - 1) / kSelEvery;
+    if (ss + (nsel + 1) / 2 + 1 != sr) return bad("select length");
+    const uint32_t* sel = (const uint32_t*)(w + ss);
+    uint64_t last = 0;
+    for (uint64_t s = 0; s < nsel; s++) {
+      uint64_t p = sel[s];
+      if (p >= ubits || !((w[su + (p >> 6)] >> (p & 63)) & 1) || (s && p <= last)) return bad("select samples");
+      last = p;
+    }
+  } else if (su != ss || ss != sr) {
+    return bad("compact layout");
+  }
+  const uint64_t nremap = total - n;
+  if (w[kHNremap] != nremap || (nremap && w[kHWremap] != (n > 1 ? host_bit_length(n - 1) : 0)))
+    return bad("remap");
+  const uint64_t want_end = sr + (nremap ? (nremap * w[kHWremap] + 63) / 64 + 1 : 0);
+  if (want_end != nwords) return bad("remap length");
+  for (uint64_t g = 0; g < nremap; g++)
+    if (host_bits(w + sr, g * w[kHWremap], (uint32_t)w[kHWremap]) >= n) return bad("remap entries");
+  return PHOBIC_OK;
+}
+
+}  // namespace phobic
+
+using namespace phobic;
+
+extern "C" void phobic_params_default(phobic_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->partition_size = 2500;
+  p->coding = PHOBIC_IC_RICE;
+  p->lambda = 7.0;
+  p->alpha_num = 1;
+  p->alpha_den = 1;
+  p->hash_seed = 0x5EED;
+}
+
+extern "C" uint64_t phobic_size_bits(const phobic_mphf* h) { return h ? h->nwords * 64 : 0; }
+extern "C" uint64_t phobic_num_keys(const phobic_mphf* h) { return h ? h->n : 0; }
+extern "C" uint64_t phobic_num_partitions(const phobic_mphf* h) { return h ? h->K : 0; }
+extern "C" uint32_t phobic_num_buckets(const phobic_mphf* h) { return h ? h->B : 0; }
+
+extern "C" phobic_status phobic_get_pilots(const phobic_mphf* h, uint32_t* h_out, uint64_t cap) {
+  if (!h || !h_out) return fail(PHOBIC_E_INVALID, "null argument");
+  if (!h->d_pilots) return fail(PHOBIC_E_INVALID, "the handle was built without PHOBIC_FLAG_KEEP_PILOTS");
+  const uint64_t K = h->K, B = h->B;
+  if (cap < K * B) return fail(PHOBIC_E_INVALID, "output buffer too small");
+  std::vector<uint32_t> em(K * B);
+  PHOBIC_HIP(hipMemcpy(em.data(), h->d_pilots, em.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+  for (uint64_t i = 0; i < B; i++)
+    for (uint64_t j = 0; j < K; j++) h_out[j * B + i] = em[i * K + j];
+  return PHOBIC_OK;
+}
+
+extern "C" phobic_status phobic_get_build_info(const phobic_mphf* h, phobic_build_info* out) {
+  if (!h || !out) return fail(PHOBIC_E_INVALID, "null argument");
+  *out = h->info;
+  return PHOBIC_OK;
+}
+
+extern "C" phobic_status phobic_serialize(const phobic_mphf* h, void* h_buf, uint64_t* inout_bytes) {
+  if (!h || !inout_bytes) return fail(PHOBIC_E_INVALID, "null argument");
+  const uint64_t bytes = h->nwords * sizeof(uint64_t);
+  if (!h_buf) {
+    *inout_bytes = bytes;
+    return PHOBIC_OK;
+  }
+  if (*inout_bytes < bytes) {
+    *inout_bytes = bytes;
+    return fail(PHOBIC_E_INVALID, "buffer too small");
+  }
+  PHOBIC_HIP(hipMemcpy(h_buf, h->d_image, bytes, hipMemcpyDeviceToHost));
+  *inout_bytes = bytes;
+  return PHOBIC_OK;
+}
+
+extern "C" phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, void* hip_stream, phobic_mphf** out) {
+  if (!out) return fail(PHOBIC_E_INVALID, "out is null");
+  *out = nullptr;
+  if (!h_buf || bytes % 8 != 0) return fail(PHOBIC_E_FORMAT, "image size is not a whole number of words");
+  const uint64_t nwords = bytes / 8;
+  std::vector<uint64_t> w(nwords);
+  std::memcpy(w.data(), h_buf, bytes);
+  phobic_status s = check_image(w.data(), nwords);
+  if (s != PHOBIC_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  auto h = new phobic_mphf();
+  PHOBIC_HIP(hipGetDevice(&h->device));
+  h->n = w[kHN];
+  h->K = w[kHK];
+  h->B = (uint32_t)w[kHB];
+  h->header.assign(w.begin(), w.begin() + kHeaderWords);
+  phobic_params_default(&h->prm);
+  h->prm.partition_size = (uint32_t)w[kHP];
+  std::memcpy(&h->prm.lambda, &w[kHLambda], 8);
+  h->prm.alpha_num = (uint32_t)w[kHAlpha];
+  h->prm.alpha_den = (uint32_t)(w[kHAlpha] >> 32);
+  h->prm.coding = (uint32_t)w[kHCoding];
+  h->prm.hash_seed = w[kHSeed];
+  h->nwords = nwords;
+  phobic_status r = upload_table(h, st);
+  if (r != PHOBIC_OK) {
+    phobic_free(h);
+    return r;
+  }
+  hipError_t e = hipMalloc(&h->d_image, bytes);
+  if (e == hipSuccess) e = hipMemcpy(h->d_image, w.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    phobic_free(h);
+    return fail(e == hipErrorOutOfMemory ? PHOBIC_E_OOM : PHOBIC_E_DEVICE, hipGetErrorString(e));
+  }
+  fill_query_args(h);
+  *out = h;
+  return PHOBIC_OK;
+}
+
+extern "C" void phobic_free(phobic_mphf* h) {
+  if (!h) return;
+  if (h->d_image) (void)hipFree(h->d_image);
+  if (h->d_table) (void)hipFree(h->d_table);
+  if (h->d_pilots) (void)hipFree(h->d_pilots);
+  delete h;
+}
+
+extern "C" const char* phobic_status_str(phobic_status s) {
+  switch (s) {
+    case PHOBIC_OK: return "ok";
+    case PHOBIC_E_INVALID: return "invalid argument";
+    case PHOBIC_E_DUPLICATE: return "duplicate keys";
+    case PHOBIC_E_OOM: return "out of memory";
+    case PHOBIC_E_PILOT_OVERFLOW: return "pilot overflow";
+    case PHOBIC_E_DEVICE: return "device error";
+    case PHOBIC_E_FORMAT: return "malformed image";
+    case PHOBIC_E_CAPACITY: return "capacity exceeded";
+  }
+  return "unknown status";
+}
+
+extern "C" const char* phobic_last_error(void) { return g_last_error.c_str(); }

@@ -1,0 +1,184 @@
+// Internal declarations of the MI355X PHOBIC library: image layout, handle, error plumbing and the
+// device helpers shared by the build and query kernels.  Everything here follows the specification
+// of the key hash, the bucket function and the image; none of it is shared with the CPU oracle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "phobic.h"
+
+namespace phobic {
+
+// ---------------------------------------------------------------------------------------------
+// Limits of the device path.  One partition is handled by one workgroup whose working set lives in
+// LDS: the per-key bucket records of the bucket sort (4 bytes per key) and the free-slot bitmap of
+// the search.  Larger partitions or more buckets are reported as PHOBIC_E_CAPACITY.
+// ---------------------------------------------------------------------------------------------
+constexpr uint32_t kMaxPartitionKeys = 8192;  // n_j
+constexpr uint32_t kMaxTableSlots = 16384;    // m_j (alpha < 1 enlarges n_j)
+constexpr uint32_t kMaxBuckets = 2048;        // B
+constexpr uint32_t kTableIntervals = 2048;    // bucket-function table: 2048 intervals, 2049 points
+constexpr uint32_t kSelEvery = 256;           // one select sample per 256 ones
+
+// Image header word indices (little-endian 64-bit words).
+enum : uint32_t {
+  kHMagic = 0, kHN, kHK, kHB, kHP, kHLambda, kHAlpha, kHCoding, kHSeed, kHTotal, kHDmin, kHWoff,
+  kHSecOff, kHSecEnc, kHSecData, kHSecUnary, kHSecSel, kHSecRemap, kHWremap, kHNremap, kHUbits,
+  kHWords, kHR, kHSpare, kHeaderWords
+};
+constexpr uint64_t kMagic = 0x31304349424F4850ULL;  // "PHOBIC01"
+
+// Everything a query kernel needs, passed by value.
+struct QueryArgs {
+  const uint64_t* img;    // device image
+  const uint64_t* table;  // device bucket-function table (kTableIntervals + 1 entries)
+  uint64_t n, K, R, total;
+  int64_t dmin;
+  uint64_t sec_off, sec_enc, sec_data, sec_unary, sec_sel, sec_remap;
+  uint64_t seed;
+  uint32_t B, woff, coding, wremap;
+};
+
+}  // namespace phobic
+
+struct phobic_mphf {
+  int device = 0;
+  uint64_t n = 0, K = 0;
+  uint32_t B = 0;
+  phobic_params prm{};
+  uint64_t* d_image = nullptr;
+  uint64_t nwords = 0;
+  std::vector<uint64_t> header;   // host copy of the header words
+  uint64_t* d_table = nullptr;
+  uint32_t* d_pilots = nullptr;   // encoder-major (i * K + j), only with PHOBIC_FLAG_KEEP_PILOTS
+  phobic_build_info info{};
+  phobic::QueryArgs qa{};
+};
+
+namespace phobic {
+
+// ---------------------------------------------------------------------------------------------
+// Error plumbing (host).
+// ---------------------------------------------------------------------------------------------
+void set_error(const std::string& msg);
+phobic_status fail(phobic_status s, const std::string& msg);
+#define PHOBIC_HIP(call)                                                                            \
+  do {                                                                                              \
+    hipError_t e_ = (call);                                                                         \
+    if (e_ != hipSuccess)                                                                           \
+      return ::phobic::fail(e_ == hipErrorOutOfMemory ? PHOBIC_E_OOM : PHOBIC_E_DEVICE,              \
+                            std::string(#call) + ": " + hipGetErrorString(e_));                    \
+  } while (0)
+
+// Host planning shared by build and deserialize.
+phobic_status validate_params(const phobic_params* p, uint32_t* B);
+uint64_t num_partitions(uint64_t n, uint32_t P);
+void bucket_table(double lambda, uint32_t P, uint32_t an, uint32_t ad, uint64_t* T);
+uint32_t rice_parameter(uint64_t sum, uint64_t count);
+phobic_status upload_table(phobic_mphf* h, hipStream_t st);
+void fill_query_args(phobic_mphf* h);
+
+// ---------------------------------------------------------------------------------------------
+// Device helpers.
+// ---------------------------------------------------------------------------------------------
+constexpr uint64_t kPhi64 = 0x9E3779B97F4A7C15ULL;
+constexpr uint64_t kSqrt2 = 0x6A09E667F3BCC909ULL;
+
+// SplitMix64 output function (Steele, Lea, Flood; Stafford variant 13).
+__host__ __device__ __forceinline__ uint64_t mix_a(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+// MurmurHash3 fmix64 (Appleby).
+__host__ __device__ __forceinline__ uint64_t mix_b(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xFF51AFD7ED558CCDULL;
+  k ^= k >> 33;
+  k *= 0xC4CEB9FE1A85EC53ULL;
+  return k ^ (k >> 33);
+}
+
+// floor(z * m / 2^64) for m < 2^32, from two 32x32 products.
+__device__ __forceinline__ uint32_t mulhi_u32(uint64_t z, uint32_t m) {
+  uint64_t lo = (uint64_t)(uint32_t)z * m;
+  uint64_t hi = (uint64_t)(uint32_t)(z >> 32) * m + (lo >> 32);
+  return (uint32_t)(hi >> 32);
+}
+
+__device__ __forceinline__ void hash_key_u64(uint64_t key, uint64_t seed, uint64_t& hi, uint64_t& lo) {
+  hi = mix_a(key ^ seed);
+  lo = mix_b(key ^ seed ^ kSqrt2);
+}
+
+// Byte string -> (hi, lo): two chains over little-endian 8-byte words, finished with the length.
+__device__ __forceinline__ void hash_key_str(const uint8_t* s, uint64_t len, uint64_t seed, uint64_t& hi,
+                                             uint64_t& lo) {
+  uint64_t a = seed, b = seed ^ kSqrt2;
+  uint64_t i = 0;
+  for (; i + 8 <= len; i += 8) {
+    uint64_t w = 0;
+#pragma unroll
+    for (int t = 0; t < 8; t++) w |= (uint64_t)s[i + t] << (8 * t);
+    a = mix_a(a ^ w);
+    b = mix_b(b ^ w);
+  }
+  if (i < len) {
+    uint64_t w = 0;
+    for (uint64_t t = 0; i + t < len; t++) w |= (uint64_t)s[i + t] << (8 * t);
+    a = mix_a(a ^ w);
+    b = mix_b(b ^ w);
+  }
+  hi = mix_a(a ^ len);
+  lo = mix_b(b ^ len);
+}
+
+// Seeded position hash h(x, s) in [0, m).
+__device__ __forceinline__ uint32_t pos_hash(uint64_t hi, uint64_t lo, uint64_t s, uint32_t m) {
+  return mulhi_u32(mix_a(lo ^ mix_b(hi ^ ((s + 1) * kPhi64))), m);
+}
+
+// Bucket of a key: linear interpolation of the tabulated bucket function, scaled to B buckets.
+__device__ __forceinline__ uint32_t bucket_of(uint64_t lo, const uint64_t* __restrict__ T, uint32_t B) {
+  uint32_t k = (uint32_t)(lo >> 53);
+  uint64_t f = (lo >> 21) & 0xFFFFFFFFULL;
+  uint64_t t0 = T[k], t1 = T[k + 1];
+  uint64_t y = t0 + (((t1 - t0) * f) >> 32);
+  uint32_t b = (uint32_t)((y * B) >> 32);
+  return b < B - 1 ? b : B - 1;
+}
+
+// Reads width (<= 64) bits at bit position pos of a word array (one zero word of slack follows
+// every section, so the second word is always in bounds).
+__device__ __forceinline__ uint64_t get_bits(const uint64_t* __restrict__ w, uint64_t pos, uint32_t width) {
+  if (width == 0) return 0;
+  uint64_t idx = pos >> 6;
+  uint32_t sh = (uint32_t)(pos & 63);
+  uint64_t v = w[idx] >> sh;
+  if (sh + width > 64) v |= w[idx + 1] << (64 - sh);
+  return width == 64 ? v : (v & ((1ULL << width) - 1));
+}
+
+__device__ __forceinline__ void put_bits_atomic(uint64_t* w, uint64_t pos, uint64_t v, uint32_t width) {
+  if (width == 0) return;
+  uint64_t idx = pos >> 6;
+  uint32_t sh = (uint32_t)(pos & 63);
+  atomicOr((unsigned long long*)&w[idx], (unsigned long long)(v << sh));
+  if (sh + width > 64) atomicOr((unsigned long long*)&w[idx + 1], (unsigned long long)(v >> (64 - sh)));
+}
+
+// Expected table offset of partition j: floor(j * R / 2^32), R = floor(total * 2^32 / K).
+__device__ __forceinline__ uint64_t expected_offset(uint64_t j, uint64_t R) {
+  return (j * R >> 32) | (__umul64hi(j, R) << 32);
+}
+
+inline uint64_t expected_offset_host(uint64_t j, uint64_t R) {
+  return (uint64_t)(((unsigned __int128)j * R) >> 32);
+}
+
+}  // namespace phobic

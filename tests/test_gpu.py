@@ -1,0 +1,231 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit, through the C ABI.
+
+Compared on the same seeded keys: partition offsets and per-partition code multisets (a1-a2), the
+pilot array (a3-a5), the serialized image word for word (a6), and query outputs (a7); at the
+1M-key workload in full, on edge shapes, and at the 100M-key benchmark workload on sampled
+partitions and keys plus properties that hold at any size (bijection onto [0, n)).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_18497_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    binding.lib()  # must load: no fallback
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+
+
+def _both(torch, keys, lam=7.0, P=2500, alpha=(1, 1), coding="rice", seed=0x5EED, pilot_limit=0):
+    gp = binding.params(partition_size=P, lam=lam, alpha=alpha, coding=coding, hash_seed=seed, pilot_limit=pilot_limit,
+                        keep_pilots=True)
+    rp = oracle.params(partition_size=P, lam=lam, alpha=alpha, coding=coding, hash_seed=seed, pilot_limit=pilot_limit)
+    g = binding.build_u64(_dev(torch, keys), gp)
+    r = oracle.build_u64(keys, rp, threads=8)
+    return g, r
+
+
+def _check_same(torch, g, r, keys, query_ref=True):
+    assert g.K == r.K and g.B == r.B
+    assert np.array_equal(g.pilots(), r.pilots()), "pilot arrays differ"
+    gi, ri = g.serialize(), r.image()
+    assert gi.size == ri.size, (gi.size, ri.size)
+    assert np.array_equal(gi, ri), f"images differ at words {np.nonzero(gi != ri)[0][:10]}"
+    pos = g.query_u64(_dev(torch, keys)).cpu().numpy().view(np.uint64)
+    n = keys.size
+    assert np.array_equal(np.sort(pos), np.arange(n, dtype=np.uint64)), "not a bijection onto [0, n)"
+    if query_ref:
+        assert np.array_equal(pos, r.query_u64(keys))
+    return pos
+
+
+def test_partition_stage_parity(torch):
+    # offsets equal the oracle's; the codes form the same multiset; every code sits in the
+    # partition its hi selects -> identical per-partition multisets
+    for n, P in [(1_000_000, 2500), (12_345, 100), (1, 2500), (5, 1), (2501, 2500), (0, 2500)]:
+        _say("partition", n, P)
+        keys = synth.u64_keys(n, 1)
+        offs, codes = binding.partition_u64(_dev(torch, keys), binding.params(partition_size=P))
+        offs = offs.cpu().numpy().view(np.uint64)
+        codes = codes.cpu().numpy().view(np.uint64).reshape(-1, 2)
+        r = oracle.build_u64(keys, oracle.params(partition_size=P, lam=5.0), threads=8)
+        assert np.array_equal(offs, r.offsets())
+        hi, lo = oracle.hash_u64(keys, 0x5EED)
+        want = np.stack([hi, lo], axis=1)
+        assert np.array_equal(want[np.lexsort((lo, hi))], codes[np.lexsort((codes[:, 1], codes[:, 0]))])
+        K = offs.size - 1
+        where = np.searchsorted(offs[1:].astype(np.int64), np.arange(n), side="right")
+        for i in range(n):
+            assert oracle.partition_of(int(codes[i, 0]), K) == where[i]
+
+
+@pytest.mark.parametrize("coding", ["rice", "compact"])
+def test_config1_full_parity(torch, coding):
+    # 1M distinct uniform u64 keys, lambda 7, P 2500, alpha 1: pilots, image and every query
+    keys = synth.u64_keys(1_000_000, 1)
+    _say("config1", coding)
+    g, r = _both(torch, keys, coding=coding)
+    _check_same(torch, g, r, keys[synth.permutation(keys.size, 11)])
+
+
+@pytest.mark.parametrize("lam", [1.5, 3.0, 5.0, 9.0])
+def test_lambda_sweep_parity(torch, lam):
+    keys = synth.u64_keys(200_000, 3)
+    _say("lambda", lam)
+    g, r = _both(torch, keys, lam=lam)
+    _check_same(torch, g, r, keys)
+
+
+EDGE = [(0, 2500), (1, 2500), (2, 2500), (63, 2500), (64, 2500), (65, 2500), (2499, 2500), (2500, 2500),
+        (2501, 2500), (10_007, 2500), (7, 1), (40, 3), (1000, 17), (300, 64)]
+
+
+@pytest.mark.parametrize("n,P", EDGE)
+def test_edge_shapes(torch, n, P):
+    _say("edge", n, P)
+    keys = synth.u64_keys(n, 500 + n)
+    for coding in ("rice", "compact"):
+        g, r = _both(torch, keys, lam=4.0, P=P, coding=coding)
+        assert np.array_equal(g.serialize(), r.image())
+        if n:
+            _check_same(torch, g, r, keys)
+
+
+@pytest.mark.parametrize("alpha", [(99, 100), (9, 10), (1, 2)])
+def test_nonminimal_remap_parity(torch, alpha):
+    keys = synth.u64_keys(150_000, 8)
+    _say("alpha", alpha)
+    g, r = _both(torch, keys, lam=6.0, alpha=alpha)
+    _check_same(torch, g, r, keys)
+
+
+def test_strings_parity(torch):
+    buf, offs = synth.ascii_strings(100_000, 3)
+    _say("strings")
+    for alpha in [(1, 1), (99, 100)]:
+        gp = binding.params(alpha=alpha, keep_pilots=True)
+        rp = oracle.params(alpha=alpha)
+        g = binding.build_str(torch.from_numpy(buf).cuda(), _dev(torch, offs), gp)
+        r = oracle.build_str(buf, offs, rp, threads=8)
+        assert np.array_equal(g.pilots(), r.pilots())
+        assert np.array_equal(g.serialize(), r.image())
+        pos = g.query_str(torch.from_numpy(buf).cuda(), _dev(torch, offs)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(pos, r.query_str(buf, offs))
+        assert np.array_equal(np.sort(pos), np.arange(offs.size - 1, dtype=np.uint64))
+
+
+def test_errors(torch):
+    keys = synth.u64_keys(5000, 9)
+    dup = np.concatenate([keys, keys[100:101]])
+    _say("errors")
+    with pytest.raises(binding.PhobicError) as e:
+        binding.build_u64(_dev(torch, dup), binding.params())
+    assert e.value.code == binding.E_DUPLICATE
+    many = np.concatenate([keys, np.repeat(keys[:1], 20)])
+    with pytest.raises(binding.PhobicError) as e:
+        binding.build_u64(_dev(torch, many), binding.params())
+    assert e.value.code == binding.E_DUPLICATE
+    with pytest.raises(binding.PhobicError) as e:
+        binding.build_u64(_dev(torch, keys), binding.params(lam=9.0, pilot_limit=3))
+    assert e.value.code == binding.E_PILOT_OVERFLOW
+    with pytest.raises(binding.PhobicError) as e:
+        binding.build_u64(_dev(torch, keys), binding.params(lam=0.5, partition_size=2500))
+    assert e.value.code == binding.E_CAPACITY
+    # the oracle agrees on the first three
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64(dup, oracle.params())
+    assert e.value.code == binding.E_DUPLICATE
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.build_u64(keys, oracle.params(lam=9.0, pilot_limit=3))
+    assert e.value.code == binding.E_PILOT_OVERFLOW
+
+
+def test_serialize_roundtrip_and_oracle_reads_gpu_image(torch):
+    keys = synth.u64_keys(300_000, 10)
+    _say("roundtrip")
+    g = binding.build_u64(_dev(torch, keys), binding.params(lam=7.0))
+    img = g.serialize()
+    h = binding.deserialize(img)
+    a = g.query_u64(_dev(torch, keys)).cpu().numpy()
+    b = h.query_u64(_dev(torch, keys)).cpu().numpy()
+    assert np.array_equal(a, b)
+    assert np.array_equal(oracle.query_image_u64(img, keys), a.view(np.uint64))
+    assert g.size_bits() == 64 * img.size
+    # non-members land somewhere in [0, n)
+    other = synth.u64_keys(100_000, 99)
+    pos = g.query_u64(_dev(torch, other)).cpu().numpy()
+    assert pos.min() >= 0 and pos.max() < keys.size
+    bad = img.copy()
+    bad[30] ^= np.uint64(1 << 40)  # corrupt an offset word
+    with pytest.raises(binding.PhobicError) as e:
+        binding.deserialize(bad)
+    assert e.value.code == binding.E_FORMAT
+
+
+def test_determinism_and_order_independence(torch):
+    keys = synth.u64_keys(500_000, 12)
+    _say("determinism")
+    p = binding.params(lam=7.0)
+    a = binding.build_u64(_dev(torch, keys), p).serialize()
+    b = binding.build_u64(_dev(torch, keys), p).serialize()
+    c = binding.build_u64(_dev(torch, keys[synth.permutation(keys.size, 5)]), p).serialize()
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_full_size_100m_sampled(torch):
+    """The benchmark workload (100M keys, lambda 7, Rice): bijection over all keys; pilots of sampled
+    partitions against the oracle's search on the same codes; sampled queries against the oracle
+    reading the GPU image; encoder parameters against the pilot statistics."""
+    n = 100_000_000
+    _say("100M keys: generate")
+    keys = synth.u64_keys(n, 1)
+    dk = _dev(torch, keys)
+    prm = binding.params(lam=7.0, keep_pilots=True)
+    _say("100M keys: build")
+    g = binding.build_u64(dk, prm)
+    _say("100M keys: query all")
+    pos = g.query_u64(dk)
+    cnt = torch.zeros(n, dtype=torch.int32, device=dk.device)
+    cnt.index_add_(0, pos, torch.ones(n, dtype=torch.int32, device=dk.device))
+    assert int(cnt.min()) == 1 and int(cnt.max()) == 1, "not a bijection onto [0, n)"
+    del cnt
+    _say("100M keys: sampled partitions")
+    offs, codes = binding.partition_u64(dk, prm)
+    offs = offs.cpu().numpy().view(np.uint64)
+    pil = g.pilots()
+    rng = np.random.default_rng(4)
+    rp = oracle.params(lam=7.0)
+    for j in rng.integers(0, g.K, 24):
+        a, b = int(offs[j]), int(offs[j + 1])
+        c = codes[a:b].cpu().numpy().view(np.uint64)
+        want, _ = oracle.search_partition(c[:, 0], c[:, 1], b - a, rp)
+        assert np.array_equal(pil[j], want), f"partition {j}"
+    _say("100M keys: sampled queries vs oracle decoding of the image")
+    img = g.serialize()
+    sample = rng.integers(0, n, 200_000)
+    got = pos[torch.from_numpy(sample).cuda()].cpu().numpy().view(np.uint64)
+    assert np.array_equal(oracle.query_image_u64(img, keys[sample]), got)
+    _say("100M keys: encoder parameters")
+    K, B = g.K, g.B
+    enc = img[int(img[13]): int(img[13]) + B]
+    for i in range(0, B, 7):
+        assert int(enc[i]) & 0xFF == oracle.rice_param(int(pil[:, i].astype(np.uint64).sum()), K)
+    bits = g.size_bits() / n
+    _say("100M keys: bits/key", bits)
+    assert 1.75 < bits < 1.9
