@@ -160,13 +160,27 @@ static phobic_status check_image(const uint64_t* w, uint64_t nwords) {
     if (ones != nvals || w[ss - 1] != 0) return bad("unary stream");
     const uint64_t nsel = (nvals + kSelEvery - 1) / kSelEvery;
     if (ss + (nsel + 1) / 2 + 1 != sr) return bad("select length");
+    // every sample must be exactly the position of one number 256 s
     const uint32_t* sel = (const uint32_t*)(w + ss);
-    uint64_t last = 0;
-    for (uint64_t s = 0; s < nsel; s++) {
-      uint64_t p = sel[s];
-      if (p >= ubits || !((w[su + (p >> 6)] >> (p & 63)) & 1) || (s && p <= last)) return bad("select samples");
-      last = p;
+    uint64_t seen = 0, s_next = 0;
+    for (uint64_t i = 0; i < (ubits + 63) / 64 && s_next < nsel; i++) {
+      uint64_t x = w[su + i];
+      while (x && s_next < nsel) {
+        const uint64_t c = (uint64_t)__builtin_popcountll(x);
+        const uint64_t want = s_next * kSelEvery;
+        if (seen + c <= want) {
+          seen += c;
+          break;
+        }
+        for (uint64_t skip = want - seen; skip; skip--) x &= x - 1;  // drop ones before the target
+        const uint64_t pos = i * 64 + (uint64_t)__builtin_ctzll(x);
+        if (sel[s_next] != pos) return bad("select samples");
+        seen = want + 1;
+        x &= x - 1;
+        s_next++;
+      }
     }
+    if (s_next != nsel) return bad("select samples");
   } else if (su != ss || ss != sr) {
     return bad("compact layout");
   }

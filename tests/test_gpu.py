@@ -171,11 +171,14 @@ def test_serialize_roundtrip_and_oracle_reads_gpu_image(torch):
     other = synth.u64_keys(100_000, 99)
     pos = g.query_u64(_dev(torch, other)).cpu().numpy()
     assert pos.min() >= 0 and pos.max() < keys.size
-    bad = img.copy()
-    bad[30] ^= np.uint64(1 << 40)  # corrupt an offset word
-    with pytest.raises(binding.PhobicError) as e:
-        binding.deserialize(bad)
-    assert e.value.code == binding.E_FORMAT
+    # corruptions that would let a query read outside the image are refused on the host
+    sec_unary, sec_sel = int(img[15]), int(img[16])
+    for word, bit in [(0, 3), (sec_unary + 2, 17), (sec_sel, 40), (21, 1)]:
+        bad = img.copy()
+        bad[word] ^= np.uint64(1 << bit)
+        with pytest.raises(binding.PhobicError) as e:
+            binding.deserialize(bad)
+        assert e.value.code == binding.E_FORMAT
 
 
 def test_determinism_and_order_independence(torch):
