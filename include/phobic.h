@@ -122,6 +122,21 @@ phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, void* hip_st
 phobic_status phobic_partition_u64(const uint64_t* d_keys, uint64_t n, const phobic_params* params,
                                    void* hip_stream, uint64_t* d_offsets, uint64_t* d_codes);
 
+/* Launch shape of the pilot search: waves_per_group wavefronts per workgroup, each working on one
+ * partition at a time; with groups_per_cu > 0 the search runs persistently (groups_per_cu
+ * workgroups per compute unit pulling items_per_grab partitions at a time from an atomic queue),
+ * with 0 it launches one wavefront per partition.  The shape never changes a result. */
+typedef struct {
+  uint32_t waves_per_group; /* 1, 2, 4 or 8 */
+  uint32_t groups_per_cu;   /* 0 = one wavefront per partition; else persistent */
+  uint32_t items_per_grab;  /* partitions taken per queue access (persistent mode), >= 1 */
+  uint32_t reserved;
+} phobic_search_config;
+
+/* Sets the search shape used by later builds on the calling process (all devices). */
+phobic_status phobic_set_search_config(const phobic_search_config* cfg);
+phobic_status phobic_get_search_config(phobic_search_config* out);
+
 void phobic_free(phobic_mphf* h);
 const char* phobic_status_str(phobic_status s);
 const char* phobic_last_error(void);

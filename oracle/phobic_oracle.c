@@ -113,10 +113,13 @@ static void hash_str(const uint8_t *s, uint64_t len, uint64_t seed, uint64_t *hi
 }
 
 /* Seeded position hash h(x, s) in [0, m) (Sec. 4, "Hash Function": the paper needs a hash of the
- * key and the seed s that stays well distributed in small partitions; XOR-ing two fixed hashes is
- * what it rules out). */
+ * key and the seed s that stays well distributed in small partitions; XOR-ing two fixed hash values
+ * without further mixing is what it rules out).  The key enters through its 64-bit fingerprint
+ * f = lo ^ mix_b(hi); the seed through the Weyl value (s + 1) * phi; a full mixer follows the XOR. */
+static uint64_t fingerprint(uint64_t hi, uint64_t lo) { return lo ^ mix_b(hi); }
+
 static uint64_t pos_hash(uint64_t hi, uint64_t lo, uint64_t s, uint64_t m) {
-  uint64_t z = mix_a(lo ^ mix_b(hi ^ ((s + 1) * PHI64)));
+  uint64_t z = mix_a(fingerprint(hi, lo) ^ ((s + 1) * PHI64));
   return mul_hi(z, m);
 }
 
@@ -318,12 +321,13 @@ static int build_partition(part_job *job, uint64_t j, int dup_only, uint64_t *st
   for (uint64_t i = 0; i < nj; i++) keyidx[start[kb[i]]++] = (uint32_t)i;
   for (uint32_t b = 0; b < B; b++) start[b] -= cnt[b];
 
-  /* two keys with the same 128-bit code can never be separated: report duplicates */
+  /* two keys of one bucket with the same fingerprint (in particular, equal keys) get the same
+   * position under every seed and can never be separated: report duplicates */
   for (uint32_t b = 0; b < B; b++)
     for (uint32_t x = 0; x < cnt[b]; x++)
       for (uint32_t y = x + 1; y < cnt[b]; y++) {
         uint32_t u = keyidx[start[b] + x], v = keyidx[start[b] + y];
-        if (hi[u] == hi[v] && lo[u] == lo[v]) return REF_E_DUPLICATE;
+        if (fingerprint(hi[u], lo[u]) == fingerprint(hi[v], lo[v])) return REF_E_DUPLICATE;
       }
   if (dup_only) return REF_OK;
 

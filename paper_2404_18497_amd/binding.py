@@ -23,7 +23,7 @@ EXPORTS = [
     "phobic_params_default", "phobic_build_u64", "phobic_build_str", "phobic_query_u64", "phobic_query_str",
     "phobic_size_bits", "phobic_num_keys", "phobic_num_partitions", "phobic_num_buckets", "phobic_get_pilots",
     "phobic_get_build_info", "phobic_serialize", "phobic_deserialize", "phobic_partition_u64", "phobic_free",
-    "phobic_status_str", "phobic_last_error",
+    "phobic_status_str", "phobic_last_error", "phobic_set_search_config", "phobic_get_search_config",
 ]
 
 
@@ -128,9 +128,9 @@ class MPHF:
         self.h = handle
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().phobic_free(self.h)
-            self.h = None
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.phobic_free(self.h)
+        self.h = None
 
     __del__ = close
 

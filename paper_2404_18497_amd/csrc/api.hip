@@ -4,7 +4,10 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "phobic_internal.h"
@@ -73,12 +76,42 @@ uint32_t rice_parameter(uint64_t sum, uint64_t count) {
   return (uint32_t)b;
 }
 
+// Device copies of bucket-function tables, one per (device, lambda, P, alpha); they live until the
+// process ends, so handles only borrow them.
+namespace {
+struct TableKey {
+  int device;
+  uint64_t lambda_bits;
+  uint32_t P, an, ad;
+  bool operator<(const TableKey& o) const {
+    return std::tie(device, lambda_bits, P, an, ad) < std::tie(o.device, o.lambda_bits, o.P, o.an, o.ad);
+  }
+};
+std::mutex g_table_mu;
+std::map<TableKey, uint64_t*> g_tables;
+}  // namespace
+
 phobic_status upload_table(phobic_mphf* h, hipStream_t st) {
+  TableKey key{h->device, 0, h->prm.partition_size, h->prm.alpha_num, h->prm.alpha_den};
+  std::memcpy(&key.lambda_bits, &h->prm.lambda, 8);
+  std::lock_guard<std::mutex> lock(g_table_mu);
+  auto it = g_tables.find(key);
+  if (it != g_tables.end()) {
+    h->d_table = it->second;
+    return PHOBIC_OK;
+  }
   std::vector<uint64_t> T(kTableIntervals + 1);
   bucket_table(h->prm.lambda, h->prm.partition_size, h->prm.alpha_num, h->prm.alpha_den, T.data());
-  PHOBIC_HIP(hipMalloc(&h->d_table, T.size() * sizeof(uint64_t)));
-  PHOBIC_HIP(hipMemcpyAsync(h->d_table, T.data(), T.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st));
-  PHOBIC_HIP(hipStreamSynchronize(st));  // T is a stack vector
+  uint64_t* d = nullptr;
+  PHOBIC_HIP(hipMalloc(&d, T.size() * sizeof(uint64_t)));
+  hipError_t e = hipMemcpyAsync(d, T.data(), T.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // T is a local vector
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return fail(PHOBIC_E_DEVICE, std::string("bucket table upload: ") + hipGetErrorString(e));
+  }
+  g_tables[key] = d;
+  h->d_table = d;
   return PHOBIC_OK;
 }
 
@@ -277,8 +310,9 @@ extern "C" phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, v
     phobic_free(h);
     return r;
   }
-  hipError_t e = hipMalloc(&h->d_image, bytes);
-  if (e == hipSuccess) e = hipMemcpy(h->d_image, w.data(), bytes, hipMemcpyHostToDevice);
+  hipError_t e = hipMallocAsync((void**)&h->d_image, bytes, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(h->d_image, w.data(), bytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
     phobic_free(h);
     return fail(e == hipErrorOutOfMemory ? PHOBIC_E_OOM : PHOBIC_E_DEVICE, hipGetErrorString(e));
@@ -290,8 +324,9 @@ extern "C" phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, v
 
 extern "C" void phobic_free(phobic_mphf* h) {
   if (!h) return;
-  if (h->d_image) (void)hipFree(h->d_image);
-  if (h->d_table) (void)hipFree(h->d_table);
+  // the image comes from the stream-ordered pool; the null stream orders the release after all
+  // work already enqueued on blocking streams
+  if (h->d_image) (void)hipFreeAsync(h->d_image, nullptr);
   if (h->d_pilots) (void)hipFree(h->d_pilots);
   delete h;
 }

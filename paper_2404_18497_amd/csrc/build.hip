@@ -6,7 +6,7 @@
 //   k_scatter_*     : hash again and scatter the 128-bit codes into their partition (order free)
 //   k_bucket_sort   : one workgroup per partition: bucket of every key by the tabulated beta_eps
 //                     (Sec. 3.1, Sec. 3.2, App. C.1), buckets ordered by size desc, index desc
-//                     (Sec. 3, Sec. 5.1), keys rewritten in processing order
+//                     (Sec. 3, Sec. 5.1), key fingerprints rewritten in processing order
 //   k_search        : one wavefront per partition: for each bucket the smallest pilot
 //                     p = s m + d whose positions are distinct and free (Sec. 4, Sec. 4.2); the
 //                     free-slot bitmap lives in LDS, the 64 lanes test 64 displacement windows of
@@ -21,6 +21,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <memory>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "phobic_internal.h"
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(uint32_t* __restrict__ cn
 __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2* __restrict__ codes,
                                                         const uint64_t* __restrict__ off,
                                                         const uint64_t* __restrict__ T, uint32_t B, uint32_t nbpad,
-                                                        ulonglong2* __restrict__ sorted, uint32_t* __restrict__ blist,
+                                                        uint64_t* __restrict__ sortedf, uint32_t* __restrict__ blist,
                                                         uint32_t* __restrict__ nbk, uint32_t* __restrict__ maxb) {
   extern __shared__ __align__(16) uint32_t lds[];
   uint32_t* cnt = lds;
@@ -227,139 +230,488 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2* __rest
   __syncthreads();
   for (uint32_t i = tid; i < nj; i += kBlock) {
     uint32_t r = rec[i];
-    sorted[base + cnt[r >> 16] + (r & 0xFFFF)] = codes[base + i];
+    ulonglong2 c = codes[base + i];
+    sortedf[base + cnt[r >> 16] + (r & 0xFFFF)] = fingerprint(c.x, c.y);
   }
 }
 
 // ---------------------------------------------------------------------------------------------
-// a5: pilot search, one wavefront per partition.
+// a1-a4, main path: coarse bins of G = 2^gshift consecutive partitions.
 //
-// F2 holds the free-slot bitmap twice in a row (bit t and bit t + m both mean "slot t is free"), so
-// the 64 bits of displacements [d, d + 64) for a key at r are bits [r + d, r + d + 64) of F2 with no
-// wrap-around.  For one seed s the lanes cover displacement windows d in [64 l, 64 l + 64); each key
-// of the bucket ANDs its shifted window into the lane's accumulator; once every accumulator is zero
-// no displacement of this seed works.  The lowest lane with a surviving bit holds the smallest d,
-// which with s-major order is the smallest pilot.  Self-collisions under s are found first with a
-// scratch bitmap and atomic OR; a collision at s = 0 also triggers the check for equal codes.
+//   k_coarse_count   : 512 workgroups, each over a contiguous range of keys, histogram the coarse bin
+//                      c = j >> gshift of every key in LDS; the row is saved and added to the bin
+//                      totals with one atomic per bin and workgroup
+//   k_coarse_scan    : bin offsets (one workgroup)
+//   k_coarse_scatter : each workgroup reserves its chunk of every bin with one atomic, then places its
+//                      codes through LDS cursors; every chunk is written by one workgroup
+//   k_segment_sort   : one workgroup per coarse bin: partition of every key, bucket by the tabulated
+//                      bucket function, ranks within (partition, bucket), buckets of every partition
+//                      ordered by size desc and index desc, partition offsets, fingerprints written
+//                      in processing order
+// No per-key global atomics: the only global atomics are one per (workgroup, bin).
 // ---------------------------------------------------------------------------------------------
+constexpr int kCoarseThreads = 1024;
+constexpr uint32_t kCoarseGroups = 512;
+constexpr uint32_t kMaxCoarse = 14336;   // bins held by the LDS histogram (56 KB)
+constexpr int kSegThreads = 512;
+constexpr uint32_t kMaxG = 8;
+constexpr size_t kSegLdsBytes = 61440;   // dynamic LDS of k_segment_sort
+
+template <bool kStr>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_count(const uint64_t* __restrict__ keys,
+                                                                 const uint8_t* __restrict__ bytes,
+                                                                 const uint64_t* __restrict__ offs,
+                                                                 ulonglong2* __restrict__ stage, uint64_t n,
+                                                                 uint64_t per, uint64_t seed, uint64_t K,
+                                                                 uint32_t gshift, uint32_t C,
+                                                                 uint32_t* __restrict__ ccnt, uint32_t* __restrict__ hrow) {
+  extern __shared__ __align__(16) uint32_t hist[];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t x = tid; x < C; x += kCoarseThreads) hist[x] = 0;
+  __syncthreads();
+  const uint64_t a = (uint64_t)blockIdx.x * per, b = min(n, a + per);
+  for (uint64_t i = a + tid; i < b; i += kCoarseThreads) {
+    uint64_t hi;
+    if (kStr) {
+      uint64_t lo;
+      const uint64_t s0 = offs[i], s1 = offs[i + 1];
+      hash_key_str(bytes + s0, s1 - s0, seed, hi, lo);
+      stage[i] = make_ulonglong2(hi, lo);
+    } else {
+      hi = mix_a(keys[i] ^ seed);
+    }
+    atomicAdd(&hist[(uint32_t)__umul64hi(hi, K) >> gshift], 1u);
+  }
+  __syncthreads();
+  for (uint32_t x = tid; x < C; x += kCoarseThreads) {
+    const uint32_t v = hist[x];
+    hrow[(uint64_t)blockIdx.x * C + x] = v;
+    if (v) atomicAdd(&ccnt[x], v);
+  }
+}
+
+// cbase[c] = bins before c (cbase[C] = n); cur[c] = cbase[c] as the scatter cursor
+__global__ __launch_bounds__(1024) void k_coarse_scan(const uint32_t* __restrict__ ccnt, uint32_t C,
+                                                      uint64_t* __restrict__ cbase, uint32_t* __restrict__ cur) {
+  __shared__ uint64_t sp[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t per = (C + 1023) / 1024;
+  const uint32_t a = min(C, t * per), b = min(C, a + per);
+  uint64_t loc = 0;
+  for (uint32_t x = a; x < b; x++) loc += ccnt[x];
+  sp[t] = loc;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    const uint64_t v = t >= d ? sp[t - d] : 0;
+    __syncthreads();
+    sp[t] += v;
+    __syncthreads();
+  }
+  uint64_t run = sp[t] - loc;
+  for (uint32_t x = a; x < b; x++) {
+    cbase[x] = run;
+    cur[x] = (uint32_t)run;
+    run += ccnt[x];
+  }
+  if (t == 1023) cbase[C] = sp[1023];
+}
+
+template <bool kStr>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_scatter(const uint64_t* __restrict__ keys,
+                                                                   const ulonglong2* __restrict__ stage, uint64_t n,
+                                                                   uint64_t per, uint64_t seed, uint64_t K,
+                                                                   uint32_t gshift, uint32_t C,
+                                                                   const uint32_t* __restrict__ hrow,
+                                                                   uint32_t* __restrict__ cur,
+                                                                   ulonglong2* __restrict__ codes) {
+  extern __shared__ __align__(16) uint32_t pos[];
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t x = tid; x < C; x += kCoarseThreads) {
+    const uint32_t v = hrow[(uint64_t)blockIdx.x * C + x];
+    pos[x] = v ? atomicAdd(&cur[x], v) : 0u;
+  }
+  __syncthreads();
+  const uint64_t a = (uint64_t)blockIdx.x * per, b = min(n, a + per);
+  for (uint64_t i = a + tid; i < b; i += kCoarseThreads) {
+    ulonglong2 code;
+    if (kStr) {
+      code = stage[i];
+    } else {
+      uint64_t hi, lo;
+      hash_key_u64(keys[i], seed, hi, lo);
+      code = make_ulonglong2(hi, lo);
+    }
+    const uint32_t c = (uint32_t)__umul64hi(code.x, K) >> gshift;
+    codes[atomicAdd(&pos[c], 1u)] = code;
+  }
+}
+
+// One workgroup per coarse bin of up to kMaxG partitions.  info[0] |= error bits, info[1] = max
+// bucket size, info[2] = max partition size.
+__global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* __restrict__ codes,
+                                                              const uint64_t* __restrict__ cbase,
+                                                              const uint64_t* __restrict__ T, uint32_t B,
+                                                              uint32_t nbpad, uint32_t gshift, uint64_t K,
+                                                              uint32_t seg_cap, uint64_t* __restrict__ sortedf,
+                                                              uint32_t* __restrict__ blist, uint32_t* __restrict__ nbk,
+                                                              uint64_t* __restrict__ off, uint32_t* __restrict__ info,
+                                                              ulonglong2* __restrict__ dbg) {
+  constexpr int kItems = (int)((kSegLdsBytes / 4 + kSegThreads - 1) / kSegThreads);
+  extern __shared__ __align__(16) uint32_t lds[];
+  const uint32_t G = 1u << gshift;
+  const uint32_t span = G * nbpad;
+  uint32_t* cnt = lds;          // [G][nbpad]: counts, then start offsets inside the bin
+  uint32_t* key = lds + span;   // [G][nbpad]: sort keys (size << 16 | bucket)
+  uint32_t* rec = lds + 2 * span;  // per key: partition << 29 | bucket << 16 | rank
+  __shared__ uint32_t part[kSegThreads];
+  __shared__ uint32_t psize[kMaxG], nonempty[kMaxG];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t c = blockIdx.x;
+  const uint64_t j0 = c << gshift;
+  const uint32_t ghere = (uint32_t)min<uint64_t>(G, K - j0);
+  const uint64_t base = cbase[c];
+  const uint32_t ns = (uint32_t)(cbase[c + 1] - base);
+  if (ns > seg_cap) {
+    if (tid == 0) atomicOr(&info[0], 1u << PHOBIC_E_CAPACITY);
+    return;
+  }
+  for (uint32_t x = tid; x < span; x += kSegThreads) cnt[x] = 0;
+  if (tid < kMaxG) { psize[tid] = 0; nonempty[tid] = 0; }
+  __syncthreads();
+  uint64_t fp[kItems];
+#pragma unroll
+  for (int t = 0; t < kItems; t++) {
+    const uint32_t i = tid + t * kSegThreads;
+    if (i < ns) {
+      const ulonglong2 cd = codes[base + i];
+      const uint32_t p = (uint32_t)(__umul64hi(cd.x, K) - j0);
+      const uint32_t b = bucket_of(cd.y, T, B);
+      const uint32_t r = atomicAdd(&cnt[p * nbpad + b], 1u);
+      rec[i] = (p << 29) | (b << 16) | r;
+      fp[t] = fingerprint(cd.x, cd.y);
+    }
+  }
+  __syncthreads();
+  for (uint32_t x = tid; x < span; x += kSegThreads) {
+    const uint32_t p = x / nbpad, xb = x % nbpad;
+    const uint32_t v = xb < B ? cnt[x] : 0;
+    key[x] = v ? ((v << 16) | xb) : 0u;
+    if (v) {
+      atomicAdd(&psize[p], v);
+      atomicAdd(&nonempty[p], 1u);
+    }
+  }
+  __syncthreads();
+  // bitonic sort of every partition's nbpad keys into descending order (size, then bucket index)
+  for (uint32_t k = 2; k <= nbpad; k <<= 1) {
+    for (uint32_t sd = k >> 1; sd > 0; sd >>= 1) {
+      for (uint32_t x = tid; x < span; x += kSegThreads) {
+        const uint32_t y = x ^ sd;
+        if (y > x) {
+          const uint32_t a = key[x], b = key[y];
+          // direction from the index inside the partition's block, so every block ends descending
+          if (((x & (nbpad - 1)) & k) == 0 ? (a < b) : (a > b)) {
+            key[x] = b;
+            key[y] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // exclusive prefix of the sizes over [G][nbpad] in order = start of every bucket inside the bin
+  const uint32_t ipt = (span + kSegThreads - 1) / kSegThreads;
+  const uint32_t x0 = min(span, tid * ipt), x1 = min(span, x0 + ipt);
+  uint32_t local = 0;
+  for (uint32_t x = x0; x < x1; x++) local += key[x] >> 16;
+  part[tid] = local;
+  __syncthreads();
+  for (uint32_t d = 1; d < kSegThreads; d <<= 1) {
+    const uint32_t v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[tid] - local;
+  for (uint32_t x = x0; x < x1; x++) {
+    const uint32_t kx = key[x];
+    const uint32_t p = x / nbpad, xb = x % nbpad;
+    if (xb < nonempty[p]) {
+      cnt[p * nbpad + (kx & 0xFFFF)] = run;
+      blist[(j0 + p) * B + xb] = kx;
+    }
+    run += kx >> 16;
+  }
+  if (tid < ghere) {
+    uint32_t st = 0;
+    for (uint32_t q = 0; q < tid; q++) st += psize[q];
+    off[j0 + tid] = base + st;
+    nbk[j0 + tid] = nonempty[tid];
+    atomicMax(&info[1], key[tid * nbpad] >> 16);
+    atomicMax(&info[2], psize[tid]);
+  }
+  if (tid == 0 && j0 + ghere == K) off[K] = base + ns;
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < kItems; t++) {
+    const uint32_t i = tid + t * kSegThreads;
+    if (i < ns) {
+      const uint32_t r = rec[i];
+      const uint64_t dest = base + cnt[(r >> 29) * nbpad + ((r >> 16) & 0x1FFF)] + (r & 0xFFFF);
+      sortedf[dest] = fp[t];
+      if (dbg) dbg[dest] = codes[base + i];
+    }
+  }
+}
+
+// Table offsets for alpha < 1 from the key offsets: toff[j] = sum of ceil(n_j' den / num), j' < j;
+// info[3] = max table size, tot[0] = total.
+__global__ __launch_bounds__(1024) void k_table_offsets(const uint64_t* __restrict__ off, uint64_t K, uint32_t an,
+                                                        uint32_t ad, uint64_t* __restrict__ toff,
+                                                        uint32_t* __restrict__ info, uint64_t* __restrict__ tot) {
+  __shared__ uint64_t sp[1024];
+  __shared__ uint32_t mx;
+  const uint32_t t = threadIdx.x;
+  if (t == 0) mx = 0;
+  const uint64_t per = (K + 1023) / 1024;
+  const uint64_t a = min(K, (uint64_t)t * per), b = min(K, a + per);
+  uint64_t loc = 0;
+  uint32_t lmx = 0;
+  for (uint64_t j = a; j < b; j++) {
+    const uint64_t m = table_slots(off[j + 1] - off[j], an, ad);
+    loc += m;
+    lmx = max(lmx, (uint32_t)min<uint64_t>(m, 0xFFFFFFFFULL));
+  }
+  sp[t] = loc;
+  __syncthreads();
+  atomicMax(&mx, lmx);
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    const uint64_t v = t >= d ? sp[t - d] : 0;
+    __syncthreads();
+    sp[t] += v;
+    __syncthreads();
+  }
+  uint64_t run = sp[t] - loc;
+  for (uint64_t j = a; j < b; j++) {
+    toff[j] = run;
+    run += table_slots(off[j + 1] - off[j], an, ad);
+  }
+  if (t == 1023) {
+    toff[K] = sp[1023];
+    tot[0] = sp[1023];
+    info[3] = mx;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// a5: pilot search, one wavefront per partition, four partitions per workgroup.
+//
+// F2 holds the free-slot bitmap twice in a row (bit t and bit t + m both mean "slot t is free", in
+// 32-bit words), so the displacements [d, d + 64) of a key at position r are bits [r + d, r + d + 64)
+// of F2 with no wrap-around.  For one seed the lanes cover displacement windows [64 l, 64 l + 64);
+// each key of the bucket ANDs its shifted window into the lane's accumulator; when every
+// accumulator is zero no displacement of this seed works.  The lowest lane with a surviving bit
+// holds the smallest d, and seeds are tried in increasing order, so the first hit is the smallest
+// pilot p = s m + d (Sec. 4; the same minimum as the sequential nested loop, Sec. 4.2).
+//
+// The key loop is pure vector/LDS work: positions are kept encoded as e = (r >> 5) << 7 | (r & 31),
+// so (e >> 5) is the byte offset of the word holding bit r and the low five bits are the funnel
+// shift; the list is padded to a multiple of four with copies of its last entry (AND is
+// idempotent), and lanes whose window lies beyond m read in-bounds words into an accumulator that
+// is already zero.
+//
+// Two keys of a bucket at the same position under s rule out every d.  Buckets of more than
+// kSmallBucket keys test this first (scratch bitmap, atomic OR); smaller ones find it while marking
+// their slots (a slot already cleared by the same bucket) and undo the marks.  A repeat at s = 0
+// between equal fingerprints means the bucket can never be placed: PHOBIC_E_DUPLICATE.
+// ---------------------------------------------------------------------------------------------
+constexpr uint32_t kSmallBucket = 24;
+
 struct SearchArgs {
-  const ulonglong2* sorted;
-  const uint64_t* off;
-  const uint64_t* toff;
-  const uint32_t* blist;
-  const uint32_t* nbk;
-  uint32_t* pilots;  // encoder-major: pilots[i * K + j]
-  uint32_t* err;     // bit (1 << status) for every error met
-  uint64_t* taken;   // global occupancy bitmap of all tables (alpha < 1), else null
+  const uint64_t* fp;     // fingerprints in processing order, partition-contiguous
+  const uint64_t* off;    // key offsets, K + 1
+  const uint64_t* toff;   // table offsets, K + 1
+  const uint32_t* blist;  // per partition: (size << 16 | bucket) in processing order
+  const uint32_t* nbk;    // non-empty buckets per partition
+  uint32_t* pilots;       // encoder-major: pilots[i * K + j]
+  uint32_t* err;          // bit (1 << status) for every error met
+  uint64_t* taken;        // occupancy bitmap of all tables (alpha < 1), else null
   uint64_t K;
   uint64_t limit;
   uint32_t B;
-  uint32_t f2_words, scr_words, rb_cap;
+  uint32_t f2_words;      // 32-bit words of F2 (multiple of 4)
+  uint32_t scr_words;     // 32-bit words of the collision scratch (multiple of 4)
+  uint32_t rb_cap;        // 32-bit position entries (multiple of 4)
+  uint32_t bl_cap;        // 32-bit bucket-list entries (multiple of 4)
+  uint32_t cm_cap;        // 64-bit collision masks
+  uint32_t wave_lds;      // bytes of LDS per wavefront (multiple of 16)
+  // several MPHFs at once: partition J belongs to MPHF owner[J], whose partitions start at
+  // Kbase[t] (K_t of them) and whose pilots start at B * Kbase[t]; null for a single MPHF
+  const uint32_t* owner;
+  const uint64_t* Kbase;
+  const uint64_t* Kt;
+  // persistent launch: partitions are taken grab at a time from *queue; null = one per wavefront
+  unsigned long long* queue;
+  uint32_t grab;
+  uint32_t fail_part_set;  // nonzero: err[2..3] receive the lowest failing partition index
 };
 
-__device__ __forceinline__ uint64_t window64(const uint32_t* __restrict__ F2, uint32_t q) {
-  uint32_t i = q >> 5, sh = q & 31;
-  uint32_t w0 = F2[i], w1 = F2[i + 1], w2 = F2[i + 2];
-  uint32_t lo = __builtin_amdgcn_alignbit(w1, w0, sh);
-  uint32_t hi = __builtin_amdgcn_alignbit(w2, w1, sh);
-  return ((uint64_t)hi << 32) | lo;
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
-__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  uint32_t* F2 = lds;
-  uint32_t* scr = lds + a.f2_words;
-  uint16_t* rbuf = (uint16_t*)(scr + a.scr_words);
-  uint64_t* cm = (uint64_t*)(rbuf + a.rb_cap);
-  const uint32_t lane = threadIdx.x;
-  const uint64_t j = blockIdx.x;
+__device__ __forceinline__ uint32_t enc_pos(uint32_t r) { return ((r >> 5) << 7) | (r & 31); }
+__device__ __forceinline__ uint32_t dec_pos(uint32_t e) { return ((e >> 7) << 5) | (e & 31); }
+
+// Marks the positions of rbuf[0..sz) in the scratch bitmap; cm[g] gets the lanes of group g whose
+// position was already marked.  Leaves the scratch clear.  Returns whether a position repeats.
+__device__ bool positions_repeat(uint32_t* scr, const uint32_t* rbuf, uint32_t sz, uint64_t* cm, uint32_t lane) {
+  bool any = false;
+  const uint32_t ng = (sz + 63) >> 6;
+  for (uint32_t g = 0; g < ng; g++) {
+    const uint32_t k = g * 64 + lane;
+    bool c = false;
+    if (k < sz) {
+      const uint32_t rr = dec_pos(rbuf[k]), bit = 1u << (rr & 31);
+      c = (atomicOr(&scr[rr >> 5], bit) & bit) != 0;
+    }
+    const uint64_t bm = __ballot(c);
+    if (lane == 0) cm[g] = bm;
+    any |= bm != 0;
+  }
+  wave_sync();
+  for (uint32_t k = lane; k < sz; k += 64) {
+    const uint32_t rr = dec_pos(rbuf[k]);
+    atomicAnd(&scr[rr >> 5], ~(1u << (rr & 31)));
+  }
+  wave_sync();
+  return any;
+}
+
+// After positions_repeat: whether a repeated position comes from two equal fingerprints.
+__device__ bool equal_fingerprints(const uint64_t* keys, const uint32_t* rbuf, uint32_t sz, const uint64_t* cm,
+                                   uint32_t lane) {
+  const uint32_t ng = (sz + 63) >> 6;
+  for (uint32_t g = 0; g < ng; g++) {
+    uint64_t bm = cm[g];
+    while (bm) {
+      const uint32_t c = g * 64 + (uint32_t)(__ffsll((long long)bm) - 1);
+      bm &= bm - 1;
+      const uint32_t rc = rbuf[c];
+      const uint64_t fc = keys[c];
+      bool f = false;
+      for (uint32_t k = lane; k < sz; k += 64)
+        if (k != c && rbuf[k] == rc) f |= keys[k] == fc;
+      if (__ballot(f)) return true;
+    }
+  }
+  return false;
+}
+
+// Positions of a bucket's keys under the seed value w, encoded into rbuf, padded to a multiple of
+// four with the last entry.  Returns lane k's position for k < 64 (the keys a small bucket marks).
+__device__ __forceinline__ uint32_t bucket_positions(uint32_t* rbuf, const uint64_t* keys, uint64_t f0, uint32_t sz,
+                                                     uint64_t w, uint32_t m, uint32_t lane) {
+  const uint32_t ng = (sz + 63) >> 6, szp = (sz + 3) & ~3u;
+  uint32_t r0 = 0;
+  for (uint32_t g = 0; g < ng; g++) {
+    const uint32_t k = g * 64 + lane;
+    uint32_t r = 0;
+    if (k < sz) {
+      r = pos_hash(g == 0 ? f0 : keys[k], w, m);
+      rbuf[k] = enc_pos(r);
+    }
+    if (g == 0) r0 = r;
+    if (g == ng - 1) {
+      const uint32_t last = __shfl(r, (int)((sz - 1) & 63));
+      if (k >= sz && k < szp) rbuf[k] = enc_pos(last);
+    }
+  }
+  wave_sync();
+  return r0;
+}
+
+__device__ __forceinline__ void note_failure(const SearchArgs& a, uint64_t j, uint32_t status) {
+  atomicOr(a.err, 1u << status);
+  if (a.fail_part_set) atomicMin((unsigned long long*)(a.err + 2), (unsigned long long)j);
+}
+
+// Places every bucket of partition j (global index).  Uniform across the wavefront.
+__device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, uint32_t lane) {
+  uint32_t* scr = F2 + a.f2_words;
+  uint32_t* rbuf = scr + a.scr_words;
+  uint32_t* bl = rbuf + a.rb_cap;
+  uint64_t* cm = (uint64_t*)(bl + a.bl_cap);
+
   const uint64_t kb = a.off[j];
   const uint32_t m = (uint32_t)(a.toff[j + 1] - a.toff[j]);
   const uint32_t twom = 2 * m;
-
   for (uint32_t w = lane; w < a.f2_words; w += 64) {
-    uint32_t lo = w * 32;
+    const uint32_t lo = w * 32;
     F2[w] = lo + 32 <= twom ? 0xFFFFFFFFu : (lo >= twom ? 0u : ((1u << (twom - lo)) - 1u));
   }
   for (uint32_t w = lane; w < a.scr_words; w += 64) scr[w] = 0;
-  __syncthreads();
-
   const uint32_t nb = a.nbk[j];
+  for (uint32_t x = lane; x < nb; x += 64) bl[x] = a.blist[j * a.B + x];
+  wave_sync();
+  const char* F2b = (const char*)F2;
+
   uint64_t kpos = kb;
+  uint32_t e = nb ? bl[0] : 0;
+  uint64_t fnext = lane < (e >> 16) ? a.fp[kpos + lane] : 0;
   bool overflow = false;
   for (uint32_t r = 0; r < nb; r++) {
-    const uint32_t e = a.blist[j * a.B + r];
     const uint32_t bid = e & 0xFFFF, sz = e >> 16;
-    const ulonglong2* keys = a.sorted + kpos;
+    const uint64_t* keys = a.fp + kpos;
+    const uint64_t f0 = fnext;
     kpos += sz;
-    const uint32_t ng = (sz + 63) / 64;
-    const ulonglong2 k0 = lane < sz ? keys[lane] : make_ulonglong2(0, 0);
+    if (r + 1 < nb) {  // prefetch the next bucket's first 64 fingerprints
+      e = bl[r + 1];
+      fnext = lane < (e >> 16) ? a.fp[kpos + lane] : 0;
+    }
+    const bool big = sz > kSmallBucket;
+    const uint32_t szp = (sz + 3) & ~3u;
+
+    if (overflow) {  // the partition has failed: only look for equal fingerprints
+      bucket_positions(rbuf, keys, f0, sz, kPhi64, m, lane);
+      if (positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
+        if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
+        return;
+      }
+      continue;
+    }
+
     for (uint64_t s = 0;; s++) {
-      // positions under seed s, and self-collisions
-      bool coll_any = false;
-      for (uint32_t g = 0; g < ng; g++) {
-        const uint32_t k = g * 64 + lane;
-        bool c = false;
-        if (k < sz) {
-          ulonglong2 key = g == 0 ? k0 : keys[k];
-          uint32_t rr = pos_hash(key.x, key.y, s, m);
-          rbuf[k] = (uint16_t)rr;
-          uint32_t bit = 1u << (rr & 31);
-          c = (atomicOr(&scr[rr >> 5], bit) & bit) != 0;
-        }
-        uint64_t bm = __ballot(c);
-        if (lane == 0) cm[g] = bm;
-        coll_any |= bm != 0;
-      }
-      __syncthreads();
-      if (coll_any && s == 0) {
-        // keys whose position repeats: an equal 128-bit code makes the bucket unplaceable
-        bool dup = false;
-        for (uint32_t g = 0; g < ng && !dup; g++) {
-          uint64_t bm = cm[g];
-          while (bm && !dup) {
-            const uint32_t c = g * 64 + (uint32_t)(__ffsll((long long)bm) - 1);
-            bm &= bm - 1;
-            const uint32_t rc = rbuf[c];
-            const ulonglong2 kc = keys[c];
-            bool f = false;
-            for (uint32_t k = lane; k < sz; k += 64) {
-              if (k != c && rbuf[k] == rc) {
-                ulonglong2 kk = keys[k];
-                f |= kk.x == kc.x && kk.y == kc.y;
-              }
-            }
-            dup = __ballot(f) != 0;
-          }
-        }
-        if (dup) {
-          if (lane == 0) atomicOr(a.err, 1u << PHOBIC_E_DUPLICATE);
-          return;
-        }
-      }
-      for (uint32_t k = lane; k < sz; k += 64) {
-        uint32_t rr = rbuf[k];
-        atomicAnd(&scr[rr >> 5], ~(1u << (rr & 31)));
-      }
-      __syncthreads();
-      if (overflow) break;  // after an overflow only the duplicate check runs
-      if (coll_any) continue;
       if (s * m > a.limit) {
         overflow = true;
         break;
       }
+      const uint32_t rmine = bucket_positions(rbuf, keys, f0, sz, (s + 1) * kPhi64, m, lane);
+      if (big && positions_repeat(scr, rbuf, sz, cm, lane)) {
+        if (s == 0 && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
+          if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
+          return;
+        }
+        continue;
+      }
 
-      // displacement scan: lowest d such that every key's slot (r + d) mod m is free
+      // displacement scan: the lowest d such that every key's slot (r + d) mod m is free
       uint32_t d_found = 0xFFFFFFFFu;
       for (uint32_t d0 = 0; d0 < m; d0 += 4096) {
         const uint32_t dl = d0 + lane * 64;
-        uint64_t acc = 0;
-        if (dl < m) acc = (m - dl >= 64) ? ~0ULL : ((1ULL << (m - dl)) - 1);
-        for (uint32_t k = 0; k < sz; k += 4) {
-          const uint64_t r4 = *(const uint64_t*)(rbuf + k);
+        const bool act = dl < m;
+        uint64_t acc = act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL;
+        const uint32_t loff = act ? (dl >> 3) : 0u;  // byte offset of this lane's window start
+        for (uint32_t k = 0; k < szp; k += 4) {
+          const uint4 e4 = *(const uint4*)(rbuf + k);
+          const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
 #pragma unroll
-          for (uint32_t t = 0; t < 4; t++) {
-            if (k + t < sz && dl < m) acc &= window64(F2, (uint32_t)((r4 >> (16 * t)) & 0xFFFF) + dl);
+          for (int t = 0; t < 4; t++) {
+            const uint32_t* wp = (const uint32_t*)(F2b + (ev[t] >> 5) + loff);
+            const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
+            acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, ev[t]) << 32) |
+                   __builtin_amdgcn_alignbit(w1, w0, ev[t]);
           }
           if (__ballot(acc != 0) == 0) break;
         }
@@ -377,28 +729,87 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         overflow = true;
         break;
       }
-      for (uint32_t k = lane; k < sz; k += 64) {
-        uint32_t t = rbuf[k] + d_found;
+      // mark the slots; a small bucket discovers here whether two of its keys share a slot
+      if (!big) {
+        bool mine = false;
+        uint32_t t = rmine + d_found;
         if (t >= m) t -= m;
-        atomicAnd(&F2[t >> 5], ~(1u << (t & 31)));
-        uint32_t t2 = t + m;
-        atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
+        if (lane < sz) mine = (atomicAnd(&F2[t >> 5], ~(1u << (t & 31))) >> (t & 31)) & 1u;
+        wave_sync();
+        if (__ballot(lane < sz && !mine)) {
+          if (mine) atomicOr(&F2[t >> 5], 1u << (t & 31));  // undo
+          wave_sync();
+          if (s == 0 && positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
+            if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
+            return;
+          }
+          continue;
+        }
+        if (lane < sz) {
+          const uint32_t t2 = t + m;
+          atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
+        }
+      } else {
+        for (uint32_t k = lane; k < sz; k += 64) {
+          uint32_t t = dec_pos(rbuf[k]) + d_found;
+          if (t >= m) t -= m;
+          atomicAnd(&F2[t >> 5], ~(1u << (t & 31)));
+          const uint32_t t2 = t + m;
+          atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
+        }
       }
-      if (lane == 0) a.pilots[(uint64_t)bid * a.K + j] = (uint32_t)p;
-      __syncthreads();
+      if (lane == 0) {
+        if (a.owner) {
+          const uint32_t t = a.owner[j];
+          const uint64_t jb = a.Kbase[t];
+          a.pilots[(uint64_t)a.B * jb + (uint64_t)bid * a.Kt[t] + (j - jb)] = (uint32_t)p;
+        } else {
+          a.pilots[(uint64_t)bid * a.K + j] = (uint32_t)p;
+        }
+      }
+      wave_sync();
       break;
     }
   }
   if (overflow) {
-    if (lane == 0) atomicOr(a.err, 1u << PHOBIC_E_PILOT_OVERFLOW);
+    if (lane == 0) note_failure(a, j, PHOBIC_E_PILOT_OVERFLOW);
     return;
   }
   if (a.taken) {
     const uint64_t tb = a.toff[j];
     for (uint32_t w = lane; w * 32 < m; w += 64) {
-      uint32_t nbits = min(32u, m - w * 32);
-      uint32_t busy = ~F2[w] & (nbits == 32 ? 0xFFFFFFFFu : ((1u << nbits) - 1));
+      const uint32_t nbits = min(32u, m - w * 32);
+      const uint32_t busy = ~F2[w] & (nbits == 32 ? 0xFFFFFFFFu : ((1u << nbits) - 1));
       put_bits_atomic(a.taken, tb + (uint64_t)w * 32, busy, nbits);
+    }
+  }
+}
+
+// One wavefront per partition.
+template <int kWaves>
+__global__ __launch_bounds__(64 * kWaves) void k_search(SearchArgs a) {
+  extern __shared__ __align__(16) uint32_t lds32[];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t j = (uint64_t)blockIdx.x * kWaves + wave;
+  if (j >= a.K) return;
+  search_partition(a, j, lds32 + (size_t)wave * (a.wave_lds / 4), lane);
+}
+
+// Persistent: every wavefront takes `grab` partitions at a time from the queue until none is left.
+template <int kWaves>
+__global__ __launch_bounds__(64 * kWaves) void k_search_persistent(SearchArgs a) {
+  extern __shared__ __align__(16) uint32_t lds32[];
+  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  uint32_t* F2 = lds32 + (size_t)wave * (a.wave_lds / 4);
+  for (;;) {
+    unsigned long long item = 0;
+    if (lane == 0) item = atomicAdd(a.queue, (unsigned long long)a.grab);
+    item = __shfl(item, 0);
+    if (item >= a.K) break;
+    const uint64_t end = min((uint64_t)item + a.grab, a.K);
+    for (uint64_t j = item; j < end; j++) {
+      search_partition(a, j, F2, lane);
+      wave_sync();
     }
   }
 }
@@ -620,6 +1031,50 @@ __global__ __launch_bounds__(kBlock) void k_remap_fill(const uint64_t* __restric
 }
 
 // ---------------------------------------------------------------------------------------------
+// Search launch shape
+// ---------------------------------------------------------------------------------------------
+std::mutex g_cfg_mu;
+phobic_search_config g_cfg = {4, 0, 1, 0};
+
+phobic_search_config search_config() {
+  std::lock_guard<std::mutex> lock(g_cfg_mu);
+  return g_cfg;
+}
+
+template <int W>
+hipError_t launch_search_w(SearchArgs& sa, uint64_t items, const phobic_search_config& cfg, hipStream_t st,
+                           unsigned long long* queue) {
+  const size_t lds = (size_t)sa.wave_lds * W;
+  if (cfg.groups_per_cu == 0) {
+    sa.queue = nullptr;
+    hipLaunchKernelGGL(k_search<W>, dim3((uint32_t)((items + W - 1) / W)), dim3(64 * W), lds, st, sa);
+    return hipGetLastError();
+  }
+  int dev = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  sa.queue = queue;
+  sa.grab = std::max<uint32_t>(1, cfg.items_per_grab);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (uint64_t*)queue, (uint64_t)1, (uint64_t)0);
+  const uint64_t groups = std::min<uint64_t>((uint64_t)cus * cfg.groups_per_cu, (items + W - 1) / W);
+  hipLaunchKernelGGL(k_search_persistent<W>, dim3((uint32_t)std::max<uint64_t>(groups, 1)), dim3(64 * W), lds, st,
+                     sa);
+  return hipGetLastError();
+}
+
+// Launches the search over `items` partitions (sa.K) with the configured shape.
+hipError_t launch_search(SearchArgs& sa, uint64_t items, hipStream_t st, unsigned long long* queue) {
+  const phobic_search_config cfg = search_config();
+  switch (cfg.waves_per_group) {
+    case 1: return launch_search_w<1>(sa, items, cfg, st, queue);
+    case 2: return launch_search_w<2>(sa, items, cfg, st, queue);
+    case 8: return launch_search_w<8>(sa, items, cfg, st, queue);
+    default: return launch_search_w<4>(sa, items, cfg, st, queue);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
 // Host orchestration
 // ---------------------------------------------------------------------------------------------
 uint32_t grid_for(uint64_t n, uint32_t block = kBlock, uint32_t cap = 256 * 32) {
@@ -738,62 +1193,15 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     if (ts != PHOBIC_OK) return ts;
   }
 
-  uint32_t* cnt;
-  uint64_t *off, *toff, *dinfo;
-  ulonglong2 *codes, *stage = nullptr;
-  PHOBIC_HIP(S.get(&cnt, K + 1));
+  // ---- a1-a4: hash, partition, bucket, order -------------------------------------------------
+  uint64_t *off, *toff = nullptr, *sortedf, *d64;
+  uint32_t *blist, *nbk, *pilots, *err;  // err[0] error bits, [1] max bucket, [2] max n_j, [3] max m_j
   PHOBIC_HIP(S.get(&off, K + 1));
-  PHOBIC_HIP(S.get(&toff, K + 1));
-  PHOBIC_HIP(S.get(&dinfo, 8));
-  PHOBIC_HIP(S.get(&codes, n));
-  if (in.src == Src::Str) PHOBIC_HIP(S.get(&stage, n));
-  std::vector<uint64_t> info(8, 0);
-
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, cnt, K + 1, 0u);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, dinfo, (uint64_t)8, (uint64_t)0);
-  tm.mark();  // 0
-  if (in.src == Src::U64)
-    hipLaunchKernelGGL(k_hash_count_u64, dim3(grid_for(n)), dim3(kBlock), 0, st, in.keys, n, prm.hash_seed, K, cnt);
-  else
-    hipLaunchKernelGGL(k_hash_count_str, dim3(grid_for(n)), dim3(kBlock), 0, st, in.bytes, in.offs, n, prm.hash_seed, K,
-                       stage, cnt);
-  tm.mark();  // 1
-  hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, cnt, K, an, ad, off, toff, dinfo);
-  tm.mark();  // 2
-  PHOBIC_HIP(hipGetLastError());
-  PHOBIC_HIP(hipMemcpyAsync(info.data(), dinfo, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipStreamSynchronize(st));
-  const uint64_t max_nj = info[0], max_m = info[1], total = info[2];
-  h->info.max_partition_keys = max_nj;
-  if (max_nj > kMaxPartitionKeys || max_m > kMaxTableSlots)
-    return fail(PHOBIC_E_CAPACITY, "a partition holds " + std::to_string(max_nj) + " keys (" + std::to_string(max_m) +
-                                       " slots); the device path holds at most " +
-                                       std::to_string(kMaxPartitionKeys) + " keys and " +
-                                       std::to_string(kMaxTableSlots) + " slots per partition");
-
-  if (in.src == Src::U64)
-    hipLaunchKernelGGL(k_scatter_u64, dim3(grid_for(n)), dim3(kBlock), 0, st, in.keys, n, prm.hash_seed, K, off, cnt,
-                       codes);
-  else
-    hipLaunchKernelGGL(k_scatter_codes, dim3(grid_for(n)), dim3(kBlock), 0, st, stage, n, K, off, cnt, codes);
-  tm.mark();  // 3
-  PHOBIC_HIP(hipGetLastError());
-
-  if (part_offsets_out) {  // stages a1-a2 only
-    PHOBIC_HIP(hipMemcpyAsync(part_offsets_out, off, (K + 1) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
-    PHOBIC_HIP(hipMemcpyAsync(part_codes_out, codes, n * sizeof(ulonglong2), hipMemcpyDeviceToDevice, st));
-    PHOBIC_HIP(hipStreamSynchronize(st));
-    return PHOBIC_OK;
-  }
-
-  // a3 + a4
-  ulonglong2* sorted;
-  uint32_t *blist, *nbk, *pilots, *err, *maxb;
-  PHOBIC_HIP(S.get(&sorted, n));
+  PHOBIC_HIP(S.get(&sortedf, n));
   PHOBIC_HIP(S.get(&blist, K * B));
   PHOBIC_HIP(S.get(&nbk, K));
   PHOBIC_HIP(S.get(&err, 4));
-  maxb = err + 1;
+  PHOBIC_HIP(S.get(&d64, 8));
   if (keep) {
     PHOBIC_HIP(hipMalloc(&h->d_pilots, std::max<uint64_t>(1, K * B) * sizeof(uint32_t)));
     pilots = h->d_pilots;
@@ -802,17 +1210,132 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   }
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(K * B)), dim3(kBlock), 0, st, pilots, K * B, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err, (uint64_t)4, 0u);
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, d64, (uint64_t)8, (uint64_t)0);
   const uint32_t nbpad = next_pow2(B);
-  const size_t sort_lds = (2 * (size_t)nbpad + std::max<uint64_t>(max_nj, 1)) * sizeof(uint32_t);
-  tm.mark();  // 4
-  hipLaunchKernelGGL(k_bucket_sort, dim3((uint32_t)K), dim3(kBlock), sort_lds, st, codes, off, h->d_table, B, nbpad,
-                     sorted, blist, nbk, maxb);
-  tm.mark();  // 5
-  PHOBIC_HIP(hipGetLastError());
-  uint32_t hmaxb = 0;
-  PHOBIC_HIP(hipMemcpyAsync(&hmaxb, maxb, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  const bool str = in.src == Src::Str;
+
+  // coarse bins: the largest G = 2^gshift <= kMaxG whose bins (G P keys plus eight standard
+  // deviations) fit the LDS of k_segment_sort
+  int gshift = -1;
+  uint32_t seg_cap = 0;
+  for (int gs = 3; gs >= 0; gs--) {
+    const double gp = (double)(1u << gs) * prm.partition_size;
+    const int64_t cap = ((int64_t)kSegLdsBytes - 8 * (int64_t)(1u << gs) * nbpad) / 4;
+    if (cap > 0 && gp + 8.0 * std::sqrt(gp) + 64.0 <= (double)cap) {
+      gshift = gs;
+      seg_cap = (uint32_t)cap;
+      break;
+    }
+  }
+  const uint64_t C = gshift >= 0 ? (K + (1ULL << gshift) - 1) >> gshift : 0;
+  const bool coarse_path = gshift >= 0 && C <= kMaxCoarse && n < (1ULL << 32);
+  uint64_t old_info[3] = {0, 0, 0};
+
+  if (coarse_path) {
+    uint32_t *ccnt, *hrow, *cur;
+    uint64_t* cbase;
+    ulonglong2 *codes, *stage = nullptr;
+    const uint32_t ngrp = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kCoarseGroups, (n + 4095) / 4096));
+    const uint64_t per = (n + ngrp - 1) / ngrp;
+    PHOBIC_HIP(S.get(&ccnt, C));
+    PHOBIC_HIP(S.get(&hrow, (uint64_t)ngrp * C));
+    PHOBIC_HIP(S.get(&cur, C));
+    PHOBIC_HIP(S.get(&cbase, C + 1));
+    PHOBIC_HIP(S.get(&codes, n));
+    if (str) PHOBIC_HIP(S.get(&stage, n));
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(C)), dim3(kBlock), 0, st, ccnt, C, 0u);
+    const size_t hist_lds = C * sizeof(uint32_t);
+    tm.mark();  // 0
+    if (str)
+      hipLaunchKernelGGL(k_coarse_count<true>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, in.bytes,
+                         in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, ccnt, hrow);
+    else
+      hipLaunchKernelGGL(k_coarse_count<false>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, in.bytes,
+                         in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, ccnt, hrow);
+    tm.mark();  // 1
+    hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1024), 0, st, ccnt, (uint32_t)C, cbase, cur);
+    tm.mark();  // 2
+    if (str)
+      hipLaunchKernelGGL(k_coarse_scatter<true>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, stage, n,
+                         per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
+    else
+      hipLaunchKernelGGL(k_coarse_scatter<false>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, stage, n,
+                         per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
+    tm.mark();  // 3
+    hipLaunchKernelGGL(k_segment_sort, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st, codes, cbase,
+                       h->d_table, B, nbpad, (uint32_t)gshift, K, seg_cap, sortedf, blist, nbk, off, err,
+                       (ulonglong2*)part_codes_out);
+    if (an != ad) {
+      PHOBIC_HIP(S.get(&toff, K + 1));
+      hipLaunchKernelGGL(k_table_offsets, dim3(1), dim3(1024), 0, st, off, K, an, ad, toff, err, d64);
+    } else {
+      toff = off;
+    }
+    tm.mark();  // 4
+    PHOBIC_HIP(hipGetLastError());
+  } else {
+    // general path for very many partitions: per-key global atomics
+    uint32_t* cnt;
+    uint64_t* dinfo;
+    ulonglong2 *codes, *stage = nullptr;
+    PHOBIC_HIP(S.get(&cnt, K + 1));
+    PHOBIC_HIP(S.get(&toff, K + 1));
+    PHOBIC_HIP(S.get(&dinfo, 8));
+    PHOBIC_HIP(S.get(&codes, n));
+    if (str) PHOBIC_HIP(S.get(&stage, n));
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, cnt, K + 1, 0u);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, dinfo, (uint64_t)8, (uint64_t)0);
+    tm.mark();  // 0
+    if (!str)
+      hipLaunchKernelGGL(k_hash_count_u64, dim3(grid_for(n)), dim3(kBlock), 0, st, in.keys, n, prm.hash_seed, K, cnt);
+    else
+      hipLaunchKernelGGL(k_hash_count_str, dim3(grid_for(n)), dim3(kBlock), 0, st, in.bytes, in.offs, n,
+                         prm.hash_seed, K, stage, cnt);
+    tm.mark();  // 1
+    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, cnt, K, an, ad, off, toff, dinfo);
+    tm.mark();  // 2
+    PHOBIC_HIP(hipGetLastError());
+    PHOBIC_HIP(hipMemcpyAsync(old_info, dinfo, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
+    PHOBIC_HIP(hipStreamSynchronize(st));
+    if (old_info[0] > kMaxPartitionKeys)
+      return fail(PHOBIC_E_CAPACITY, "a partition holds " + std::to_string(old_info[0]) +
+                                         " keys; the device path holds at most " + std::to_string(kMaxPartitionKeys));
+    if (!str)
+      hipLaunchKernelGGL(k_scatter_u64, dim3(grid_for(n)), dim3(kBlock), 0, st, in.keys, n, prm.hash_seed, K, off,
+                         cnt, codes);
+    else
+      hipLaunchKernelGGL(k_scatter_codes, dim3(grid_for(n)), dim3(kBlock), 0, st, stage, n, K, off, cnt, codes);
+    tm.mark();  // 3
+    if (part_codes_out)
+      PHOBIC_HIP(hipMemcpyAsync(part_codes_out, codes, n * sizeof(ulonglong2), hipMemcpyDeviceToDevice, st));
+    const size_t sort_lds = (2 * (size_t)nbpad + std::max<uint64_t>(old_info[0], 1)) * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_bucket_sort, dim3((uint32_t)K), dim3(kBlock), sort_lds, st, codes, off, h->d_table, B,
+                       nbpad, sortedf, blist, nbk, err + 1);
+    tm.mark();  // 4
+    PHOBIC_HIP(hipGetLastError());
+  }
+
+  uint32_t hinfo[4] = {0, 0, 0, 0};
+  uint64_t htot = 0;
+  PHOBIC_HIP(hipMemcpyAsync(hinfo, err, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(&htot, d64, sizeof(htot), hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipStreamSynchronize(st));
+  if (hinfo[0] & (1u << PHOBIC_E_CAPACITY))
+    return fail(PHOBIC_E_CAPACITY, "a group of partitions exceeds the LDS of the bucket-sort workgroup");
+  if (part_offsets_out) {  // stages a1-a2 only
+    PHOBIC_HIP(hipMemcpyAsync(part_offsets_out, off, (K + 1) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+    PHOBIC_HIP(hipStreamSynchronize(st));
+    return PHOBIC_OK;
+  }
+  const uint64_t max_nj = coarse_path ? hinfo[2] : old_info[0];
+  const uint64_t max_m = coarse_path ? (an != ad ? hinfo[3] : max_nj) : old_info[1];
+  const uint64_t total = coarse_path ? (an != ad ? htot : n) : old_info[2];
+  const uint32_t hmaxb = hinfo[1];
+  h->info.max_partition_keys = max_nj;
   h->info.max_bucket_keys = hmaxb;
+  if (max_m > kMaxTableSlots)
+    return fail(PHOBIC_E_CAPACITY, "a partition needs " + std::to_string(max_m) + " slots; the device path holds " +
+                                       std::to_string(kMaxTableSlots));
 
   // a5
   uint64_t* taken = nullptr;
@@ -823,7 +1346,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
                        (uint64_t)0);
   }
   SearchArgs sa;
-  sa.sorted = sorted;
+  sa.fp = sortedf;
   sa.off = off;
   sa.toff = toff;
   sa.blist = blist;
@@ -835,16 +1358,23 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   sa.limit = limit;
   sa.B = B;
   const uint32_t mm = (uint32_t)std::max<uint64_t>(max_m, 1);
-  sa.f2_words = (2 * mm + 127) / 32 + 1;
-  sa.scr_words = (mm + 31) / 32 + 1;
-  if ((sa.f2_words + sa.scr_words) & 1) sa.scr_words++;  // keeps rbuf 8-byte aligned
-  sa.rb_cap = ((std::max<uint32_t>(hmaxb, 1) + 3) / 4) * 4 + 4;
-  const uint32_t ngroups = (std::max<uint32_t>(hmaxb, 1) + 63) / 64;
-  const size_t search_lds = (size_t)(sa.f2_words + sa.scr_words) * 4 + (size_t)sa.rb_cap * 2 + (size_t)ngroups * 8;
+  const uint32_t mb = std::max<uint32_t>(hmaxb, 1);
+  auto up4 = [](uint32_t v) { return (v + 3) & ~3u; };
+  sa.f2_words = up4((2 * mm + 127) / 32 + 1);
+  sa.scr_words = up4((mm + 31) / 32 + 1);
+  sa.rb_cap = up4(mb) + 4;
+  sa.bl_cap = up4(B);
+  sa.cm_cap = (mb + 63) / 64 + 1;
+  sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
+  sa.owner = nullptr;
+  sa.Kbase = nullptr;
+  sa.Kt = nullptr;
+  sa.fail_part_set = 0;
+  unsigned long long* queue;
+  PHOBIC_HIP(S.get(&queue, 1));
+  tm.mark();  // 5
+  PHOBIC_HIP(launch_search(sa, K, st, queue));
   tm.mark();  // 6
-  hipLaunchKernelGGL(k_search, dim3((uint32_t)K), dim3(64), search_lds, st, sa);
-  tm.mark();  // 7
-  PHOBIC_HIP(hipGetLastError());
 
   // a6: statistics -> host parameters
   uint64_t* shsum;
@@ -918,7 +1448,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   hdr[kHR] = R;
   const uint64_t nwords = hdr[kHWords];
 
-  PHOBIC_HIP(hipMalloc(&h->d_image, nwords * sizeof(uint64_t)));
+  PHOBIC_HIP(hipMallocAsync((void**)&h->d_image, nwords * sizeof(uint64_t), st));
   h->nwords = nwords;
   h->header = hdr;
   uint64_t* img = h->d_image;
@@ -951,16 +1481,16 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
                        wremap, img + hdr[kHSecRemap]);
     PHOBIC_HIP(hipGetLastError());
   }
-  tm.mark();  // 8
+  tm.mark();  // 7
   PHOBIC_HIP(hipStreamSynchronize(st));
   auto t_host1 = std::chrono::steady_clock::now();
 
   h->info.hash_count_ms = tm.ms(0, 1);
   h->info.scan_ms = tm.ms(1, 2);
   h->info.scatter_ms = tm.ms(2, 3);
-  h->info.bucket_sort_ms = tm.ms(4, 5);
-  h->info.search_ms = tm.ms(6, 7);
-  h->info.encode_ms = tm.ms(7, 8);
+  h->info.bucket_sort_ms = tm.ms(3, 4);
+  h->info.search_ms = tm.ms(5, 6);
+  h->info.encode_ms = tm.ms(6, 7);
   h->info.total_ms = std::chrono::duration<double, std::milli>(t_host1 - t_host0).count();
   fill_query_args(h);
   *out = h;
@@ -992,4 +1522,23 @@ extern "C" phobic_status phobic_partition_u64(const uint64_t* d_keys, uint64_t n
   if (!d_offsets || (n && !d_codes)) return fail(PHOBIC_E_INVALID, "null output pointer");
   BuildInput in{Src::U64, d_keys, nullptr, nullptr, n};
   return build_impl(in, params, (hipStream_t)hip_stream, nullptr, d_offsets, d_codes);
+}
+
+extern "C" phobic_status phobic_set_search_config(const phobic_search_config* cfg) {
+  if (!cfg) return fail(PHOBIC_E_INVALID, "cfg is null");
+  const uint32_t w = cfg->waves_per_group;
+  if (w != 1 && w != 2 && w != 4 && w != 8) return fail(PHOBIC_E_INVALID, "waves_per_group must be 1, 2, 4 or 8");
+  if (cfg->groups_per_cu > 64) return fail(PHOBIC_E_INVALID, "groups_per_cu must be at most 64");
+  if (cfg->groups_per_cu && (cfg->items_per_grab < 1 || cfg->items_per_grab > 4096))
+    return fail(PHOBIC_E_INVALID, "items_per_grab must be in [1, 4096]");
+  std::lock_guard<std::mutex> lock(g_cfg_mu);
+  g_cfg = *cfg;
+  g_cfg.reserved = 0;
+  return PHOBIC_OK;
+}
+
+extern "C" phobic_status phobic_get_search_config(phobic_search_config* out) {
+  if (!out) return fail(PHOBIC_E_INVALID, "out is null");
+  *out = search_config();
+  return PHOBIC_OK;
 }

@@ -53,7 +53,7 @@ struct phobic_mphf {
   uint64_t* d_image = nullptr;
   uint64_t nwords = 0;
   std::vector<uint64_t> header;   // host copy of the header words
-  uint64_t* d_table = nullptr;
+  uint64_t* d_table = nullptr;   // borrowed from the per-device table cache
   uint32_t* d_pilots = nullptr;   // encoder-major (i * K + j), only with PHOBIC_FLAG_KEEP_PILOTS
   phobic_build_info info{};
   phobic::QueryArgs qa{};
@@ -138,9 +138,12 @@ __device__ __forceinline__ void hash_key_str(const uint8_t* s, uint64_t len, uin
   lo = mix_b(b ^ len);
 }
 
-// Seeded position hash h(x, s) in [0, m).
-__device__ __forceinline__ uint32_t pos_hash(uint64_t hi, uint64_t lo, uint64_t s, uint32_t m) {
-  return mulhi_u32(mix_a(lo ^ mix_b(hi ^ ((s + 1) * kPhi64))), m);
+// 64-bit fingerprint of a key's code; the position hash sees the key only through it.
+__device__ __forceinline__ uint64_t fingerprint(uint64_t hi, uint64_t lo) { return lo ^ mix_b(hi); }
+
+// Seeded position hash h(x, s) in [0, m): w = (s + 1) * phi is the seed's Weyl value.
+__device__ __forceinline__ uint32_t pos_hash(uint64_t f, uint64_t w, uint32_t m) {
+  return mulhi_u32(mix_a(f ^ w), m);
 }
 
 // Bucket of a key: linear interpolation of the tabulated bucket function, scaled to B buckets.

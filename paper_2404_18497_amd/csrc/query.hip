@@ -87,7 +87,7 @@ __device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, 
   const uint32_t p32 = (uint32_t)p;
   const uint32_t s = p32 / m;
   const uint32_t d = p32 - s * m;
-  uint32_t pos = pos_hash(hi, lo, s, m) + d;
+  uint32_t pos = pos_hash(fingerprint(hi, lo), (uint64_t)(s + 1) * kPhi64, m) + d;
   if (pos >= m) pos -= m;
   const uint64_t g = o0 + pos;
   if (g < a.n) return g;

@@ -354,3 +354,28 @@ def test_offsets_are_prefix_sums(ref):
     part = np.array([(int(x) * K) >> 64 for x in hi])
     want = np.concatenate([[0], np.cumsum(np.bincount(part, minlength=K))]).astype(np.uint64)
     assert np.array_equal(h.offsets(), want)
+
+
+def test_position_hash_collisions_independent_of_seed(ref):
+    # Sec. 4 "Hash Function": XOR-combined hashes fail in small partitions because two keys that
+    # collide under one seed keep colliding under others.  For the project's hash, a pair of keys
+    # must collide under a fraction ~1/m of the seeds, independently per seed, also for keys whose
+    # codes differ in a single bit.
+    m, seeds = 97, 400
+    rng = np.random.default_rng(5)
+    pairs = []
+    for _ in range(300):
+        hi, lo = (int(x) for x in rng.bit_generator.random_raw(2))
+        pairs.append(((hi, lo), (hi, lo ^ (1 << int(rng.integers(0, 64))))))
+        pairs.append(((hi, lo), (hi ^ (1 << int(rng.integers(0, 64))), lo)))
+        h2, l2 = (int(x) for x in rng.bit_generator.random_raw(2))
+        pairs.append(((hi, lo), (h2, l2)))
+    counts = []
+    for (a, b) in pairs:
+        c = sum(ref.pos_hash(a[0], a[1], s, m) == ref.pos_hash(b[0], b[1], s, m) for s in range(seeds))
+        counts.append(c)
+    counts = np.array(counts)
+    p = 1 / m
+    assert abs(counts.mean() / seeds - p) < 4 * math.sqrt(p / (seeds * len(pairs)))
+    # Binomial(400, 1/97): mean 4.1; no pair may stick together
+    assert counts.max() <= 20
