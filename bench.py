@@ -1,14 +1,21 @@
 #!/usr/bin/env python3
-"""PHOBIC build + bulk query on one MI355X.
+"""PHOBIC on one MI355X: build + bulk query (default), batched builds, and serving.
 
-Workload (the 100M-key configuration): 100,000,000 distinct uniform uint64 keys (seed 1), P = 2500,
-lambda = 7, alpha = 1, interleaved Rice coding; then 100,000,000 lookups drawn uniformly with
-replacement from the key set (seed 2), queried in batches of 1,000,000. One step = one full build
-(hash, partition, bucket, order, search, encode) plus the 100 query batches. Keys and query keys are
-resident in HBM before timing starts.
+--workload build_query (default; the 100M-key configuration): 100,000,000 distinct uniform uint64 keys
+    (seed 1), P = 2500, lambda = 7, alpha = 1, interleaved Rice coding; then 100,000,000 lookups drawn
+    uniformly with replacement from the key set (seed 2), queried in batches of 1,000,000. One step =
+    one full build (hash, partition, bucket, order, search, encode) plus the 100 query batches. Keys
+    and query keys are resident in HBM before timing starts. ``value`` = build ns/key + query
+    ns/query (lower is better).
+--workload batch: 4096 MPHFs, key counts lognormal(median 50K, sigma 1.5) clipped to [1K, 10M]
+    (seed 5), uniform uint64 keys (set t from seed 100 + t), P 2500, lambda 7; one batched build with
+    an autotuned search shape versus 4096 sequential plain builds. ``value`` = batched ns/key.
+--workload serve: Poisson arrivals of build requests (10%, lognormal sizes median 5e5, sigma 1.5,
+    clipped to [10K, 50M]) and query requests (90%, 1K-1M lookups, log-uniform, against resident
+    MPHFs) under a 200 GB HBM budget; the library's server with continuous batching versus plain
+    per-request FIFO execution, at the same arrival trace. ``value`` = p99 query latency (ms).
 
-Prints one JSON line. ``value`` is build ns/key + query ns/query (lower is better); the breakdown,
-bits/key, the roofline of the dominant kernel and the CPU-oracle baseline ride along.
+Each mode prints one JSON line.
 """
 
 from __future__ import annotations
@@ -24,8 +31,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 39.3 T int32 lane-ops/s
+HBM_PEAK_GBS = 8000.0                                # MI355X HBM3E, 8 TB/s
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12           # 39.3 T int32 lane-ops/s (256 CU x 4 SIMD16 x 2.4 GHz)
+HASH_OPS = 30          # int32 ops of one position-hash evaluation (one 64-bit mixer, xor, multiply-high)
+PROBE_OPS = 1.0 / 16   # a funnel shift and an AND test 32 displacements: 2 ops per 32 slot probes
 
 
 def parse():
@@ -33,13 +42,22 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="build_query", choices=["build_query", "batch", "serve"])
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--lam", type=float, default=7.0)
     ap.add_argument("--coding", default="rice", choices=["rice", "compact"])
     ap.add_argument("--batch", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--mphfs", type=int, default=4096)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--requests", type=int, default=1500)
+    ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of plain capacity")
     return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def cpu_baseline(args):
@@ -60,19 +78,20 @@ def cpu_baseline(args):
     b = (t1 - t0) * 1e9 / keys.size
     qn = (t2 - t1) * 1e9 / q.size
     return {"value": round(b + qn, 2), "unit": "ns/key (build + query)", "cores": threads, "kind": "oracle",
-            "sample": f"{keys.size} keys of the same distribution (seed 1), lambda {args.lam}, {args.coding}; "
+            "sample": f"{keys.size} keys of the same distribution (seed 1), lambda {args.lam:g}, {args.coding}; "
                       f"build {b:.1f} ns/key on {threads} threads, query {qn:.1f} ns/query on 1 thread",
             "build_ns_per_key": round(b, 2), "query_ns_per_query": round(qn, 2)}
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU: this library has no multi-GPU path (how it would shard is described "
-              "in DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
+def search_work(n, lam):
+    """The oracle's exact search counters for the 100M-key workload (tests/golden), else None."""
+    path = os.path.join(ROOT, "tests", "golden", "search_work_100m.json")
+    if n != 100_000_000 or not os.path.exists(path):
+        return None
+    return json.load(open(path))["counters"].get(f"{lam:g}")
 
+
+def headline(args):
     import torch
 
     from paper_2404_18497_amd import binding, synth
@@ -81,7 +100,7 @@ def main():
     dev = torch.device("cuda", 0)
     binding.lib()
     n, batch = args.n, args.batch
-    print(f"[bench] generating {n} keys", file=sys.stderr, flush=True)
+    log(f"generating {n} keys")
     keys = synth.u64_keys(n, 1)
     qidx = synth.query_indices(n, n, 2)
     dk = torch.from_numpy(keys.view(np.int64)).to(dev)
@@ -104,13 +123,12 @@ def main():
             record[2].record(stream)
         return h
 
-    print("[bench] warmup", file=sys.stderr, flush=True)
+    log("warmup")
     for _ in range(args.warmup):
         step().close()
     torch.cuda.synchronize()
-
     handles, events = [], []
-    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -129,23 +147,27 @@ def main():
     bits = handles[0].size_bits() / n
     nlaunch = (n + batch - 1) // batch
 
-    # kernels with their algorithmic traffic per launch
-    kern = {
-        "k_query_u64": {"ms": query_ms / nlaunch, "bytes": 16.0 * min(batch, n), "bound": "hbm"},
-        "k_search": {"ms": phase["search_ms"], "bytes": 16.0 * n + 4.0 * n / args.lam * 2, "bound": "hbm"},
-        "k_scatter_u64": {"ms": phase["scatter_ms"], "bytes": 24.0 * n, "bound": "hbm"},
-        "k_hash_count_u64": {"ms": phase["hash_count_ms"], "bytes": 8.0 * n, "bound": "hbm"},
-        "k_bucket_sort": {"ms": phase["bucket_sort_ms"], "bytes": 32.0 * n, "bound": "hbm"},
-    }
-    total_per_kernel = {k: v["ms"] * (nlaunch if k == "k_query_u64" else 1) for k, v in kern.items()}
-    dom = max(total_per_kernel, key=total_per_kernel.get)
-    d = kern[dom]
-    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-    roofline = {"kernel": dom, "bound": d["bound"], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "per_launch_ms": round(d["ms"], 4), "launches_per_step": nlaunch if dom == "k_query_u64" else 1,
-                "algorithmic_bytes_per_launch": d["bytes"]}
-
+    # dominant kernel and its roofline (per launch; durations from HIP events on the launch stream)
+    per_step = {"k_search": phase["search_ms"], "k_query_u64": query_ms}
+    dom = max(per_step, key=per_step.get)
+    if dom == "k_search":
+        w = search_work(n, args.lam)
+        ops = HASH_OPS * w["hash_evals"] + PROBE_OPS * w["slot_probes"] if w else None
+        achieved = ops / (phase["search_ms"] * 1e-3) / 1e12 if ops else None
+        roofline = {"kernel": "k_search", "bound": "alu", "achieved": None if achieved is None else round(achieved, 3),
+                    "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
+                    "frac": None if achieved is None else round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                    "per_launch_ms": round(phase["search_ms"], 4), "launches_per_step": 1,
+                    "algorithmic_ops_per_launch": ops,
+                    "work": None if not w else {"hash_evals": w["hash_evals"], "slot_probes": w["slot_probes"]}}
+    else:
+        per = query_ms / nlaunch
+        achieved = 16.0 * min(batch, n) / (per * 1e-3) / 1e9
+        roofline = {"kernel": "k_query_u64", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "per_launch_ms": round(per, 4), "launches_per_step": nlaunch,
+                    "algorithmic_bytes_per_launch": 16.0 * min(batch, n)}
+    q_per = query_ms / nlaunch
     out = {
         "metric": "build ns/key + query ns/key @100M keys, bits/key",
         "value": round(ms_per_step * 1e6 / n, 4),
@@ -169,13 +191,168 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in phase.items()} | {"build_ms": round(build_ms, 4),
                                                                    "query_all_batches_ms": round(query_ms, 4)},
         "roofline": roofline,
+        "query_kernel": {"per_launch_ms": round(q_per, 4),
+                         "hbm_GBps": round(16.0 * min(batch, n) / (q_per * 1e-3) / 1e9, 1)},
     }
     for h in handles:
         h.close()
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
+
+
+def batch_mode(args):
+    import torch
+
+    from paper_2404_18497_amd import autotune, binding, synth
+
+    torch.cuda.set_device(0)
+    binding.lib()
+    sizes = synth.lognormal_sizes(args.mphfs, 50_000, 1.5, 1_000, 10_000_000, 5)
+    log(f"generating {args.mphfs} key sets, {int(sizes.sum())} keys")
+    sets = synth.u64_key_sets(sizes, 100)
+    dev = [torch.from_numpy(s.view(np.int64)).cuda() for s in sets]
+    del sets
+    prm = binding.params(lam=7.0)
+    total = int(sizes.sum())
+    tuned, table = None, None
+    if not args.no_tune:
+        log("autotuning the search shape on the first 512 key sets")
+        tuned, table = autotune.tune_batch(dev[:512], prm, repeats=1, log=log)
+    cfg = binding.get_search_config()
+    log("batched build")
+    binding.build_batch_u64(dev, prm)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hs = binding.build_batch_u64(dev, prm)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    info = hs[0].build_info()
+    bits = sum(h.size_bits() for h in hs) / total
+    del hs
+    log("sequential plain builds")
+    binding.build_u64(dev[0], prm).close()
+    t0 = time.perf_counter()
+    for d in dev:
+        binding.build_u64(d, prm).close()
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    out = {
+        "metric": "batched build ns/key (4096 MPHFs in one launch) vs sequential plain builds",
+        "value": round(t_batch * 1e9 / total, 4), "unit": "ns/key", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(t_batch * 1e3, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{args.mphfs} MPHFs, sizes lognormal(median 50K, sigma 1.5) clipped [1K, 10M] "
+                               f"(seed 5), uniform u64 keys (set t seed 100+t), P 2500, lambda 7",
+                   "total_keys": total},
+        "batched_ms": round(t_batch * 1e3, 3), "sequential_ms": round(t_seq * 1e3, 3),
+        "speedup_vs_sequential": round(t_seq / t_batch, 2), "bits_per_key": round(bits, 4),
+        "batched_phases_ms": {k: round(info[k], 3) for k in ["bucket_sort_ms", "search_ms", "encode_ms", "total_ms"]},
+        "search_config": cfg, "tuned": tuned,
+        "tuning_table": None if table is None else [[c, round(ms, 3)] for c, ms in table],
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_mode(args):
+    import torch
+
+    from paper_2404_18497_amd import binding, synth
+
+    torch.cuda.set_device(0)
+    binding.lib()
+    rng = np.random.default_rng(6)
+    R = args.requests
+    kinds = rng.random(R) < 0.1  # True = build
+    nb = int(kinds.sum())
+    bsizes = synth.lognormal_sizes(nb + 16, 500_000, 1.5, 10_000, 50_000_000, 7)
+    qsizes = synth.log_uniform_sizes(R - nb, 1_000, 1_000_000, 8)
+    log(f"{R} requests: {nb} builds ({int(bsizes[16:].sum())} keys), {R - nb} queries; 16 resident MPHFs")
+    keysets = synth.u64_key_sets(bsizes, 500)
+    dkeys = [torch.from_numpy(k.view(np.int64)).cuda() for k in keysets]
+    targets = rng.integers(0, 16, R - nb)
+    qkeys = [dkeys[t][torch.from_numpy(rng.integers(0, keysets[t].size, int(m))).cuda()]
+             for t, m in zip(targets, qsizes)]
+    outs = [torch.empty(int(m), dtype=torch.int64, device="cuda") for m in qsizes]
+    prm = binding.params(lam=7.0)
+    budget = 200 << 30
+
+    def run(server_kw, arrivals):
+        srv = binding.Server(prm, budget_bytes=budget, **server_kw)
+        ids0 = [srv.submit_build(dkeys[t]) for t in range(16)]
+        done = {}
+        while len(done) < 16:
+            for r in srv.poll(wait_ms=100):
+                done[r["request_id"]] = r
+        srv.poll()
+        t_start = srv.now()
+        results, bi, qi = {}, 16, 0
+        for i in range(R):
+            if arrivals is not None:
+                while srv.now() - t_start < arrivals[i]:
+                    for r in srv.poll():
+                        results[r["request_id"]] = r
+                    time.sleep(0.0002)
+            if kinds[i]:
+                srv.submit_build(dkeys[bi])
+                bi += 1
+            else:
+                srv.submit_query(ids0[targets[qi]], qkeys[qi], outs[qi])
+                qi += 1
+        while len(results) < R:
+            for r in srv.poll(wait_ms=100):
+                results[r["request_id"]] = r
+        t_end = max(r["done_s"] for r in results.values())
+        st = srv.stats()
+        srv.close()
+        lat = {k: np.array([r["done_s"] - r["submit_s"] for r in results.values() if r["kind"] == k]) * 1e3
+               for k in ("build", "query")}
+        ok = all(r["status"] == 0 for r in results.values())
+        return {"ok": ok, "makespan_s": t_end - t_start, "throughput_rps": R / (t_end - t_start),
+                "p50_ms": {k: float(np.percentile(v, 50)) for k, v in lat.items() if v.size},
+                "p99_ms": {k: float(np.percentile(v, 99)) for k, v in lat.items() if v.size},
+                "mean_batch": float(np.mean([r["batch"] for r in results.values()])), "stats": st}
+
+    plain_kw = dict(workers=1, max_query_batch=1, max_build_batch=1)
+    served_kw = dict(workers=4, max_query_batch=64, max_build_batch=8)
+    log("plain capacity (all requests at once, FIFO, one at a time)")
+    cap = run(plain_kw, None)
+    rate = args.load * cap["throughput_rps"]
+    arrivals = synth.poisson_arrivals(R, rate, 9)
+    log(f"open loop at {rate:.1f} requests/s: plain")
+    plain = run(plain_kw, arrivals)
+    log("open loop: served (continuous batching)")
+    served = run(served_kw, arrivals)
+    r2 = lambda d: {k: round(v, 3) for k, v in d.items()}  # noqa: E731
+    out = {
+        "metric": "serving p99 query latency (ms), Poisson arrivals, 200 GB HBM budget",
+        "value": round(served["p99_ms"]["query"], 3), "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(served["makespan_s"] * 1e3, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{R} requests, 10% builds (lognormal median 5e5, sigma 1.5, [10K, 50M]), 90% "
+                               f"queries (log-uniform 1K-1M) on 16 resident MPHFs, Poisson at {args.load:g} x "
+                               f"plain capacity ({rate:.1f}/s), 200 GB budget"},
+        "served": {"p50_ms": r2(served["p50_ms"]), "p99_ms": r2(served["p99_ms"]),
+                   "throughput_rps": round(served["throughput_rps"], 2), "mean_batch": round(served["mean_batch"], 2),
+                   "ok": served["ok"], "peak_bytes": served["stats"]["peak_bytes"],
+                   "query_launches": served["stats"]["query_launches"],
+                   "build_launches": served["stats"]["build_launches"]},
+        "plain": {"p50_ms": r2(plain["p50_ms"]), "p99_ms": r2(plain["p99_ms"]),
+                  "throughput_rps": round(plain["throughput_rps"], 2), "ok": plain["ok"]},
+        "plain_capacity_rps": round(cap["throughput_rps"], 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU: this library has no multi-GPU path (how it would shard is described "
+              "in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    {"build_query": headline, "batch": batch_mode, "serve": serve_mode}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -96,6 +96,15 @@ phobic_status phobic_query_u64(const phobic_mphf* h, const uint64_t* d_keys, uin
 phobic_status phobic_query_str(const phobic_mphf* h, const uint8_t* d_bytes, const uint64_t* d_offsets,
                                uint64_t n, uint64_t* d_pos, void* hip_stream);
 
+/* Evaluates `count` requests in one launch: request r queries h_handles[r] for the h_counts[r] keys
+ * at the device pointer h_keys[r] and writes positions to the device pointer h_outs[r] (all four are
+ * host arrays of `count` entries; handles may differ and must live on the current device).  Every
+ * output equals that of a separate phobic_query_u64.  Asynchronous on hip_stream; the host arrays
+ * may be reused as soon as the call returns. */
+phobic_status phobic_query_multi_u64(const phobic_mphf* const* h_handles, const uint64_t* const* h_keys,
+                                     const uint64_t* h_counts, uint64_t* const* h_outs, uint32_t count,
+                                     void* hip_stream);
+
 /* Size of the structure in bits = 8 x serialized bytes (header and tables included). */
 uint64_t phobic_size_bits(const phobic_mphf* h);
 uint64_t phobic_num_keys(const phobic_mphf* h);
@@ -106,7 +115,8 @@ uint32_t phobic_num_buckets(const phobic_mphf* h);
  * h_out (host, cap entries).  Needs PHOBIC_FLAG_KEEP_PILOTS at build time. */
 phobic_status phobic_get_pilots(const phobic_mphf* h, uint32_t* h_out, uint64_t cap);
 
-/* Per-phase times of the build that produced h (zeros for deserialized handles). */
+/* Per-phase times of the build that produced h (zeros for deserialized handles; for members of a
+ * batch, the times of the whole batch, with hashing, partitioning and bucketing in bucket_sort_ms). */
 phobic_status phobic_get_build_info(const phobic_mphf* h, phobic_build_info* out);
 
 /* Serializes h into h_buf (host).  *inout_bytes holds the capacity on entry and the image size on
@@ -136,6 +146,80 @@ typedef struct {
 /* Sets the search shape used by later builds on the calling process (all devices). */
 phobic_status phobic_set_search_config(const phobic_search_config* cfg);
 phobic_status phobic_get_search_config(phobic_search_config* out);
+
+/* Builds `count` independent MPHFs together: MPHF t is built from the h_counts[t] distinct keys at
+ * the device pointer h_key_ptrs[t] (both arrays are host arrays of `count` entries), all with the
+ * same params (alpha must be 1).  Every handle outs[t] is identical -- pilots, image, positions --
+ * to what phobic_build_u64 returns for the same keys.  Hashing, partitioning and bucketing run over
+ * the concatenated key sets; the pilot search is one persistent launch over all (MPHF, partition)
+ * items; encoding runs for all MPHFs in a handful of launches.  The handles share one device
+ * allocation that is released with the last of them.  On failure every outs[t] is NULL and
+ * phobic_last_error() names the first failing MPHF. */
+phobic_status phobic_build_batch_u64(const uint64_t* const* h_key_ptrs, const uint64_t* h_counts, uint32_t count,
+                                     const phobic_params* params, void* hip_stream, phobic_mphf** outs);
+
+/* ---- Serving: resident MPHFs, build and query requests under an HBM budget ----------------------
+ * A server keeps the MPHFs it built resident on the device and runs requests on `workers` HIP
+ * streams at once.  Requests are admitted in arrival order as workers and memory free up: a build
+ * is admitted when its estimated device memory (32 bytes per key plus 64 MiB) fits in what the
+ * budget leaves after resident images and builds in flight; a query needs no memory of its own.
+ * Continuous batching: a worker that picks up queries takes up to max_query_batch pending ones (any
+ * MPHFs) into one launch, and a worker that picks up builds takes up to max_build_batch admissible
+ * ones into one batched build.  Neither changes any pilot, image or position.  The caller owns all
+ * key and output buffers and keeps them valid until the request completes.  All calls are
+ * thread-safe. */
+typedef struct phobic_server phobic_server;
+
+typedef struct {
+  uint64_t hbm_budget_bytes; /* device memory for builds in flight and resident images */
+  uint32_t workers;          /* requests in flight at once, one HIP stream each, >= 1 */
+  uint32_t max_query_batch;  /* queries per launch, >= 1 (1 = no query batching) */
+  uint32_t max_build_batch;  /* builds per batched build, >= 1 (1 = no build batching) */
+  uint32_t reserved;
+} phobic_server_config;
+
+enum { PHOBIC_REQ_BUILD = 0, PHOBIC_REQ_QUERY = 1 };
+
+typedef struct {
+  uint64_t request_id;
+  uint64_t mphf_id;  /* builds: the id of the new MPHF (= request_id); queries: the queried MPHF */
+  uint64_t n;        /* keys of the request */
+  int32_t status;    /* phobic_status of the request */
+  uint32_t kind;     /* PHOBIC_REQ_BUILD or PHOBIC_REQ_QUERY */
+  uint32_t batch;    /* requests that ran in the same launch or batched build */
+  uint32_t reserved;
+  double submit_s, start_s, done_s; /* seconds on the server's steady clock */
+} phobic_request_result;
+
+typedef struct {
+  uint64_t resident_mphfs;
+  uint64_t resident_bytes;
+  uint64_t reserved_bytes;   /* estimates of builds in flight */
+  uint64_t peak_bytes;       /* peak of resident + reserved */
+  uint64_t query_launches, build_launches;
+  uint64_t completed, pending;
+} phobic_server_stats;
+
+phobic_status phobic_server_create(const phobic_server_config* cfg, const phobic_params* params,
+                                   phobic_server** out);
+/* Queues a build of the n keys at d_keys; *request_id is also the id of the MPHF it creates, so
+ * queries against it may be queued before it completes (they wait for it). */
+phobic_status phobic_server_submit_build(phobic_server* s, const uint64_t* d_keys, uint64_t n,
+                                         uint64_t* request_id);
+/* Queues a query of the n keys at d_keys against MPHF mphf_id; positions go to d_pos. */
+phobic_status phobic_server_submit_query(phobic_server* s, uint64_t mphf_id, const uint64_t* d_keys, uint64_t n,
+                                         uint64_t* d_pos, uint64_t* request_id);
+/* Moves up to cap completed results into out (completion order); waits up to wait_ms for one. */
+phobic_status phobic_server_poll(phobic_server* s, phobic_request_result* out, uint32_t cap, uint32_t* got,
+                                 uint32_t wait_ms);
+/* The resident MPHF mphf_id (borrowed; valid until released), or NULL. */
+const phobic_mphf* phobic_server_mphf(phobic_server* s, uint64_t mphf_id);
+/* Frees a resident MPHF once no queued or running query uses it. */
+phobic_status phobic_server_release(phobic_server* s, uint64_t mphf_id);
+phobic_status phobic_server_get_stats(phobic_server* s, phobic_server_stats* out);
+double phobic_server_now(phobic_server* s); /* the server's clock, seconds */
+/* Waits for every queued request, then frees the resident MPHFs and the server. */
+void phobic_server_destroy(phobic_server* s);
 
 void phobic_free(phobic_mphf* h);
 const char* phobic_status_str(phobic_status s);

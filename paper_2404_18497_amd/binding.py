@@ -24,7 +24,11 @@ EXPORTS = [
     "phobic_size_bits", "phobic_num_keys", "phobic_num_partitions", "phobic_num_buckets", "phobic_get_pilots",
     "phobic_get_build_info", "phobic_serialize", "phobic_deserialize", "phobic_partition_u64", "phobic_free",
     "phobic_status_str", "phobic_last_error", "phobic_set_search_config", "phobic_get_search_config",
+    "phobic_build_batch_u64", "phobic_query_multi_u64", "phobic_server_create", "phobic_server_submit_build",
+    "phobic_server_submit_query", "phobic_server_poll", "phobic_server_mphf", "phobic_server_release",
+    "phobic_server_get_stats", "phobic_server_now", "phobic_server_destroy",
 ]
+REQ_BUILD, REQ_QUERY = 0, 1
 
 
 class PhobicError(RuntimeError):
@@ -37,6 +41,27 @@ class Params(C.Structure):
     _fields_ = [("partition_size", C.c_uint32), ("coding", C.c_uint32), ("lambda_", C.c_double),
                 ("alpha_num", C.c_uint32), ("alpha_den", C.c_uint32), ("hash_seed", C.c_uint64),
                 ("pilot_limit", C.c_uint64), ("n_compact", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class SearchConfig(C.Structure):
+    _fields_ = [("waves_per_group", C.c_uint32), ("groups_per_cu", C.c_uint32), ("items_per_grab", C.c_uint32),
+                ("reserved", C.c_uint32)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("workers", C.c_uint32), ("max_query_batch", C.c_uint32),
+                ("max_build_batch", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("request_id", C.c_uint64), ("mphf_id", C.c_uint64), ("n", C.c_uint64), ("status", C.c_int32),
+                ("kind", C.c_uint32), ("batch", C.c_uint32), ("reserved", C.c_uint32), ("submit_s", C.c_double),
+                ("start_s", C.c_double), ("done_s", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in ["resident_mphfs", "resident_bytes", "reserved_bytes", "peak_bytes",
+                                          "query_launches", "build_launches", "completed", "pending"]]
 
 
 class BuildInfo(C.Structure):
@@ -73,6 +98,22 @@ def lib() -> C.CDLL:
         L.phobic_serialize.argtypes = [vp, vp, C.POINTER(u64)]
         L.phobic_deserialize.argtypes = [vp, u64, vp, C.POINTER(vp)]
         L.phobic_partition_u64.argtypes = [vp, u64, P, vp, vp, vp]
+        L.phobic_build_batch_u64.argtypes = [C.POINTER(vp), C.POINTER(u64), u32, P, vp, C.POINTER(vp)]
+        L.phobic_set_search_config.argtypes = [C.POINTER(SearchConfig)]
+        L.phobic_get_search_config.argtypes = [C.POINTER(SearchConfig)]
+        L.phobic_query_multi_u64.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(u64), C.POINTER(vp), u32, vp]
+        L.phobic_server_create.argtypes = [C.POINTER(ServerConfig), P, C.POINTER(vp)]
+        L.phobic_server_submit_build.argtypes = [vp, vp, u64, C.POINTER(u64)]
+        L.phobic_server_submit_query.argtypes = [vp, u64, vp, u64, vp, C.POINTER(u64)]
+        L.phobic_server_poll.argtypes = [vp, C.POINTER(RequestResult), u32, C.POINTER(u32), u32]
+        L.phobic_server_mphf.argtypes = [vp, u64]
+        L.phobic_server_mphf.restype = vp
+        L.phobic_server_release.argtypes = [vp, u64]
+        L.phobic_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.phobic_server_now.argtypes = [vp]
+        L.phobic_server_now.restype = C.c_double
+        L.phobic_server_destroy.argtypes = [vp]
+        L.phobic_server_destroy.restype = None
         L.phobic_free.argtypes = [vp]
         L.phobic_free.restype = None
         L.phobic_status_str.argtypes = [C.c_int]
@@ -81,7 +122,10 @@ def lib() -> C.CDLL:
         L.phobic_last_error.restype = C.c_char_p
         for name in ["phobic_build_u64", "phobic_build_str", "phobic_query_u64", "phobic_query_str",
                      "phobic_get_pilots", "phobic_get_build_info", "phobic_serialize", "phobic_deserialize",
-                     "phobic_partition_u64"]:
+                     "phobic_partition_u64", "phobic_build_batch_u64", "phobic_set_search_config",
+                     "phobic_get_search_config", "phobic_query_multi_u64", "phobic_server_create",
+                     "phobic_server_submit_build", "phobic_server_submit_query", "phobic_server_poll",
+                     "phobic_server_release", "phobic_server_get_stats"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -122,13 +166,14 @@ def _dptr(t) -> C.c_void_p:
 
 
 class MPHF:
-    """A device-resident PHOBIC MPHF (owns the library handle)."""
+    """A device-resident PHOBIC MPHF (owns the library handle unless borrowed from a server)."""
 
-    def __init__(self, handle: C.c_void_p):
+    def __init__(self, handle: C.c_void_p, owned: bool = True):
         self.h = handle
+        self.owned = owned
 
     def close(self):
-        if getattr(self, "h", None) and _lib is not None:
+        if getattr(self, "h", None) and self.owned and _lib is not None:
             _lib.phobic_free(self.h)
         self.h = None
 
@@ -195,6 +240,102 @@ def build_str(data, offsets, prm: Params, stream=None) -> MPHF:
     n = offsets.numel() - 1
     _check(lib().phobic_build_str(_dptr(data), _dptr(offsets), n, C.byref(prm), _stream(stream), C.byref(h)))
     return MPHF(h)
+
+
+def build_batch_u64(key_tensors, prm: Params, stream=None) -> list:
+    """Builds one MPHF per tensor of keys in a single batched pass; returns the handles in order."""
+    count = len(key_tensors)
+    for t in key_tensors:
+        _dptr(t)
+    ptrs = (C.c_void_p * max(count, 1))(*[t.data_ptr() if t.numel() else None for t in key_tensors])
+    counts = (C.c_uint64 * max(count, 1))(*[t.numel() for t in key_tensors])
+    outs = (C.c_void_p * max(count, 1))()
+    _check(lib().phobic_build_batch_u64(ptrs, counts, count, C.byref(prm), _stream(stream), outs))
+    return [MPHF(C.c_void_p(outs[t])) for t in range(count)]
+
+
+def query_multi_u64(handles, key_tensors, out_tensors, stream=None):
+    """One launch for several (MPHF, keys) requests; out_tensors receive the positions."""
+    count = len(handles)
+    hs = (C.c_void_p * max(count, 1))(*[h.h.value if isinstance(h.h, C.c_void_p) else h.h for h in handles])
+    ks = (C.c_void_p * max(count, 1))(*[_dptr(k).value for k in key_tensors])
+    ns = (C.c_uint64 * max(count, 1))(*[k.numel() for k in key_tensors])
+    os_ = (C.c_void_p * max(count, 1))(*[_dptr(o).value for o in out_tensors])
+    _check(lib().phobic_query_multi_u64(hs, ks, ns, os_, count, _stream(stream)))
+
+
+class Server:
+    """The library's serving loop (resident MPHFs, HBM-budget admission, continuous batching).
+
+    Keeps a reference to every tensor of a request until its completion is polled."""
+
+    def __init__(self, prm: Params, budget_bytes: int, workers: int = 4, max_query_batch: int = 32,
+                 max_build_batch: int = 8):
+        cfg = ServerConfig(budget_bytes, workers, max_query_batch, max_build_batch, 0)
+        self.s = C.c_void_p()
+        _check(lib().phobic_server_create(C.byref(cfg), C.byref(prm), C.byref(self.s)))
+        self._live = {}
+
+    def submit_build(self, keys) -> int:
+        rid = C.c_uint64()
+        _check(lib().phobic_server_submit_build(self.s, _dptr(keys), keys.numel(), C.byref(rid)))
+        self._live[rid.value] = (keys,)
+        return rid.value
+
+    def submit_query(self, mphf_id: int, keys, out) -> int:
+        rid = C.c_uint64()
+        _check(lib().phobic_server_submit_query(self.s, mphf_id, _dptr(keys), keys.numel(), _dptr(out),
+                                                C.byref(rid)))
+        self._live[rid.value] = (keys, out)
+        return rid.value
+
+    def poll(self, cap: int = 1024, wait_ms: int = 0) -> list:
+        buf = (RequestResult * cap)()
+        got = C.c_uint32()
+        _check(lib().phobic_server_poll(self.s, buf, cap, C.byref(got), wait_ms))
+        out = []
+        for i in range(got.value):
+            r = buf[i]
+            self._live.pop(r.request_id, None)
+            out.append({"request_id": r.request_id, "mphf_id": r.mphf_id, "n": r.n, "status": r.status,
+                        "kind": "build" if r.kind == REQ_BUILD else "query", "batch": r.batch,
+                        "submit_s": r.submit_s, "start_s": r.start_s, "done_s": r.done_s})
+        return out
+
+    def mphf(self, mphf_id: int):
+        p = lib().phobic_server_mphf(self.s, mphf_id)
+        return MPHF(C.c_void_p(p), owned=False) if p else None
+
+    def release(self, mphf_id: int):
+        _check(lib().phobic_server_release(self.s, mphf_id))
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().phobic_server_get_stats(self.s, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def now(self) -> float:
+        return lib().phobic_server_now(self.s)
+
+    def close(self):
+        if getattr(self, "s", None) and _lib is not None:
+            _lib.phobic_server_destroy(self.s)
+        self.s = None
+        self._live = {}
+
+    __del__ = close
+
+
+def set_search_config(waves_per_group=4, groups_per_cu=0, items_per_grab=1):
+    cfg = SearchConfig(waves_per_group, groups_per_cu, items_per_grab, 0)
+    _check(lib().phobic_set_search_config(C.byref(cfg)))
+
+
+def get_search_config() -> dict:
+    cfg = SearchConfig()
+    _check(lib().phobic_get_search_config(C.byref(cfg)))
+    return {"waves_per_group": cfg.waves_per_group, "groups_per_cu": cfg.groups_per_cu,
+            "items_per_grab": cfg.items_per_grab}
 
 
 def deserialize(image: np.ndarray, stream=None) -> MPHF:

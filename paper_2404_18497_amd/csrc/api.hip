@@ -16,6 +16,7 @@ namespace phobic {
 
 namespace {
 thread_local std::string g_last_error;
+uint32_t host_bit_length_pub(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
 }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -113,6 +114,40 @@ phobic_status upload_table(phobic_mphf* h, hipStream_t st) {
   g_tables[key] = d;
   h->d_table = d;
   return PHOBIC_OK;
+}
+
+// Header words of an image; the section layout follows from the sizes (see the format notes).
+std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phobic_params& prm, uint64_t total,
+                                  int64_t dmin, uint32_t woff, uint64_t data_bits, uint64_t unary_bits, uint64_t R) {
+  const bool rice = prm.coding == PHOBIC_IC_RICE;
+  const uint64_t nremap = total - n;
+  const uint32_t wremap = n > 1 ? host_bit_length_pub(n - 1) : 0;
+  const uint64_t nsel = rice ? (K * B + kSelEvery - 1) / kSelEvery : 0;
+  std::vector<uint64_t> hdr(kHeaderWords, 0);
+  hdr[kHMagic] = kMagic;
+  hdr[kHN] = n;
+  hdr[kHK] = K;
+  hdr[kHB] = B;
+  hdr[kHP] = prm.partition_size;
+  std::memcpy(&hdr[kHLambda], &prm.lambda, 8);
+  hdr[kHAlpha] = (uint64_t)prm.alpha_num | ((uint64_t)prm.alpha_den << 32);
+  hdr[kHCoding] = prm.coding;
+  hdr[kHSeed] = prm.hash_seed;
+  hdr[kHTotal] = total;
+  hdr[kHDmin] = (uint64_t)dmin;
+  hdr[kHWoff] = woff;
+  hdr[kHSecOff] = kHeaderWords;
+  hdr[kHSecEnc] = hdr[kHSecOff] + ((K + 1) * woff + 63) / 64 + 1;
+  hdr[kHSecData] = hdr[kHSecEnc] + B + 1;
+  hdr[kHSecUnary] = hdr[kHSecData] + (data_bits + 63) / 64 + 1;
+  hdr[kHSecSel] = hdr[kHSecUnary] + (rice ? (unary_bits + 63) / 64 + 1 : 0);
+  hdr[kHSecRemap] = hdr[kHSecSel] + (rice ? (nsel + 1) / 2 + 1 : 0);
+  hdr[kHWremap] = wremap;
+  hdr[kHNremap] = nremap;
+  hdr[kHUbits] = rice ? unary_bits : 0;
+  hdr[kHWords] = hdr[kHSecRemap] + (nremap ? (nremap * wremap + 63) / 64 + 1 : 0);
+  hdr[kHR] = R;
+  return hdr;
 }
 
 void fill_query_args(phobic_mphf* h) {
@@ -325,8 +360,11 @@ extern "C" phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, v
 extern "C" void phobic_free(phobic_mphf* h) {
   if (!h) return;
   // the image comes from the stream-ordered pool; the null stream orders the release after all
-  // work already enqueued on blocking streams
-  if (h->d_image) (void)hipFreeAsync(h->d_image, nullptr);
+  // work already enqueued on blocking streams.  Batch members share one allocation.
+  if (h->shared)
+    h->shared.reset();
+  else if (h->d_image)
+    (void)hipFreeAsync(h->d_image, nullptr);
   if (h->d_pilots) (void)hipFree(h->d_pilots);
   delete h;
 }

@@ -19,6 +19,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -348,10 +349,17 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_scatter(const uint64_
 
 // One workgroup per coarse bin of up to kMaxG partitions.  info[0] |= error bits, info[1] = max
 // bucket size, info[2] = max partition size.
+//
+// kRecords = false: codes are (hi, lo) of one MPHF with K partitions; the partition is mulhi(hi, K).
+// kRecords = true (batches): codes are (fingerprint, lo with the partition's slot in the bin in its
+// low three bits, which the bucket function never reads); partitions are global indices of the
+// batch, this launch covers [jbase, jend), and kbase is the global index of its first key.
+template <bool kRecords>
 __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* __restrict__ codes,
                                                               const uint64_t* __restrict__ cbase,
                                                               const uint64_t* __restrict__ T, uint32_t B,
                                                               uint32_t nbpad, uint32_t gshift, uint64_t K,
+                                                              uint64_t jbase, uint64_t jend, uint64_t kbase,
                                                               uint32_t seg_cap, uint64_t* __restrict__ sortedf,
                                                               uint32_t* __restrict__ blist, uint32_t* __restrict__ nbk,
                                                               uint64_t* __restrict__ off, uint32_t* __restrict__ info,
@@ -367,9 +375,9 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* 
   __shared__ uint32_t psize[kMaxG], nonempty[kMaxG];
   const uint32_t tid = threadIdx.x;
   const uint64_t c = blockIdx.x;
-  const uint64_t j0 = c << gshift;
-  const uint32_t ghere = (uint32_t)min<uint64_t>(G, K - j0);
-  const uint64_t base = cbase[c];
+  const uint64_t j0 = jbase + (c << gshift);
+  const uint32_t ghere = (uint32_t)min<uint64_t>(G, jend - j0);
+  const uint64_t base = cbase[c];  // inside this launch's code array
   const uint32_t ns = (uint32_t)(cbase[c + 1] - base);
   if (ns > seg_cap) {
     if (tid == 0) atomicOr(&info[0], 1u << PHOBIC_E_CAPACITY);
@@ -384,11 +392,11 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* 
     const uint32_t i = tid + t * kSegThreads;
     if (i < ns) {
       const ulonglong2 cd = codes[base + i];
-      const uint32_t p = (uint32_t)(__umul64hi(cd.x, K) - j0);
+      const uint32_t p = kRecords ? (uint32_t)(cd.y & 7) : (uint32_t)(__umul64hi(cd.x, K) - j0);
       const uint32_t b = bucket_of(cd.y, T, B);
       const uint32_t r = atomicAdd(&cnt[p * nbpad + b], 1u);
       rec[i] = (p << 29) | (b << 16) | r;
-      fp[t] = fingerprint(cd.x, cd.y);
+      fp[t] = kRecords ? (uint64_t)cd.x : fingerprint(cd.x, cd.y);
     }
   }
   __syncthreads();
@@ -445,19 +453,19 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* 
   if (tid < ghere) {
     uint32_t st = 0;
     for (uint32_t q = 0; q < tid; q++) st += psize[q];
-    off[j0 + tid] = base + st;
+    off[j0 + tid] = kbase + base + st;
     nbk[j0 + tid] = nonempty[tid];
     atomicMax(&info[1], key[tid * nbpad] >> 16);
     atomicMax(&info[2], psize[tid]);
   }
-  if (tid == 0 && j0 + ghere == K) off[K] = base + ns;
+  if (tid == 0 && j0 + ghere == jend) off[jend] = kbase + base + ns;
   __syncthreads();
 #pragma unroll
   for (int t = 0; t < kItems; t++) {
     const uint32_t i = tid + t * kSegThreads;
     if (i < ns) {
       const uint32_t r = rec[i];
-      const uint64_t dest = base + cnt[(r >> 29) * nbpad + ((r >> 16) & 0x1FFF)] + (r & 0xFFFF);
+      const uint64_t dest = kbase + base + cnt[(r >> 29) * nbpad + ((r >> 16) & 0x1FFF)] + (r & 0xFFFF);
       sortedf[dest] = fp[t];
       if (dbg) dbg[dest] = codes[base + i];
     }
@@ -1130,16 +1138,16 @@ struct Timer {
 };
 
 void configure_pool_once() {
-  static bool done = false;
-  if (done) return;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return;
-  hipMemPool_t pool;
-  if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-    uint64_t thr = UINT64_MAX;
-    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-  }
-  done = true;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+      uint64_t thr = UINT64_MAX;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+  });
 }
 
 enum class Src { U64, Str };
@@ -1262,9 +1270,9 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
       hipLaunchKernelGGL(k_coarse_scatter<false>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, stage, n,
                          per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
     tm.mark();  // 3
-    hipLaunchKernelGGL(k_segment_sort, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st, codes, cbase,
-                       h->d_table, B, nbpad, (uint32_t)gshift, K, seg_cap, sortedf, blist, nbk, off, err,
-                       (ulonglong2*)part_codes_out);
+    hipLaunchKernelGGL(k_segment_sort<false>, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st, codes, cbase,
+                       h->d_table, B, nbpad, (uint32_t)gshift, K, (uint64_t)0, K, (uint64_t)0, seg_cap, sortedf,
+                       blist, nbk, off, err, (ulonglong2*)part_codes_out);
     if (an != ad) {
       PHOBIC_HIP(S.get(&toff, K + 1));
       hipLaunchKernelGGL(k_table_offsets, dim3(1), dim3(1024), 0, st, off, K, an, ad, toff, err, d64);
@@ -1420,32 +1428,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   const uint32_t woff = bit_length((uint64_t)(hmm[1] - hmm[0]));
   const uint64_t nremap = total - n;
   const uint32_t wremap = n > 1 ? bit_length(n - 1) : 0;
-  const uint64_t nvals = K * B;
-  const uint64_t nsel = rice ? (nvals + kSelEvery - 1) / kSelEvery : 0;
-  std::vector<uint64_t> hdr(kHeaderWords, 0);
-  hdr[kHMagic] = kMagic;
-  hdr[kHN] = n;
-  hdr[kHK] = K;
-  hdr[kHB] = B;
-  hdr[kHP] = prm.partition_size;
-  std::memcpy(&hdr[kHLambda], &prm.lambda, 8);
-  hdr[kHAlpha] = (uint64_t)an | ((uint64_t)ad << 32);
-  hdr[kHCoding] = prm.coding;
-  hdr[kHSeed] = prm.hash_seed;
-  hdr[kHTotal] = total;
-  hdr[kHDmin] = (uint64_t)dmin;
-  hdr[kHWoff] = woff;
-  hdr[kHSecOff] = kHeaderWords;
-  hdr[kHSecEnc] = hdr[kHSecOff] + ((K + 1) * woff + 63) / 64 + 1;
-  hdr[kHSecData] = hdr[kHSecEnc] + B + 1;
-  hdr[kHSecUnary] = hdr[kHSecData] + (data_bits + 63) / 64 + 1;
-  hdr[kHSecSel] = hdr[kHSecUnary] + (rice ? (unary_bits + 63) / 64 + 1 : 0);
-  hdr[kHSecRemap] = hdr[kHSecSel] + (rice ? (nsel + 1) / 2 + 1 : 0);
-  hdr[kHWremap] = wremap;
-  hdr[kHNremap] = nremap;
-  hdr[kHUbits] = rice ? unary_bits : 0;
-  hdr[kHWords] = hdr[kHSecRemap] + (nremap ? (nremap * wremap + 63) / 64 + 1 : 0);
-  hdr[kHR] = R;
+  const std::vector<uint64_t> hdr = make_header(n, K, B, prm, total, dmin, woff, data_bits, unary_bits, R);
   const uint64_t nwords = hdr[kHWords];
 
   PHOBIC_HIP(hipMallocAsync((void**)&h->d_image, nwords * sizeof(uint64_t), st));
@@ -1498,6 +1481,508 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   return PHOBIC_OK;
 }
 
+
+// ---------------------------------------------------------------------------------------------
+// Batched builds.  The partitions of all MPHFs form one global index space (MPHF t owns
+// [Kbase_t, Kbase_t + K_t)) and their keys one global key space (MPHF t owns
+// [nbase_t, nbase_t + n_t)).  Every per-partition step is the plain build's; only the mapping
+// from a key to its global partition and from a partition to its MPHF is new.
+// ---------------------------------------------------------------------------------------------
+struct BatchDesc {
+  const uint64_t* keys;
+  uint64_t n, K, Kbase, nbase, R;  // R = floor(n 2^32 / K), the offset expectation step
+};
+
+// the last MPHF t in [lo, hi) with nbase_t <= gi (empty MPHFs share nbase with their successor)
+__device__ __forceinline__ uint32_t batch_owner(const BatchDesc* __restrict__ d, uint32_t lo, uint32_t hi,
+                                                uint64_t gi) {
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (d[mid].nbase <= gi) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <bool kScatter>
+__global__ __launch_bounds__(kCoarseThreads) void k_batch_coarse(const BatchDesc* __restrict__ d, uint32_t t0,
+                                                                 uint32_t t1, uint64_t nb0, uint64_t nchunk,
+                                                                 uint64_t per, uint64_t seed, uint64_t Jc0,
+                                                                 uint32_t gshift, uint32_t C,
+                                                                 uint32_t* __restrict__ ccnt, uint32_t* __restrict__ hrow,
+                                                                 uint32_t* __restrict__ cur,
+                                                                 ulonglong2* __restrict__ codes) {
+  extern __shared__ __align__(16) uint32_t hist[];
+  const uint32_t tid = threadIdx.x;
+  if (kScatter) {
+    for (uint32_t x = tid; x < C; x += kCoarseThreads) {
+      const uint32_t v = hrow[(uint64_t)blockIdx.x * C + x];
+      hist[x] = v ? atomicAdd(&cur[x], v) : 0u;
+    }
+  } else {
+    for (uint32_t x = tid; x < C; x += kCoarseThreads) hist[x] = 0;
+  }
+  __syncthreads();
+  const uint64_t a = (uint64_t)blockIdx.x * per, b = min(nchunk, a + per);
+  uint64_t i = a + tid;
+  uint32_t t = i < b ? batch_owner(d, t0, t1, nb0 + i) : t0;
+  const uint64_t gmask = (1ULL << gshift) - 1;
+  for (; i < b; i += kCoarseThreads) {
+    const uint64_t gi = nb0 + i;
+    while (t + 1 < t1 && d[t + 1].nbase <= gi) t++;
+    const uint64_t key = d[t].keys[gi - d[t].nbase];
+    const uint64_t J = d[t].Kbase + __umul64hi(mix_a(key ^ seed), d[t].K);
+    const uint32_t bin = (uint32_t)((J - Jc0) >> gshift);
+    if (kScatter) {
+      uint64_t hi, lo;
+      hash_key_u64(key, seed, hi, lo);
+      codes[atomicAdd(&hist[bin], 1u)] = make_ulonglong2(fingerprint(hi, lo), (lo & ~7ULL) | ((J - Jc0) & gmask));
+    } else {
+      atomicAdd(&hist[bin], 1u);
+    }
+  }
+  if (!kScatter) {
+    __syncthreads();
+    for (uint32_t x = tid; x < C; x += kCoarseThreads) {
+      const uint32_t v = hist[x];
+      hrow[(uint64_t)blockIdx.x * C + x] = v;
+      if (v) atomicAdd(&ccnt[x], v);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_owner(const BatchDesc* __restrict__ d, uint32_t count, uint64_t Ktot,
+                                                        uint32_t* __restrict__ owner) {
+  for (uint64_t J = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; J < Ktot; J += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (d[mid].Kbase <= J) lo = mid; else hi = mid;
+    }
+    owner[J] = lo;
+  }
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint64_t)__shfl_xor(v, o));
+  return v;
+}
+
+// One wavefront per (MPHF t, encoder i): sum and maximum of the K_t pilots of bucket i.
+__global__ __launch_bounds__(256) void k_batch_stats(const uint32_t* __restrict__ pilots,
+                                                     const BatchDesc* __restrict__ d, uint32_t count, uint32_t B,
+                                                     uint64_t* __restrict__ sum, uint32_t* __restrict__ mx) {
+  const uint64_t item = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63;
+  if (item >= (uint64_t)count * B) return;
+  const uint32_t t = (uint32_t)(item / B), i = (uint32_t)(item % B);
+  const uint64_t K = d[t].K;
+  const uint32_t* col = pilots + (uint64_t)B * d[t].Kbase + (uint64_t)i * K;
+  uint64_t s = 0, m = 0;
+  for (uint64_t j = lane; j < K; j += 64) {
+    const uint64_t v = col[j];
+    s += v;
+    m = max(m, v);
+  }
+  s = wave_sum_u64(s);
+  m = wave_max_u64(m);
+  if (lane == 0) {
+    sum[item] = s;
+    mx[item] = (uint32_t)m;
+  }
+}
+
+// One wavefront per (t, i): bits of the unary stream, sum (v >> w) + K_t.
+__global__ __launch_bounds__(256) void k_batch_unary(const uint32_t* __restrict__ pilots,
+                                                     const BatchDesc* __restrict__ d, uint32_t count, uint32_t B,
+                                                     const uint8_t* __restrict__ width, uint64_t* __restrict__ ubits) {
+  const uint64_t item = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63;
+  if (item >= (uint64_t)count * B) return;
+  const uint32_t t = (uint32_t)(item / B), i = (uint32_t)(item % B);
+  const uint64_t K = d[t].K;
+  const uint32_t w = width[item];
+  const uint32_t* col = pilots + (uint64_t)B * d[t].Kbase + (uint64_t)i * K;
+  uint64_t s = 0;
+  for (uint64_t j = lane; j < K; j += 64) s += (uint64_t)col[j] >> w;
+  s = wave_sum_u64(s);
+  if (lane == 0) ubits[item] = s + K;
+}
+
+// One wavefront per MPHF: minimum and maximum offset residue.
+__global__ __launch_bounds__(256) void k_batch_offstats(const uint64_t* __restrict__ off,
+                                                        const BatchDesc* __restrict__ d, uint32_t count,
+                                                        long long* __restrict__ mm) {
+  const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (t >= count) return;
+  const BatchDesc e = d[t];
+  long long lmin = LLONG_MAX, lmax = LLONG_MIN;
+  for (uint64_t j = lane; j <= e.K; j += 64) {
+    const long long v = (long long)((off[e.Kbase + j] - e.nbase) - expected_offset(j, e.R));
+    lmin = min(lmin, v);
+    lmax = max(lmax, v);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lmin = min(lmin, (long long)__shfl_xor(lmin, o));
+    lmax = max(lmax, (long long)__shfl_xor(lmax, o));
+  }
+  if (lane == 0) {
+    mm[2 * t] = lmin;
+    mm[2 * t + 1] = lmax;
+  }
+}
+
+// One workgroup per MPHF: header and encoder words into its image.
+__global__ __launch_bounds__(256) void k_batch_heads(const uint64_t* __restrict__ hdrs, const uint64_t* __restrict__ encw,
+                                                     const uint64_t* __restrict__ ibase, uint32_t B,
+                                                     uint64_t* __restrict__ buf) {
+  const uint32_t t = blockIdx.x;
+  const uint64_t* h = hdrs + (uint64_t)t * kHeaderWords;
+  uint64_t* img = buf + ibase[t];
+  for (uint32_t x = threadIdx.x; x < kHeaderWords; x += blockDim.x) img[x] = h[x];
+  for (uint32_t x = threadIdx.x; x < B; x += blockDim.x) img[h[kHSecEnc] + x] = encw[(uint64_t)t * B + x];
+}
+
+// One wavefront per MPHF: offset residues into the OFF section.
+__global__ __launch_bounds__(256) void k_batch_pack_off(const uint64_t* __restrict__ off, const BatchDesc* __restrict__ d,
+                                                        uint32_t count, const uint64_t* __restrict__ hdrs,
+                                                        const uint64_t* __restrict__ ibase, uint64_t* __restrict__ buf) {
+  const uint32_t t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (t >= count) return;
+  const BatchDesc e = d[t];
+  const uint64_t* h = hdrs + (uint64_t)t * kHeaderWords;
+  const long long dmin = (long long)h[kHDmin];
+  const uint32_t woff = (uint32_t)h[kHWoff];
+  uint64_t* sec = buf + ibase[t] + h[kHSecOff];
+  for (uint64_t j = lane; j <= e.K; j += 64) {
+    const uint64_t u = (uint64_t)((long long)((off[e.Kbase + j] - e.nbase) - expected_offset(j, e.R)) - dmin);
+    put_bits_atomic(sec, j * woff, u, woff);
+  }
+}
+
+// One wavefront per (t, i): values (Compact) or low bits and unary stream with select samples (Rice).
+__global__ __launch_bounds__(256) void k_batch_pack_vals(const uint32_t* __restrict__ pilots,
+                                                         const BatchDesc* __restrict__ d, uint32_t count, uint32_t B,
+                                                         const uint64_t* __restrict__ hdrs,
+                                                         const uint64_t* __restrict__ encw,
+                                                         const uint64_t* __restrict__ ubase,
+                                                         const uint64_t* __restrict__ ibase, uint64_t* __restrict__ buf) {
+  const uint64_t item = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const uint32_t lane = threadIdx.x & 63;
+  if (item >= (uint64_t)count * B) return;
+  const uint32_t t = (uint32_t)(item / B), i = (uint32_t)(item % B);
+  const uint64_t K = d[t].K;
+  const uint64_t* h = hdrs + (uint64_t)t * kHeaderWords;
+  uint64_t* img = buf + ibase[t];
+  const bool rice = h[kHCoding] == PHOBIC_IC_RICE;
+  const uint64_t e = encw[item];
+  const uint32_t w = (uint32_t)(e & 0xFF);
+  const uint64_t base = e >> 8;
+  const uint32_t* col = pilots + (uint64_t)B * d[t].Kbase + (uint64_t)i * K;
+  uint64_t carry = rice ? ubase[item] : 0;
+  for (uint64_t j0 = 0; j0 < K; j0 += 64) {
+    const uint64_t j = j0 + lane;
+    const bool in = j < K;
+    const uint64_t v = in ? col[j] : 0;
+    put_bits_atomic(img + h[kHSecData], base + j * w, w >= 64 ? v : (v & ((1ULL << w) - 1)), in ? w : 0);
+    if (rice) {
+      const uint64_t len = in ? (v >> w) + 1 : 0;
+      uint64_t incl = len;
+      for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t y = __shfl_up(incl, o);
+        if (lane >= (uint32_t)o) incl += y;
+      }
+      if (in) {
+        const uint64_t pos = carry + incl - 1;  // this value's one
+        atomicOr((unsigned long long*)&img[h[kHSecUnary] + (pos >> 6)], 1ULL << (pos & 63));
+        const uint64_t tg = (uint64_t)i * K + j;
+        if ((tg & (kSelEvery - 1)) == 0) ((uint32_t*)(img + h[kHSecSel]))[tg / kSelEvery] = (uint32_t)pos;
+      }
+      carry += __shfl(incl, 63);
+    }
+  }
+}
+
+phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* counts, uint32_t count,
+                               const phobic_params* params, hipStream_t st, phobic_mphf** outs) {
+  uint32_t B = 0;
+  phobic_status vs = validate_params(params, &B);
+  if (vs != PHOBIC_OK) return vs;
+  const phobic_params& prm = *params;
+  if (prm.alpha_num != prm.alpha_den) return fail(PHOBIC_E_INVALID, "batched builds need alpha = 1");
+  if (B > kMaxBuckets) return fail(PHOBIC_E_CAPACITY, "B exceeds the device limit");
+  configure_pool_once();
+  const uint32_t nbpad = next_pow2(B);
+  int gshift = -1;
+  uint32_t seg_cap = 0;
+  for (int gs = 3; gs >= 0; gs--) {
+    const double gp = (double)(1u << gs) * prm.partition_size;
+    const int64_t cap = ((int64_t)kSegLdsBytes - 8 * (int64_t)(1u << gs) * nbpad) / 4;
+    if (cap > 0 && gp + 8.0 * std::sqrt(gp) + 64.0 <= (double)cap) {
+      gshift = gs;
+      seg_cap = (uint32_t)cap;
+      break;
+    }
+  }
+  if (gshift < 0) return fail(PHOBIC_E_CAPACITY, "partition_size too large for batched builds");
+  const uint64_t G = 1ULL << gshift;
+  uint64_t chunk_parts = (uint64_t)kMaxCoarse * G;
+  // PHOBIC_BATCH_CHUNK_PARTS lowers the partitions handled per chunk (tests use it to exercise
+  // several chunks with small batches); it never changes a result.
+  if (const char* env = std::getenv("PHOBIC_BATCH_CHUNK_PARTS")) {
+    const uint64_t v = std::strtoull(env, nullptr, 10);
+    if (v >= 1) chunk_parts = std::min<uint64_t>(chunk_parts, v);
+  }
+  const uint64_t limit = prm.pilot_limit ? prm.pilot_limit : 0xFFFFFFFFULL;
+
+  // host descriptors and chunks of whole MPHFs
+  std::vector<BatchDesc> desc(count);
+  std::vector<uint64_t> hKbase(count), hKt(count);
+  uint64_t Ktot = 0, Ntot = 0;
+  for (uint32_t t = 0; t < count; t++) {
+    const uint64_t n = counts[t];
+    if (n && !keys[t]) return fail(PHOBIC_E_INVALID, "MPHF " + std::to_string(t) + ": null key pointer");
+    const uint64_t K = num_partitions(n, prm.partition_size);
+    if (K > chunk_parts || n >= (1ULL << 31))
+      return fail(PHOBIC_E_CAPACITY, "MPHF " + std::to_string(t) + " is too large for a batch; build it alone");
+    desc[t] = BatchDesc{keys[t], n, K, Ktot, Ntot, (uint64_t)(((unsigned __int128)n << 32) / K)};
+    hKbase[t] = Ktot;
+    hKt[t] = K;
+    Ktot += K;
+    Ntot += n;
+  }
+  struct Chunk { uint32_t t0, t1; };
+  std::vector<Chunk> chunks;
+  for (uint32_t t = 0; t < count;) {
+    uint32_t u = t;
+    uint64_t kc = 0, nc = 0;
+    while (u < count && kc + desc[u].K <= chunk_parts && nc + desc[u].n < (1ULL << 31)) {
+      kc += desc[u].K;
+      nc += desc[u].n;
+      u++;
+    }
+    chunks.push_back({t, u});
+    t = u;
+  }
+  uint64_t max_chunk_keys = 0;
+  for (auto& c : chunks)
+    max_chunk_keys = std::max<uint64_t>(max_chunk_keys,
+                                        desc[c.t1 - 1].nbase + desc[c.t1 - 1].n - desc[c.t0].nbase);
+
+  int dev = 0;
+  PHOBIC_HIP(hipGetDevice(&dev));
+  phobic_mphf tbl;  // borrows the cached bucket-function table
+  tbl.device = dev;
+  tbl.prm = prm;
+  {
+    phobic_status ts = upload_table(&tbl, st);
+    if (ts != PHOBIC_OK) return ts;
+  }
+
+  Scratch S(st);
+  Timer tm(st);
+  auto t_host0 = std::chrono::steady_clock::now();
+  BatchDesc* d_desc;
+  uint64_t *fp, *off, *d_Kbase, *d_Kt, *cbase;
+  uint32_t *blist, *nbk, *pilots, *err, *owner, *ccnt, *hrow, *cur;
+  ulonglong2* codes;
+  unsigned long long* queue;
+  const uint32_t ngrp_max = kCoarseGroups;
+  PHOBIC_HIP(S.get(&d_desc, count));
+  PHOBIC_HIP(S.get(&fp, Ntot));
+  PHOBIC_HIP(S.get(&off, Ktot + 1));
+  PHOBIC_HIP(S.get(&d_Kbase, count));
+  PHOBIC_HIP(S.get(&d_Kt, count));
+  PHOBIC_HIP(S.get(&cbase, kMaxCoarse + 1));
+  PHOBIC_HIP(S.get(&blist, Ktot * B));
+  PHOBIC_HIP(S.get(&nbk, Ktot));
+  PHOBIC_HIP(S.get(&pilots, Ktot * B));
+  PHOBIC_HIP(S.get(&err, 4));
+  PHOBIC_HIP(S.get(&owner, Ktot));
+  PHOBIC_HIP(S.get(&ccnt, kMaxCoarse));
+  PHOBIC_HIP(S.get(&hrow, (uint64_t)ngrp_max * kMaxCoarse));
+  PHOBIC_HIP(S.get(&cur, kMaxCoarse));
+  PHOBIC_HIP(S.get(&codes, max_chunk_keys));
+  PHOBIC_HIP(S.get(&queue, 1));
+  PHOBIC_HIP(hipMemcpyAsync(d_desc, desc.data(), count * sizeof(BatchDesc), hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(d_Kbase, hKbase.data(), count * 8, hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(d_Kt, hKt.data(), count * 8, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(Ktot * B)), dim3(kBlock), 0, st, pilots, Ktot * B, 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err, (uint64_t)2, 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err + 2, (uint64_t)2, 0xFFFFFFFFu);
+
+  // a1-a4 chunk by chunk
+  tm.mark();  // 0
+  for (const Chunk& c : chunks) {
+    const uint64_t Jc0 = desc[c.t0].Kbase, Jc1 = desc[c.t1 - 1].Kbase + desc[c.t1 - 1].K;
+    const uint64_t nb0 = desc[c.t0].nbase, nchunk = desc[c.t1 - 1].nbase + desc[c.t1 - 1].n - nb0;
+    const uint64_t C = (Jc1 - Jc0 + G - 1) >> gshift;
+    const uint32_t ngrp = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ngrp_max, (nchunk + 4095) / 4096));
+    const uint64_t per = (nchunk + ngrp - 1) / ngrp;
+    const size_t hist_lds = C * sizeof(uint32_t);
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(C)), dim3(kBlock), 0, st, ccnt, C, 0u);
+    hipLaunchKernelGGL(k_batch_coarse<false>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, d_desc, c.t0, c.t1, nb0,
+                       nchunk, per, prm.hash_seed, Jc0, (uint32_t)gshift, (uint32_t)C, ccnt, hrow, cur, codes);
+    hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1024), 0, st, ccnt, (uint32_t)C, cbase, cur);
+    hipLaunchKernelGGL(k_batch_coarse<true>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, d_desc, c.t0, c.t1, nb0,
+                       nchunk, per, prm.hash_seed, Jc0, (uint32_t)gshift, (uint32_t)C, ccnt, hrow, cur, codes);
+    hipLaunchKernelGGL(k_segment_sort<true>, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st, codes, cbase,
+                       tbl.d_table, B, nbpad, (uint32_t)gshift, (uint64_t)0, Jc0, Jc1, nb0, seg_cap, fp, blist, nbk,
+                       off, err, (ulonglong2*)nullptr);
+    PHOBIC_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_batch_owner, dim3(grid_for(Ktot)), dim3(kBlock), 0, st, d_desc, count, Ktot, owner);
+  tm.mark();  // 1
+  uint32_t hinfo[4];
+  PHOBIC_HIP(hipMemcpyAsync(hinfo, err, sizeof(hinfo), hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipStreamSynchronize(st));
+  if (hinfo[0] & (1u << PHOBIC_E_CAPACITY))
+    return fail(PHOBIC_E_CAPACITY, "a group of partitions exceeds the LDS of the bucket-sort workgroup");
+
+  // a5: one search over every (MPHF, partition)
+  SearchArgs sa;
+  sa.fp = fp;
+  sa.off = off;
+  sa.toff = off;
+  sa.blist = blist;
+  sa.nbk = nbk;
+  sa.pilots = pilots;
+  sa.err = err;
+  sa.taken = nullptr;
+  sa.K = Ktot;
+  sa.limit = limit;
+  sa.B = B;
+  const uint32_t mm = std::max<uint32_t>(hinfo[2], 1), mb = std::max<uint32_t>(hinfo[1], 1);
+  auto up4 = [](uint32_t v) { return (v + 3) & ~3u; };
+  sa.f2_words = up4((2 * mm + 127) / 32 + 1);
+  sa.scr_words = up4((mm + 31) / 32 + 1);
+  sa.rb_cap = up4(mb) + 4;
+  sa.bl_cap = up4(B);
+  sa.cm_cap = (mb + 63) / 64 + 1;
+  sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
+  sa.owner = owner;
+  sa.Kbase = d_Kbase;
+  sa.Kt = d_Kt;
+  sa.fail_part_set = 1;
+  tm.mark();  // 2
+  PHOBIC_HIP(launch_search(sa, Ktot, st, queue));
+  tm.mark();  // 3
+
+  // a6: statistics, parameters on the host, then packing
+  const uint64_t items = (uint64_t)count * B;
+  uint64_t* sum;
+  uint32_t* mx;
+  long long* dmm;
+  PHOBIC_HIP(S.get(&sum, items));
+  PHOBIC_HIP(S.get(&mx, items));
+  PHOBIC_HIP(S.get(&dmm, 2 * (uint64_t)count));
+  const uint32_t item_groups = (uint32_t)((items + 3) / 4), mphf_groups = (count + 3) / 4;
+  hipLaunchKernelGGL(k_batch_stats, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, sum, mx);
+  hipLaunchKernelGGL(k_batch_offstats, dim3(mphf_groups), dim3(256), 0, st, off, d_desc, count, dmm);
+  PHOBIC_HIP(hipGetLastError());
+  std::vector<uint64_t> hsum(items);
+  std::vector<uint32_t> hmx(items);
+  std::vector<long long> hmm(2 * (size_t)count);
+  uint32_t herr[4];
+  PHOBIC_HIP(hipMemcpyAsync(hsum.data(), sum, items * 8, hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(hmx.data(), mx, items * 4, hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(hmm.data(), dmm, hmm.size() * 8, hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipStreamSynchronize(st));
+  if (herr[0] & ((1u << PHOBIC_E_DUPLICATE) | (1u << PHOBIC_E_PILOT_OVERFLOW))) {
+    const uint64_t J = (uint64_t)herr[2] | ((uint64_t)herr[3] << 32);
+    const uint32_t t = (uint32_t)(std::upper_bound(hKbase.begin(), hKbase.end(), J) - hKbase.begin()) - 1;
+    const bool dup = herr[0] & (1u << PHOBIC_E_DUPLICATE);
+    return fail(dup ? PHOBIC_E_DUPLICATE : PHOBIC_E_PILOT_OVERFLOW,
+                "MPHF " + std::to_string(t) + (dup ? ": two keys share their hash code" : ": pilot overflow"));
+  }
+  const bool rice = prm.coding == PHOBIC_IC_RICE;
+  std::vector<uint8_t> hw(items);
+  for (uint64_t it = 0; it < items; it++)
+    hw[it] = (uint8_t)(rice ? rice_parameter(hsum[it], desc[it / B].K) : bit_length(hmx[it]));
+  std::vector<uint64_t> hub(items, 0);
+  if (rice) {
+    uint8_t* dw;
+    uint64_t* dub;
+    PHOBIC_HIP(S.get(&dw, items));
+    PHOBIC_HIP(S.get(&dub, items));
+    PHOBIC_HIP(hipMemcpyAsync(dw, hw.data(), items, hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_batch_unary, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, dw, dub);
+    PHOBIC_HIP(hipMemcpyAsync(hub.data(), dub, items * 8, hipMemcpyDeviceToHost, st));
+    PHOBIC_HIP(hipStreamSynchronize(st));
+  }
+  std::vector<uint64_t> hdrs((size_t)count * kHeaderWords), encw(items), ubase(items), ibase(count);
+  uint64_t total_words = 0;
+  for (uint32_t t = 0; t < count; t++) {
+    uint64_t data_bits = 0, unary_bits = 0;
+    for (uint32_t i = 0; i < B; i++) {
+      const uint64_t it = (uint64_t)t * B + i;
+      encw[it] = (data_bits << 8) | hw[it];
+      data_bits += (uint64_t)hw[it] * desc[t].K;
+      ubase[it] = unary_bits;
+      unary_bits += hub[it];
+    }
+    if (rice && unary_bits > 0xFFFFFFFFULL) return fail(PHOBIC_E_CAPACITY, "a unary stream exceeds 2^32 bits");
+    const long long dmin = hmm[2 * t], dmax = hmm[2 * t + 1];
+    const std::vector<uint64_t> h = make_header(desc[t].n, desc[t].K, B, prm, desc[t].n, dmin,
+                                                bit_length((uint64_t)(dmax - dmin)), data_bits, unary_bits, desc[t].R);
+    std::copy(h.begin(), h.end(), hdrs.begin() + (size_t)t * kHeaderWords);
+    ibase[t] = total_words;
+    total_words += h[kHWords];
+  }
+  void* big = nullptr;
+  PHOBIC_HIP(hipMallocAsync(&big, total_words * 8, st));
+  std::shared_ptr<void> shared(big, [](void* p) { (void)hipFreeAsync(p, nullptr); });
+  uint64_t *dh, *de, *du, *dib;
+  PHOBIC_HIP(S.get(&dh, hdrs.size()));
+  PHOBIC_HIP(S.get(&de, items));
+  PHOBIC_HIP(S.get(&du, items));
+  PHOBIC_HIP(S.get(&dib, count));
+  PHOBIC_HIP(hipMemcpyAsync(dh, hdrs.data(), hdrs.size() * 8, hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(de, encw.data(), items * 8, hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(du, ubase.data(), items * 8, hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(dib, ibase.data(), count * 8, hipMemcpyHostToDevice, st));
+  uint64_t* bufw = (uint64_t*)big;
+  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(total_words)), dim3(kBlock), 0, st, bufw, total_words, (uint64_t)0);
+  hipLaunchKernelGGL(k_batch_heads, dim3(count), dim3(256), 0, st, dh, de, dib, B, bufw);
+  hipLaunchKernelGGL(k_batch_pack_off, dim3(mphf_groups), dim3(256), 0, st, off, d_desc, count, dh, dib, bufw);
+  hipLaunchKernelGGL(k_batch_pack_vals, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, dh, de, du,
+                     dib, bufw);
+  PHOBIC_HIP(hipGetLastError());
+  tm.mark();  // 4
+  PHOBIC_HIP(hipStreamSynchronize(st));
+  phobic_build_info info{};
+  info.bucket_sort_ms = tm.ms(0, 1);  // hashing, partitioning and bucketing of all chunks
+  info.search_ms = tm.ms(2, 3);
+  info.encode_ms = tm.ms(3, 4);
+  info.total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_host0).count();
+  info.max_partition_keys = hinfo[2];
+  info.max_bucket_keys = hinfo[1];
+
+  std::vector<phobic_mphf*> made(count, nullptr);
+  for (uint32_t t = 0; t < count; t++) {
+    phobic_mphf* h = new (std::nothrow) phobic_mphf();
+    if (!h) {
+      for (auto q : made) phobic_free(q);
+      return fail(PHOBIC_E_OOM, "host allocation");
+    }
+    h->device = dev;
+    h->n = desc[t].n;
+    h->K = desc[t].K;
+    h->B = B;
+    h->prm = prm;
+    h->d_table = tbl.d_table;
+    h->d_image = bufw + ibase[t];
+    h->header.assign(hdrs.begin() + (size_t)t * kHeaderWords, hdrs.begin() + (size_t)(t + 1) * kHeaderWords);
+    h->nwords = h->header[kHWords];
+    h->shared = shared;
+    h->info = info;
+    fill_query_args(h);
+    made[t] = h;
+  }
+  for (uint32_t t = 0; t < count; t++) outs[t] = made[t];
+  return PHOBIC_OK;
+}
+
 }  // namespace
 }  // namespace phobic
 
@@ -1541,4 +2026,13 @@ extern "C" phobic_status phobic_get_search_config(phobic_search_config* out) {
   if (!out) return fail(PHOBIC_E_INVALID, "out is null");
   *out = search_config();
   return PHOBIC_OK;
+}
+
+extern "C" phobic_status phobic_build_batch_u64(const uint64_t* const* h_key_ptrs, const uint64_t* h_counts,
+                                                uint32_t count, const phobic_params* params, void* hip_stream,
+                                                phobic_mphf** outs) {
+  if (count && (!outs || !h_key_ptrs || !h_counts)) return fail(PHOBIC_E_INVALID, "null argument");
+  for (uint32_t t = 0; t < count; t++) outs[t] = nullptr;
+  if (count == 0) return PHOBIC_OK;
+  return build_batch_impl(h_key_ptrs, h_counts, count, params, (hipStream_t)hip_stream, outs);
 }

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -57,6 +58,7 @@ struct phobic_mphf {
   uint32_t* d_pilots = nullptr;   // encoder-major (i * K + j), only with PHOBIC_FLAG_KEEP_PILOTS
   phobic_build_info info{};
   phobic::QueryArgs qa{};
+  std::shared_ptr<void> shared;   // set when d_image lives inside one allocation shared by a batch
 };
 
 namespace phobic {
@@ -80,6 +82,8 @@ uint64_t num_partitions(uint64_t n, uint32_t P);
 void bucket_table(double lambda, uint32_t P, uint32_t an, uint32_t ad, uint64_t* T);
 uint32_t rice_parameter(uint64_t sum, uint64_t count);
 phobic_status upload_table(phobic_mphf* h, hipStream_t st);
+std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phobic_params& prm, uint64_t total,
+                                  int64_t dmin, uint32_t woff, uint64_t data_bits, uint64_t unary_bits, uint64_t R);
 void fill_query_args(phobic_mphf* h);
 
 // ---------------------------------------------------------------------------------------------

@@ -8,6 +8,11 @@
 // dependent cache-line reads that mostly hit the L2 / Infinity Cache.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
 #include "phobic_internal.h"
 
 namespace phobic {
@@ -114,6 +119,40 @@ __global__ __launch_bounds__(kQBlock) void k_query_str(QueryArgs a, const uint8_
   }
 }
 
+// Several requests in one launch: blocks [bstart[r], bstart[r+1]) serve request r.
+struct QueryJob {
+  QueryArgs qa;
+  const uint64_t* keys;
+  uint64_t* out;
+  uint64_t n;
+};
+constexpr uint32_t kMultiItems = 4;
+
+__global__ __launch_bounds__(kQBlock) void k_query_multi(const QueryJob* __restrict__ jobs,
+                                                         const uint64_t* __restrict__ bstart, uint32_t count) {
+  __shared__ uint32_t sj;
+  if (threadIdx.x == 0) {
+    uint32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (bstart[mid] <= blockIdx.x) lo = mid; else hi = mid;
+    }
+    sj = lo;
+  }
+  __syncthreads();
+  const QueryJob& jb = jobs[sj];
+  const uint64_t first = (uint64_t)(blockIdx.x - bstart[sj]) * kQBlock * kMultiItems;
+#pragma unroll
+  for (uint32_t t = 0; t < kMultiItems; t++) {
+    const uint64_t x = first + t * kQBlock + threadIdx.x;
+    if (x < jb.n) {
+      uint64_t hi, lo;
+      hash_key_u64(jb.keys[x], jb.qa.seed, hi, lo);
+      jb.out[x] = query_code(jb.qa, hi, lo);
+    }
+  }
+}
+
 uint32_t query_grid(uint64_t n) {
   uint64_t g = (n + kQBlock - 1) / kQBlock;
   return (uint32_t)(g < 1 ? 1 : (g > 1048576 ? 1048576 : g));
@@ -143,5 +182,59 @@ extern "C" phobic_status phobic_query_str(const phobic_mphf* h, const uint8_t* d
   hipLaunchKernelGGL(k_query_str, dim3(query_grid(n)), dim3(kQBlock), 0, (hipStream_t)hip_stream, h->qa, d_bytes,
                      d_offsets, n, d_pos);
   PHOBIC_HIP(hipGetLastError());
+  return PHOBIC_OK;
+}
+
+extern "C" phobic_status phobic_query_multi_u64(const phobic_mphf* const* h_handles, const uint64_t* const* h_keys,
+                                                const uint64_t* h_counts, uint64_t* const* h_outs, uint32_t count,
+                                                void* hip_stream) {
+  if (count == 0) return PHOBIC_OK;
+  if (!h_handles || !h_keys || !h_counts || !h_outs) return fail(PHOBIC_E_INVALID, "null argument");
+  std::vector<QueryJob> jobs;
+  std::vector<uint64_t> bstart;
+  uint64_t blocks = 0;
+  for (uint32_t r = 0; r < count; r++) {
+    if (!h_handles[r]) return fail(PHOBIC_E_INVALID, "null handle in request " + std::to_string(r));
+    const uint64_t n = h_counts[r];
+    if (n == 0) continue;
+    if (!h_keys[r] || !h_outs[r]) return fail(PHOBIC_E_INVALID, "null pointer in request " + std::to_string(r));
+    jobs.push_back(QueryJob{h_handles[r]->qa, h_keys[r], h_outs[r], n});
+    bstart.push_back(blocks);
+    blocks += (n + (uint64_t)kQBlock * kMultiItems - 1) / ((uint64_t)kQBlock * kMultiItems);
+  }
+  if (jobs.empty()) return PHOBIC_OK;
+  if (blocks > 0x7FFFFFFFULL) return fail(PHOBIC_E_INVALID, "too many keys in one call");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const size_t jbytes = jobs.size() * sizeof(QueryJob), bbytes = bstart.size() * sizeof(uint64_t);
+  // per-thread pinned staging; the event of its last copy guards reuse
+  struct Staging {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+  };
+  thread_local Staging stg;
+  if (!stg.ev) PHOBIC_HIP(hipEventCreateWithFlags(&stg.ev, hipEventDisableTiming));
+  PHOBIC_HIP(hipEventSynchronize(stg.ev));
+  if (stg.cap < jbytes + bbytes) {
+    if (stg.p) (void)hipHostFree(stg.p);
+    stg.p = nullptr;
+    stg.cap = 0;
+    const size_t cap = std::max<size_t>(jbytes + bbytes, 1 << 16);
+    PHOBIC_HIP(hipHostMalloc(&stg.p, cap, hipHostMallocDefault));
+    stg.cap = cap;
+  }
+  std::memcpy(stg.p, jobs.data(), jbytes);
+  std::memcpy((char*)stg.p + jbytes, bstart.data(), bbytes);
+  void* dbuf = nullptr;
+  PHOBIC_HIP(hipMallocAsync(&dbuf, jbytes + bbytes, st));
+  hipError_t e = hipMemcpyAsync(dbuf, stg.p, jbytes + bbytes, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(stg.ev, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_query_multi, dim3((uint32_t)blocks), dim3(kQBlock), 0, st, (const QueryJob*)dbuf,
+                       (const uint64_t*)((char*)dbuf + jbytes), (uint32_t)jobs.size());
+    e = hipGetLastError();
+  }
+  (void)hipFreeAsync(dbuf, st);
+  if (e != hipSuccess) return fail(PHOBIC_E_DEVICE, std::string("query_multi: ") + hipGetErrorString(e));
   return PHOBIC_OK;
 }

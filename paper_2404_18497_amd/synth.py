@@ -42,6 +42,24 @@ def u64_keys(n: int, seed: int) -> np.ndarray:
         keys = np.concatenate([kept, extra])
 
 
+def u64_key_sets(sizes, base_seed: int) -> list:
+    """One key set per size, set t drawn from PCG64 default_rng(base_seed + t) (uniform uint64).
+    Not deduplicated: the chance that any set of the 4096-set batched workload holds a repeated key
+    is below 1e-5, and a repeat would surface as a DUPLICATE status of that build."""
+    return [np.random.default_rng(base_seed + t).bit_generator.random_raw(int(n)).astype(np.uint64, copy=False)
+            for t, n in enumerate(sizes)]
+
+
+def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process with the given rate."""
+    return np.cumsum(np.random.default_rng(seed).exponential(1.0 / rate, count))
+
+
+def log_uniform_sizes(count: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), count))).astype(np.int64)
+
+
 def query_indices(n_keys: int, n_queries: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.integers(0, n_keys, size=n_queries, dtype=np.int64)

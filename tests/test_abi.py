@@ -70,3 +70,30 @@ def test_header_and_oracle_agree_on_status_codes():
     for code, name in oracle.STATUS.items():
         key = "OK" if name == "OK" else "E_" + name
         assert codes[key] == code
+
+
+def test_search_config_validation(lib):
+    from paper_2404_18497_amd import binding
+
+    before = binding.get_search_config()
+    for bad in [dict(waves_per_group=3), dict(waves_per_group=16), dict(groups_per_cu=65),
+                dict(groups_per_cu=2, items_per_grab=0)]:
+        with pytest.raises(binding.PhobicError):
+            binding.set_search_config(**bad)
+    binding.set_search_config(waves_per_group=2, groups_per_cu=4, items_per_grab=8)
+    assert binding.get_search_config() == {"waves_per_group": 2, "groups_per_cu": 4, "items_per_grab": 8}
+    binding.set_search_config(**before)
+
+
+def test_batch_rejects_bad_arguments_on_host(lib):
+    from paper_2404_18497_amd import binding
+
+    outs = (C.c_void_p * 2)()
+    ptrs = (C.c_void_p * 2)(None, None)
+    counts = (C.c_uint64 * 2)(5, 0)
+    p = binding.params()
+    assert lib.phobic_build_batch_u64(ptrs, counts, 2, C.byref(p), None, outs) == binding.E_INVALID
+    q = binding.params(alpha=(99, 100))
+    counts0 = (C.c_uint64 * 2)(0, 0)
+    assert lib.phobic_build_batch_u64(ptrs, counts0, 2, C.byref(q), None, outs) == binding.E_INVALID
+    assert not outs[0] and not outs[1]

@@ -232,3 +232,62 @@ def test_full_size_100m_sampled(torch):
     bits = g.size_bits() / n
     _say("100M keys: bits/key", bits)
     assert 1.75 < bits < 1.9
+
+
+BATCH_SIZES = [0, 1, 2, 5, 63, 2500, 2501, 10_007, 50_000, 123_456, 7, 300_000, 1, 0, 40_000]
+
+
+@pytest.mark.parametrize("coding,lam", [("rice", 7.0), ("compact", 5.0)])
+def test_batch_matches_plain_builds(torch, monkeypatch, coding, lam):
+    keysets = [synth.u64_keys(n, 900 + i) for i, n in enumerate(BATCH_SIZES)]
+    dev = [_dev(torch, k) for k in keysets]
+    prm = binding.params(lam=lam, coding=coding)
+    plain = [binding.build_u64(d, prm).serialize() for d in dev]
+    before = binding.get_search_config()
+    shapes = [dict(waves_per_group=4, groups_per_cu=0, items_per_grab=1),
+              dict(waves_per_group=1, groups_per_cu=2, items_per_grab=4),
+              dict(waves_per_group=8, groups_per_cu=1, items_per_grab=1)]
+    try:
+        for chunk, shape in [(None, shapes[0]), ("130", shapes[1]), ("400", shapes[2])]:
+            _say("batch", coding, chunk, shape)
+            if chunk:
+                monkeypatch.setenv("PHOBIC_BATCH_CHUNK_PARTS", chunk)
+            else:
+                monkeypatch.delenv("PHOBIC_BATCH_CHUNK_PARTS", raising=False)
+            binding.set_search_config(**shape)
+            hs = binding.build_batch_u64(dev, prm)
+            for t, (k, h, d) in enumerate(zip(keysets, hs, dev)):
+                assert np.array_equal(h.serialize(), plain[t]), f"member {t} (n={k.size})"
+                if k.size:
+                    pos = h.query_u64(d).cpu().numpy().view(np.uint64)
+                    assert np.array_equal(np.sort(pos), np.arange(k.size, dtype=np.uint64))
+            del hs
+    finally:
+        binding.set_search_config(**before)
+    for t in (3, 8):
+        r = oracle.build_u64(keysets[t], oracle.params(lam=lam, coding=coding))
+        assert np.array_equal(plain[t], r.image())
+
+
+def test_batch_reports_the_failing_member(torch):
+    a = synth.u64_keys(5000, 1)
+    b = synth.u64_keys(3000, 2)
+    bad = np.concatenate([b, b[10:11]])
+    with pytest.raises(binding.PhobicError) as e:
+        binding.build_batch_u64([_dev(torch, a), _dev(torch, bad), _dev(torch, a)], binding.params())
+    assert e.value.code == binding.E_DUPLICATE and "MPHF 1" in str(e.value)
+
+
+def test_search_shapes_do_not_change_results(torch):
+    keys = synth.u64_keys(400_000, 17)
+    dk = _dev(torch, keys)
+    prm = binding.params(lam=8.0)
+    ref = binding.build_u64(dk, prm).serialize()
+    before = binding.get_search_config()
+    try:
+        for w in (1, 2, 4, 8):
+            for g, grab in [(0, 1), (1, 1), (4, 16)]:
+                binding.set_search_config(waves_per_group=w, groups_per_cu=g, items_per_grab=grab)
+                assert np.array_equal(binding.build_u64(dk, prm).serialize(), ref), (w, g, grab)
+    finally:
+        binding.set_search_config(**before)

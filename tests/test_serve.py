@@ -1,0 +1,136 @@
+"""Serving loop and multi-request queries on the GPU: results are the same alone and in the mix.
+
+A request served alone (one worker, no batching, submitted only after the previous one completed)
+and the same request served in a mix (several workers, queries coalesced into one launch, builds
+coalesced into batched builds, everything submitted at once) must give identical MPHF images and
+identical positions, and both must equal the plain library calls.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2404_18497_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    assert torch.cuda.is_available()
+    binding.lib()
+    return torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+
+
+def test_query_multi_matches_single_queries(torch):
+    prm = binding.params(lam=6.0)
+    sets = [synth.u64_keys(n, 40 + n) for n in (1000, 50_000, 7, 250_000)]
+    hs = [binding.build_u64(_dev(torch, k), prm) for k in sets]
+    rng = np.random.default_rng(3)
+    reqs = []
+    for r in range(12):
+        t = int(rng.integers(0, len(sets)))
+        q = sets[t][rng.integers(0, sets[t].size, int(rng.integers(0, 30_000)))]
+        reqs.append((t, _dev(torch, q)))
+    outs = [torch.empty(q.numel(), dtype=torch.int64, device="cuda") for _, q in reqs]
+    binding.query_multi_u64([hs[t] for t, _ in reqs], [q for _, q in reqs], outs)
+    for (t, q), o in zip(reqs, outs):
+        assert torch.equal(o, hs[t].query_u64(q))
+
+
+def _trace(seed, nbuild=10, nquery=60):
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in np.clip(rng.lognormal(np.log(20_000), 1.2, nbuild), 1, 400_000)]
+    keysets = [synth.u64_keys(n, 7000 + i) for i, n in enumerate(sizes)]
+    queries = []
+    for q in range(nquery):
+        b = int(rng.integers(0, nbuild))
+        m = int(rng.integers(1, 20_000))
+        queries.append((b, keysets[b][rng.integers(0, keysets[b].size, m)]))
+    return keysets, queries
+
+
+def _run(torch, keysets, queries, workers, qb, bb, alone):
+    prm = binding.params(lam=7.0)
+    srv = binding.Server(prm, budget_bytes=8 << 30, workers=workers, max_query_batch=qb, max_build_batch=bb)
+    dk = [_dev(torch, k) for k in keysets]
+    dq = [(b, _dev(torch, q)) for b, q in queries]
+    outs = [torch.full((q.numel(),), -1, dtype=torch.int64, device="cuda") for _, q in dq]
+    ids, results = [], {}
+
+    def drain(block):
+        for r in srv.poll(wait_ms=200 if block else 0):
+            results[r["request_id"]] = r
+
+    for k in dk:
+        ids.append(srv.submit_build(k))
+        if alone:
+            while ids[-1] not in results:
+                drain(True)
+    qids = []
+    for (b, q), o in zip(dq, outs):
+        qids.append(srv.submit_query(ids[b], q, o))
+        if alone:
+            while qids[-1] not in results:
+                drain(True)
+    while len(results) < len(ids) + len(qids):
+        drain(True)
+    assert all(results[i]["status"] == 0 for i in ids + qids)
+    images = [srv.mphf(i).serialize() for i in ids]
+    pos = [o.cpu().numpy() for o in outs]
+    batches = max(r["batch"] for r in results.values())
+    stats = srv.stats()
+    srv.close()
+    return images, pos, batches, stats
+
+
+def test_server_same_alone_and_in_the_mix(torch):
+    keysets, queries = _trace(1)
+    _say("alone")
+    img_a, pos_a, batch_a, _ = _run(torch, keysets, queries, workers=1, qb=1, bb=1, alone=True)
+    _say("mix")
+    img_m, pos_m, batch_m, stats = _run(torch, keysets, queries, workers=4, qb=16, bb=4, alone=False)
+    assert batch_a == 1 and batch_m > 1  # the mix really batched
+    prm = binding.params(lam=7.0)
+    for k, a, m in zip(keysets, img_a, img_m):
+        plain = binding.build_u64(_dev(torch, k), prm).serialize()
+        assert np.array_equal(a, plain) and np.array_equal(m, plain)
+    for a, m in zip(pos_a, pos_m):
+        assert np.array_equal(a, m) and a.min() >= 0
+    assert stats["resident_mphfs"] == len(keysets)
+
+
+def test_server_budget_admission(torch):
+    prm = binding.params(lam=7.0)
+    keys = [_dev(torch, synth.u64_keys(200_000, 60 + i)) for i in range(4)]
+    est = 32 * 200_000 + (64 << 20)
+    # room for exactly one build in flight: all succeed, never two at once
+    srv = binding.Server(prm, budget_bytes=est + est // 2, workers=4, max_query_batch=8, max_build_batch=4)
+    ids = [srv.submit_build(k) for k in keys]
+    got = {}
+    while len(got) < len(ids):
+        for r in srv.poll(wait_ms=200):
+            got[r["request_id"]] = r
+    assert all(got[i]["status"] == 0 for i in ids)
+    st = srv.stats()
+    assert st["peak_bytes"] <= est + est // 2 and st["build_launches"] == 4
+    # a build that can never fit is refused at once
+    big = srv.submit_build(_dev(torch, synth.u64_keys(3_000_000, 99)))
+    r = srv.poll(wait_ms=1000)
+    assert r and r[0]["request_id"] == big and r[0]["status"] == binding.E_OOM
+    with pytest.raises(binding.PhobicError):
+        srv.submit_query(big, keys[0], torch.empty(200_000, dtype=torch.int64, device="cuda"))
+    srv.release(ids[0])
+    assert srv.stats()["resident_mphfs"] == 3
+    with pytest.raises(binding.PhobicError):
+        srv.submit_query(ids[0], keys[0], torch.empty(200_000, dtype=torch.int64, device="cuda"))
+    srv.close()
