@@ -15,6 +15,10 @@
     MPHFs) under a 200 GB HBM budget; the library's server with continuous batching versus plain
     per-request FIFO execution, at the same arrival trace. ``value`` = p99 query latency (ms).
 
+--workload copy: a plain 1 GiB device-to-device copy, repeated; the reference kernel whose HBM counter
+    readings (FETCH_SIZE, WRITE_SIZE) calibrate the traffic figures of the other kernels, and a
+    measured copy bandwidth next to the 8 TB/s peak.
+
 Each mode prints one JSON line.
 """
 
@@ -42,7 +46,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="build_query", choices=["build_query", "batch", "serve"])
+    ap.add_argument("--workload", default="build_query", choices=["build_query", "batch", "serve", "copy"])
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--lam", type=float, default=7.0)
     ap.add_argument("--coding", default="rice", choices=["rice", "compact"])
@@ -345,6 +349,32 @@ def serve_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def copy_mode(args):
+    import torch
+
+    torch.cuda.set_device(0)
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(args.steps):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / args.steps
+    gbs = 2.0 * nbytes / (ms * 1e-3) / 1e9
+    out = {"metric": "device copy GB/s (read + write)", "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "1 GiB device-to-device copy", "bytes_read": nbytes, "bytes_written": nbytes},
+           "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -352,7 +382,7 @@ def main():
         print("bench.py runs on one GPU: this library has no multi-GPU path (how it would shard is described "
               "in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
-    {"build_query": headline, "batch": batch_mode, "serve": serve_mode}[args.workload](args)
+    {"build_query": headline, "batch": batch_mode, "serve": serve_mode, "copy": copy_mode}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -561,7 +561,7 @@ struct SearchArgs {
   // persistent launch: partitions are taken grab at a time from *queue; null = one per wavefront
   unsigned long long* queue;
   uint32_t grab;
-  uint32_t fail_part_set;  // nonzero: err[2..3] receive the lowest failing partition index
+  unsigned long long* fail_part;  // non-null: receives the lowest failing partition index (atomic min)
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -642,7 +642,7 @@ __device__ __forceinline__ uint32_t bucket_positions(uint32_t* rbuf, const uint6
 
 __device__ __forceinline__ void note_failure(const SearchArgs& a, uint64_t j, uint32_t status) {
   atomicOr(a.err, 1u << status);
-  if (a.fail_part_set) atomicMin((unsigned long long*)(a.err + 2), (unsigned long long)j);
+  if (a.fail_part) atomicMin(a.fail_part, (unsigned long long)j);
 }
 
 // Places every bucket of partition j (global index).  Uniform across the wavefront.
@@ -1053,6 +1053,7 @@ template <int W>
 hipError_t launch_search_w(SearchArgs& sa, uint64_t items, const phobic_search_config& cfg, hipStream_t st,
                            unsigned long long* queue) {
   const size_t lds = (size_t)sa.wave_lds * W;
+  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   if (cfg.groups_per_cu == 0) {
     sa.queue = nullptr;
     hipLaunchKernelGGL(k_search<W>, dim3((uint32_t)((items + W - 1) / W)), dim3(64 * W), lds, st, sa);
@@ -1377,7 +1378,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   sa.owner = nullptr;
   sa.Kbase = nullptr;
   sa.Kt = nullptr;
-  sa.fail_part_set = 0;
+  sa.fail_part = nullptr;
   unsigned long long* queue;
   PHOBIC_HIP(S.get(&queue, 1));
   tm.mark();  // 5
@@ -1796,7 +1797,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   PHOBIC_HIP(S.get(&blist, Ktot * B));
   PHOBIC_HIP(S.get(&nbk, Ktot));
   PHOBIC_HIP(S.get(&pilots, Ktot * B));
-  PHOBIC_HIP(S.get(&err, 4));
+  PHOBIC_HIP(S.get(&err, 6));
   PHOBIC_HIP(S.get(&owner, Ktot));
   PHOBIC_HIP(S.get(&ccnt, kMaxCoarse));
   PHOBIC_HIP(S.get(&hrow, (uint64_t)ngrp_max * kMaxCoarse));
@@ -1807,8 +1808,9 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   PHOBIC_HIP(hipMemcpyAsync(d_Kbase, hKbase.data(), count * 8, hipMemcpyHostToDevice, st));
   PHOBIC_HIP(hipMemcpyAsync(d_Kt, hKt.data(), count * 8, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(Ktot * B)), dim3(kBlock), 0, st, pilots, Ktot * B, 0u);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err, (uint64_t)2, 0u);
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err + 2, (uint64_t)2, 0xFFFFFFFFu);
+  // err[0] error bits, [1] max bucket, [2] max n_j, [3] max m_j; err[4..5] the lowest failing partition
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err, (uint64_t)4, 0u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err + 4, (uint64_t)2, 0xFFFFFFFFu);
 
   // a1-a4 chunk by chunk
   tm.mark();  // 0
@@ -1837,6 +1839,9 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   PHOBIC_HIP(hipStreamSynchronize(st));
   if (hinfo[0] & (1u << PHOBIC_E_CAPACITY))
     return fail(PHOBIC_E_CAPACITY, "a group of partitions exceeds the LDS of the bucket-sort workgroup");
+  if (hinfo[2] > kMaxTableSlots)
+    return fail(PHOBIC_E_CAPACITY, "a partition holds " + std::to_string(hinfo[2]) + " keys; the device path holds " +
+                                       std::to_string(kMaxTableSlots));
 
   // a5: one search over every (MPHF, partition)
   SearchArgs sa;
@@ -1862,7 +1867,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   sa.owner = owner;
   sa.Kbase = d_Kbase;
   sa.Kt = d_Kt;
-  sa.fail_part_set = 1;
+  sa.fail_part = (unsigned long long*)(err + 4);
   tm.mark();  // 2
   PHOBIC_HIP(launch_search(sa, Ktot, st, queue));
   tm.mark();  // 3
@@ -1882,14 +1887,14 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   std::vector<uint64_t> hsum(items);
   std::vector<uint32_t> hmx(items);
   std::vector<long long> hmm(2 * (size_t)count);
-  uint32_t herr[4];
+  uint32_t herr[6];
   PHOBIC_HIP(hipMemcpyAsync(hsum.data(), sum, items * 8, hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipMemcpyAsync(hmx.data(), mx, items * 4, hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipMemcpyAsync(hmm.data(), dmm, hmm.size() * 8, hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipStreamSynchronize(st));
   if (herr[0] & ((1u << PHOBIC_E_DUPLICATE) | (1u << PHOBIC_E_PILOT_OVERFLOW))) {
-    const uint64_t J = (uint64_t)herr[2] | ((uint64_t)herr[3] << 32);
+    const uint64_t J = (uint64_t)herr[4] | ((uint64_t)herr[5] << 32);
     const uint32_t t = (uint32_t)(std::upper_bound(hKbase.begin(), hKbase.end(), J) - hKbase.begin()) - 1;
     const bool dup = herr[0] & (1u << PHOBIC_E_DUPLICATE);
     return fail(dup ? PHOBIC_E_DUPLICATE : PHOBIC_E_PILOT_OVERFLOW,
