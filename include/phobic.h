@@ -206,7 +206,9 @@ phobic_status phobic_server_create(const phobic_server_config* cfg, const phobic
  * queries against it may be queued before it completes (they wait for it). */
 phobic_status phobic_server_submit_build(phobic_server* s, const uint64_t* d_keys, uint64_t n,
                                          uint64_t* request_id);
-/* Queues a query of the n keys at d_keys against MPHF mphf_id; positions go to d_pos. */
+/* Queues a query of the n keys at d_keys against MPHF mphf_id; positions go to d_pos.  Fails at
+ * once (PHOBIC_E_INVALID) for an unknown or released MPHF and for one whose build has already
+ * failed; a query queued before its build fails completes with status PHOBIC_E_INVALID. */
 phobic_status phobic_server_submit_query(phobic_server* s, uint64_t mphf_id, const uint64_t* d_keys, uint64_t n,
                                          uint64_t* d_pos, uint64_t* request_id);
 /* Moves up to cap completed results into out (completion order); waits up to wait_ms for one. */

@@ -308,6 +308,10 @@ extern "C" phobic_status phobic_server_submit_query(phobic_server* s, uint64_t m
       delete r;
       return fail(PHOBIC_E_INVALID, "unknown or released MPHF " + std::to_string(mphf_id));
     }
+    if (m->second.failed) {
+      delete r;
+      return fail(PHOBIC_E_INVALID, "the build of MPHF " + std::to_string(mphf_id) + " failed");
+    }
     m->second.users++;
     r->id = s->next_id++;
     r->submit = s->now();
