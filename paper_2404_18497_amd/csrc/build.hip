@@ -569,6 +569,17 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Values that are the same on every lane of the wavefront, moved to scalar registers so that the
+// branches and loops that depend on them are scalar branches instead of exec-mask updates.
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t lane_value64(uint64_t v, uint32_t lane) {
+  return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), lane) << 32) |
+         __builtin_amdgcn_readlane((uint32_t)v, lane);
+}
+
 __device__ __forceinline__ uint32_t enc_pos(uint32_t r) { return ((r >> 5) << 7) | (r & 31); }
 __device__ __forceinline__ uint32_t dec_pos(uint32_t e) { return ((e >> 7) << 5) | (e & 31); }
 
@@ -632,7 +643,7 @@ __device__ __forceinline__ uint32_t bucket_positions(uint32_t* rbuf, const uint6
     }
     if (g == 0) r0 = r;
     if (g == ng - 1) {
-      const uint32_t last = __shfl(r, (int)((sz - 1) & 63));
+      const uint32_t last = __builtin_amdgcn_readlane(r, (sz - 1) & 63);
       if (k >= sz && k < szp) rbuf[k] = enc_pos(last);
     }
   }
@@ -652,21 +663,26 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   uint32_t* bl = rbuf + a.rb_cap;
   uint64_t* cm = (uint64_t*)(bl + a.bl_cap);
 
-  const uint64_t kb = a.off[j];
-  const uint32_t m = (uint32_t)(a.toff[j + 1] - a.toff[j]);
+  const uint64_t kb = uniform64(a.off[j]);
+  const uint32_t m = uniform((uint32_t)(a.toff[j + 1] - a.toff[j]));
   const uint32_t twom = 2 * m;
   for (uint32_t w = lane; w < a.f2_words; w += 64) {
     const uint32_t lo = w * 32;
     F2[w] = lo + 32 <= twom ? 0xFFFFFFFFu : (lo >= twom ? 0u : ((1u << (twom - lo)) - 1u));
   }
   for (uint32_t w = lane; w < a.scr_words; w += 64) scr[w] = 0;
-  const uint32_t nb = a.nbk[j];
+  const uint32_t nb = uniform(a.nbk[j]);
   for (uint32_t x = lane; x < nb; x += 64) bl[x] = a.blist[j * a.B + x];
   wave_sync();
   const char* F2b = (const char*)F2;
 
+  // this lane's displacement window of the first pass (d0 = 0): its bits below m, its byte offset
+  const uint32_t dl0 = lane * 64;
+  const uint64_t acc_first = dl0 < m ? (m - dl0 >= 64 ? ~0ULL : ((1ULL << (m - dl0)) - 1)) : 0ULL;
+  const uint32_t loff_first = dl0 < m ? (dl0 >> 3) : 0u;
+
   uint64_t kpos = kb;
-  uint32_t e = nb ? bl[0] : 0;
+  uint32_t e = nb ? uniform(bl[0]) : 0;
   uint64_t fnext = lane < (e >> 16) ? a.fp[kpos + lane] : 0;
   bool overflow = false;
   for (uint32_t r = 0; r < nb; r++) {
@@ -675,7 +691,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
     const uint64_t f0 = fnext;
     kpos += sz;
     if (r + 1 < nb) {  // prefetch the next bucket's first 64 fingerprints
-      e = bl[r + 1];
+      e = uniform(bl[r + 1]);
       fnext = lane < (e >> 16) ? a.fp[kpos + lane] : 0;
     }
     const bool big = sz > kSmallBucket;
@@ -707,10 +723,14 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       // displacement scan: the lowest d such that every key's slot (r + d) mod m is free
       uint32_t d_found = 0xFFFFFFFFu;
       for (uint32_t d0 = 0; d0 < m; d0 += 4096) {
-        const uint32_t dl = d0 + lane * 64;
-        const bool act = dl < m;
-        uint64_t acc = act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL;
-        const uint32_t loff = act ? (dl >> 3) : 0u;  // byte offset of this lane's window start
+        uint64_t acc = acc_first;
+        uint32_t loff = loff_first;  // byte offset of this lane's window start
+        if (d0) {
+          const uint32_t dl = d0 + dl0;
+          const bool act = dl < m;
+          acc = act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL;
+          loff = act ? (dl >> 3) : 0u;
+        }
         for (uint32_t k = 0; k < szp; k += 4) {
           const uint4 e4 = *(const uint4*)(rbuf + k);
           const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
@@ -726,7 +746,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         const uint64_t bal = __ballot(acc != 0);
         if (bal) {
           const uint32_t L = (uint32_t)(__ffsll((long long)bal) - 1);
-          const uint64_t accL = __shfl(acc, (int)L);
+          const uint64_t accL = lane_value64(acc, L);
           d_found = d0 + L * 64 + (uint32_t)(__ffsll((long long)accL) - 1);
           break;
         }
@@ -797,7 +817,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
 template <int kWaves>
 __global__ __launch_bounds__(64 * kWaves) void k_search(SearchArgs a) {
   extern __shared__ __align__(16) uint32_t lds32[];
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const uint64_t j = (uint64_t)blockIdx.x * kWaves + wave;
   if (j >= a.K) return;
   search_partition(a, j, lds32 + (size_t)wave * (a.wave_lds / 4), lane);
@@ -807,12 +827,12 @@ __global__ __launch_bounds__(64 * kWaves) void k_search(SearchArgs a) {
 template <int kWaves>
 __global__ __launch_bounds__(64 * kWaves) void k_search_persistent(SearchArgs a) {
   extern __shared__ __align__(16) uint32_t lds32[];
-  const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   uint32_t* F2 = lds32 + (size_t)wave * (a.wave_lds / 4);
   for (;;) {
     unsigned long long item = 0;
     if (lane == 0) item = atomicAdd(a.queue, (unsigned long long)a.grab);
-    item = __shfl(item, 0);
+    item = lane_value64(item, 0);
     if (item >= a.K) break;
     const uint64_t end = min((uint64_t)item + a.grab, a.K);
     for (uint64_t j = item; j < end; j++) {
@@ -888,8 +908,36 @@ __global__ __launch_bounds__(kBlock) void k_pack_offsets(const uint64_t* __restr
 // One workgroup of 1024 threads per encoder i: low bits (or Compact values) at base_i + j w_i; for
 // Rice the unary stream of q = v >> w_i (q zeros then a one), whose one for value t = i K + j sits at
 // ubase_i + sum_{j' < j} (q_j' + 1) + q_j, and a select sample for every 256th one.
+//
+// Values go through in chunks of 4096.  A chunk's low bits (at most 4096 x 32 bits) and, when they
+// fit, its unary bits are assembled in LDS and written out as whole words: plain stores for the
+// words only this chunk touches, an atomic OR for its first and last word, which a neighbouring
+// chunk or encoder may share.  A chunk whose unary run is too long for the buffer (a few huge
+// pilots) sets its ones in global memory directly.
 constexpr int kPackThreads = 1024;
 constexpr int kPackItems = 4;
+constexpr uint32_t kPackChunk = kPackThreads * kPackItems;
+constexpr uint32_t kPackWords = kPackChunk / 2 + 2;  // 4096 fields of <= 32 bits, plus two partial words
+
+__device__ __forceinline__ void lds_put_bits(uint64_t* buf, uint64_t rel, uint64_t v, uint32_t w) {
+  const uint32_t idx = (uint32_t)(rel >> 6), sh = (uint32_t)(rel & 63);
+  atomicOr((unsigned long long*)&buf[idx], (unsigned long long)(v << sh));
+  if (sh + w > 64) atomicOr((unsigned long long*)&buf[idx + 1], (unsigned long long)(v >> (64 - sh)));
+}
+
+// Writes buf[0 .. last] to dst[first .. first + last]: interior words stored, the two end words ORed.
+__device__ __forceinline__ void flush_words(const uint64_t* buf, uint64_t* __restrict__ dst, uint64_t first,
+                                            uint32_t last, uint32_t tid) {
+  for (uint32_t x = tid; x <= last; x += kPackThreads) {
+    const uint64_t v = buf[x];
+    if (x == 0 || x == last) {
+      if (v) atomicOr((unsigned long long*)&dst[first + x], (unsigned long long)v);
+    } else {
+      dst[first + x] = v;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __restrict__ pilots, uint64_t K,
                                                               const uint64_t* __restrict__ enc,
                                                               const uint64_t* __restrict__ ubase, uint32_t rice,
@@ -897,13 +945,19 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __
                                                               uint32_t* __restrict__ sel) {
   __shared__ uint64_t part[kPackThreads / 64];
   __shared__ uint64_t chunk_total;
+  __shared__ uint64_t dbuf[kPackWords];
+  __shared__ uint64_t ubuf[kPackWords];
   const uint32_t tid = threadIdx.x, i = blockIdx.x;
   const uint64_t e = enc[i];
   const uint32_t w = (uint32_t)(e & 0xFF);
   const uint64_t base = e >> 8;
   const uint32_t* col = pilots + (uint64_t)i * K;
   uint64_t carry = rice ? ubase[i] : 0;
-  for (uint64_t j0 = 0; j0 < K; j0 += (uint64_t)kPackThreads * kPackItems) {
+  for (uint64_t j0 = 0; j0 < K; j0 += kPackChunk) {
+    for (uint32_t x = tid; x < kPackWords; x += kPackThreads) {
+      dbuf[x] = 0;
+      ubuf[x] = 0;
+    }
     const uint64_t jb = j0 + (uint64_t)tid * kPackItems;
     uint64_t v[kPackItems];
     uint64_t local = 0;
@@ -912,10 +966,9 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __
       v[t] = jb + t < K ? col[jb + t] : 0;
       if (jb + t < K) local += (v[t] >> w) + 1;
     }
-    uint64_t excl = 0;
+    uint64_t incl = local;  // inclusive prefix of the unary lengths inside the wavefront
     if (rice) {
       // block exclusive scan of local
-      uint64_t incl = local;
       const uint32_t ln = tid & 63;
       for (int o = 1; o < 64; o <<= 1) {
         uint64_t y = __shfl_up(incl, o);
@@ -933,29 +986,37 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __
         if (tid < kPackThreads / 64) part[tid] = pi - pv;
         if (tid == kPackThreads / 64 - 1) chunk_total = pi;
       }
-      __syncthreads();
-      excl = carry + part[tid >> 6] + (incl - local);
     }
+    __syncthreads();  // buffers cleared; scan results visible
+    const uint64_t ctot = rice ? chunk_total : 0;
+    uint64_t excl = rice ? carry + part[tid >> 6] + (incl - local) : 0;
+    const uint64_t jend = min(K, j0 + kPackChunk);
+    const uint64_t d_first = (base + j0 * w) >> 6;
+    const uint64_t u_first = carry >> 6;
+    const bool u_lds = ctot == 0 || ((carry + ctot - 1) >> 6) - u_first < kPackWords;
 #pragma unroll
     for (int t = 0; t < kPackItems; t++) {
       const uint64_t jj = jb + t;
       if (jj < K) {
         const uint64_t q = v[t] >> w;
-        put_bits_atomic(data, base + jj * w, w >= 64 ? v[t] : (v[t] & ((1ULL << w) - 1)), w);
+        if (w) lds_put_bits(dbuf, base + jj * w - d_first * 64, v[t] & ((1ULL << w) - 1), w);
         if (rice) {
           const uint64_t pos = excl + q;
-          atomicOr((unsigned long long*)&unary[pos >> 6], 1ULL << (pos & 63));
+          if (u_lds)
+            atomicOr((unsigned long long*)&ubuf[(pos >> 6) - u_first], 1ULL << (pos & 63));
+          else
+            atomicOr((unsigned long long*)&unary[pos >> 6], 1ULL << (pos & 63));
           const uint64_t t_glob = (uint64_t)i * K + jj;
           if ((t_glob & (kSelEvery - 1)) == 0) sel[t_glob / kSelEvery] = (uint32_t)pos;
           excl = pos + 1;
         }
       }
     }
-    if (rice) {
-      __syncthreads();
-      carry += chunk_total;
-      __syncthreads();
-    }
+    __syncthreads();
+    if (w) flush_words(dbuf, data, d_first, (uint32_t)(((base + jend * w - 1) >> 6) - d_first), tid);
+    if (rice && u_lds && ctot) flush_words(ubuf, unary, u_first, (uint32_t)(((carry + ctot - 1) >> 6) - u_first), tid);
+    carry += ctot;
+    __syncthreads();
   }
 }
 

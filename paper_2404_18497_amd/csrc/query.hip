@@ -72,16 +72,41 @@ __device__ __forceinline__ uint64_t unary_high(const uint64_t* __restrict__ un, 
   return cur - prev - 1;
 }
 
-__device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, uint64_t lo) {
+// The residues of offsets j and j + 1: adjacent fields of woff <= 32 bits lie in two consecutive
+// words (the section's trailing pad word keeps idx + 1 inside it).
+__device__ __forceinline__ void offset_pair(const uint64_t* __restrict__ offs, uint64_t j, uint32_t woff,
+                                            uint64_t& r0, uint64_t& r1) {
+  if (woff == 0) {
+    r0 = r1 = 0;
+  } else if (woff <= 32) {
+    const uint64_t pos = j * woff, idx = pos >> 6;
+    const uint32_t sh = (uint32_t)(pos & 63);
+    const uint64_t w0 = offs[idx], w1 = offs[idx + 1];
+    const uint64_t lo64 = sh ? ((w0 >> sh) | (w1 << (64 - sh))) : w0;  // bits [pos, pos + 64)
+    const uint64_t mask = (1ULL << woff) - 1;
+    r0 = lo64 & mask;
+    r1 = (lo64 >> woff) & mask;
+  } else {
+    r0 = get_bits(offs, j * woff, woff);
+    r1 = get_bits(offs, (j + 1) * woff, woff);
+  }
+}
+
+// T: the bucket-function table, enc: the B encoder words, offs: the offset section; each either
+// in global memory or staged in LDS by the caller.
+__device__ __forceinline__ uint64_t query_code(const QueryArgs& a, const uint64_t* __restrict__ T,
+                                               const uint64_t* __restrict__ enc, const uint64_t* __restrict__ offs,
+                                               uint64_t hi, uint64_t lo) {
   if (a.n == 0) return 0;
   const uint64_t j = __umul64hi(hi, a.K);
-  const uint64_t* offs = a.img + a.sec_off;
-  const uint64_t o0 = expected_offset(j, a.R) + (uint64_t)a.dmin + get_bits(offs, j * a.woff, a.woff);
-  const uint64_t o1 = expected_offset(j + 1, a.R) + (uint64_t)a.dmin + get_bits(offs, (j + 1) * a.woff, a.woff);
+  uint64_t r0, r1;
+  offset_pair(offs, j, a.woff, r0, r1);
+  const uint64_t o0 = expected_offset(j, a.R) + (uint64_t)a.dmin + r0;
+  const uint64_t o1 = expected_offset(j + 1, a.R) + (uint64_t)a.dmin + r1;
   const uint32_t m = (uint32_t)(o1 - o0);
   if (m == 0) return o0 < a.n ? o0 : a.n - 1;  // only a non-member reaches an empty partition
-  const uint32_t i = bucket_of(lo, a.table, a.B);
-  const uint64_t e = a.img[a.sec_enc + i];
+  const uint32_t i = bucket_of(lo, T, a.B);
+  const uint64_t e = enc[i];
   const uint32_t w = (uint32_t)(e & 0xFF);
   uint64_t p = get_bits(a.img + a.sec_data, (e >> 8) + j * w, w);
   if (a.coding == PHOBIC_IC_RICE) {
@@ -99,12 +124,46 @@ __device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, 
   return get_bits(a.img + a.sec_remap, (g - a.n) * a.wremap, a.wremap);
 }
 
-__global__ __launch_bounds__(kQBlock) void k_query_u64(QueryArgs a, const uint64_t* __restrict__ keys, uint64_t n,
-                                                       uint64_t* __restrict__ out) {
+__device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, uint64_t lo) {
+  return query_code(a, a.table, a.img + a.sec_enc, a.img + a.sec_off, hi, lo);
+}
+
+__global__ __launch_bounds__(kQBlock) void k_query_u64_global(QueryArgs a, const uint64_t* __restrict__ keys,
+                                                              uint64_t n, uint64_t* __restrict__ out) {
   for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t hi, lo;
     hash_key_u64(keys[x], a.seed, hi, lo);
     out[x] = query_code(a, hi, lo);
+  }
+}
+
+// Bulk u64 query with the bucket-function table and the encoder words staged in LDS (and the
+// offset section too when kOffLds): a grid of a few workgroups per CU strides over the keys, so
+// the per-key random reads left in global memory are the offsets (unless staged), the pilot's low
+// bits and, for Rice, one select sample and the unary words.
+constexpr int kQStageThreads = 512;
+constexpr uint32_t kTablePad = kTableIntervals + 2;  // 2049 entries, rounded up to 16 bytes
+constexpr uint64_t kQueryLdsBytes = 64 * 1024;
+
+template <bool kOffLds>
+__global__ __launch_bounds__(kQStageThreads) void k_query_u64(QueryArgs a, const uint64_t* __restrict__ keys,
+                                                             uint64_t n, uint64_t* __restrict__ out,
+                                                             uint32_t off_words) {
+  extern __shared__ __align__(16) uint64_t qs[];
+  uint64_t* sT = qs;
+  uint64_t* sE = qs + kTablePad;
+  uint64_t* sO = sE + a.B;
+  for (uint32_t x = threadIdx.x; x <= kTableIntervals; x += kQStageThreads) sT[x] = a.table[x];
+  for (uint32_t x = threadIdx.x; x < a.B; x += kQStageThreads) sE[x] = a.img[a.sec_enc + x];
+  if (kOffLds)
+    for (uint32_t x = threadIdx.x; x < off_words; x += kQStageThreads) sO[x] = a.img[a.sec_off + x];
+  __syncthreads();
+  const uint64_t* offs = kOffLds ? sO : a.img + a.sec_off;
+  for (uint64_t x = blockIdx.x * (uint64_t)kQStageThreads + threadIdx.x; x < n;
+       x += (uint64_t)gridDim.x * kQStageThreads) {
+    uint64_t hi, lo;
+    hash_key_u64(keys[x], a.seed, hi, lo);
+    out[x] = query_code(a, sT, sE, offs, hi, lo);
   }
 }
 
@@ -168,8 +227,33 @@ extern "C" phobic_status phobic_query_u64(const phobic_mphf* h, const uint64_t* 
   if (!h) return fail(PHOBIC_E_INVALID, "null handle");
   if (n == 0) return PHOBIC_OK;
   if (!d_keys || !d_pos) return fail(PHOBIC_E_INVALID, "null key or output pointer");
-  hipLaunchKernelGGL(k_query_u64, dim3(query_grid(n)), dim3(kQBlock), 0, (hipStream_t)hip_stream, h->qa, d_keys, n,
-                     d_pos);
+  const QueryArgs& qa = h->qa;
+  // words of the offset section, its trailing pad word included
+  const uint64_t off_words = qa.sec_enc - qa.sec_off;
+  const uint64_t fixed = 8ULL * (kTablePad + qa.B);
+#ifndef PHOBIC_QEXP
+#define PHOBIC_QEXP 1
+#endif
+  if (PHOBIC_QEXP == 0 || fixed > kQueryLdsBytes) {  // very many buckets: everything from global memory
+    hipLaunchKernelGGL(k_query_u64_global, dim3(query_grid(n)), dim3(kQBlock), 0, (hipStream_t)hip_stream, qa, d_keys,
+                       n, d_pos);
+    PHOBIC_HIP(hipGetLastError());
+    return PHOBIC_OK;
+  }
+  const bool off_lds = fixed + 8 * off_words <= kQueryLdsBytes;
+  const size_t lds = (size_t)(fixed + (off_lds ? 8 * off_words : 0));
+  int dev = 0, cus = 0;
+  PHOBIC_HIP(hipGetDevice(&dev));
+  PHOBIC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const uint64_t want = (n + kQStageThreads - 1) / kQStageThreads;
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(
+      1, PHOBIC_QEXP == 2 ? std::min<uint64_t>(want, 1u << 20) : std::min<uint64_t>(want, 4ULL * std::max(cus, 1)));
+  if (off_lds)
+    hipLaunchKernelGGL(k_query_u64<true>, dim3(grid), dim3(kQStageThreads), lds, (hipStream_t)hip_stream, qa, d_keys,
+                       n, d_pos, (uint32_t)off_words);
+  else
+    hipLaunchKernelGGL(k_query_u64<false>, dim3(grid), dim3(kQStageThreads), lds, (hipStream_t)hip_stream, qa, d_keys,
+                       n, d_pos, 0u);
   PHOBIC_HIP(hipGetLastError());
   return PHOBIC_OK;
 }
