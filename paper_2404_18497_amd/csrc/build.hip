@@ -1160,21 +1160,102 @@ uint32_t next_pow2(uint32_t v) {
   return p;
 }
 
-// Stream-ordered scratch allocations, released on every exit path.
+// Build scratch.  Device blocks (hipMalloc) and pinned host blocks (hipHostMalloc, for the small
+// transfers between the phases) are grouped into workspaces that outlive the builds: a build leases
+// one workspace per device (concurrent builds lease different ones), takes its buffers from the
+// blocks in request order with a bump pointer, and returns the workspace once its stream is idle.
+// Blocks are allocated only when a request does not fit (grow-only) and stay allocated until the
+// process ends, so repeated builds of similar sizes allocate and free nothing.
+struct WsBlock {
+  void* p;
+  size_t cap;
+};
+struct Workspace {
+  int device = 0;
+  std::vector<WsBlock> dev, host;
+};
+std::mutex g_ws_mu;
+std::vector<Workspace*> g_ws_idle;
+
+Workspace* lease_workspace(int device) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  for (size_t i = 0; i < g_ws_idle.size(); i++) {
+    if (g_ws_idle[i]->device == device) {
+      Workspace* w = g_ws_idle[i];
+      g_ws_idle.erase(g_ws_idle.begin() + (ptrdiff_t)i);
+      return w;
+    }
+  }
+  Workspace* w = new Workspace();
+  w->device = device;
+  return w;
+}
+
+void return_workspace(Workspace* w) {
+  std::lock_guard<std::mutex> lock(g_ws_mu);
+  g_ws_idle.push_back(w);
+}
+
 struct Scratch {
   hipStream_t st;
-  std::vector<void*> ptrs;
-  explicit Scratch(hipStream_t s) : st(s) {}
+  Workspace* ws;
+  size_t db = 0, doff = 0, hb = 0, hoff = 0;
+  explicit Scratch(hipStream_t s) : st(s) {
+    int d = 0;
+    (void)hipGetDevice(&d);
+    ws = lease_workspace(d);
+  }
   template <class T>
   hipError_t get(T** p, uint64_t count) {
     void* q = nullptr;
-    hipError_t e = hipMallocAsync(&q, std::max<uint64_t>(count, 1) * sizeof(T), st);
-    if (e == hipSuccess) ptrs.push_back(q);
+    const hipError_t e = take(ws->dev, db, doff, std::max<uint64_t>(count, 1) * sizeof(T), false, &q);
     *p = (T*)q;
     return e;
   }
+  // pinned host staging
+  template <class T>
+  hipError_t host(T** p, uint64_t count) {
+    void* q = nullptr;
+    const hipError_t e = take(ws->host, hb, hoff, std::max<uint64_t>(count, 1) * sizeof(T), true, &q);
+    *p = (T*)q;
+    return e;
+  }
+  // copies `count` values from src through pinned staging to the device address dst, on the stream
+  template <class T>
+  hipError_t upload(T* dst, const T* src, uint64_t count) {
+    if (count == 0) return hipSuccess;
+    T* stage = nullptr;
+    hipError_t e = host(&stage, count);
+    if (e != hipSuccess) return e;
+    std::memcpy(stage, src, count * sizeof(T));
+    return hipMemcpyAsync(dst, stage, count * sizeof(T), hipMemcpyHostToDevice, st);
+  }
   ~Scratch() {
-    for (void* p : ptrs) (void)hipFreeAsync(p, st);
+    (void)hipStreamSynchronize(st);  // nothing on the stream may still use the blocks
+    return_workspace(ws);
+  }
+
+ private:
+  static hipError_t take(std::vector<WsBlock>& bl, size_t& b, size_t& off, size_t bytes, bool pinned, void** out) {
+    bytes = (bytes + 255) & ~(size_t)255;
+    while (b < bl.size()) {
+      if (off + bytes <= bl[b].cap) {
+        *out = (char*)bl[b].p + off;
+        off += bytes;
+        return hipSuccess;
+      }
+      b++;
+      off = 0;
+    }
+    const size_t cap = std::max(bytes, pinned ? ((size_t)4 << 20) : ((size_t)64 << 20));
+    void* q = nullptr;
+    const hipError_t e = pinned ? hipHostMalloc(&q, cap, hipHostMallocDefault) : hipMalloc(&q, cap);
+    if (e != hipSuccess) return e;
+    bl.push_back({q, cap});
+    b = bl.size() - 1;
+    off = bytes;
+    *out = q;
+    return hipSuccess;
   }
 };
 
@@ -1299,7 +1380,9 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   }
   const uint64_t C = gshift >= 0 ? (K + (1ULL << gshift) - 1) >> gshift : 0;
   const bool coarse_path = gshift >= 0 && C <= kMaxCoarse && n < (1ULL << 32);
-  uint64_t old_info[3] = {0, 0, 0};
+  uint64_t* old_info;  // pinned: max n_j, max m_j, table total of the fallback path
+  PHOBIC_HIP(S.host(&old_info, 3));
+  old_info[0] = old_info[1] = old_info[2] = 0;
 
   if (coarse_path) {
     uint32_t *ccnt, *hrow, *cur;
@@ -1385,10 +1468,12 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     PHOBIC_HIP(hipGetLastError());
   }
 
-  uint32_t hinfo[4] = {0, 0, 0, 0};
-  uint64_t htot = 0;
-  PHOBIC_HIP(hipMemcpyAsync(hinfo, err, sizeof(hinfo), hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(&htot, d64, sizeof(htot), hipMemcpyDeviceToHost, st));
+  uint32_t* hinfo;  // pinned
+  uint64_t* htotp;
+  PHOBIC_HIP(S.host(&hinfo, 4));
+  PHOBIC_HIP(S.host(&htotp, 1));
+  PHOBIC_HIP(hipMemcpyAsync(hinfo, err, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(htotp, d64, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipStreamSynchronize(st));
   if (hinfo[0] & (1u << PHOBIC_E_CAPACITY))
     return fail(PHOBIC_E_CAPACITY, "a group of partitions exceeds the LDS of the bucket-sort workgroup");
@@ -1399,7 +1484,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   }
   const uint64_t max_nj = coarse_path ? hinfo[2] : old_info[0];
   const uint64_t max_m = coarse_path ? (an != ad ? hinfo[3] : max_nj) : old_info[1];
-  const uint64_t total = coarse_path ? (an != ad ? htot : n) : old_info[2];
+  const uint64_t total = coarse_path ? (an != ad ? *htotp : n) : old_info[2];
   const uint32_t hmaxb = hinfo[1];
   h->info.max_partition_keys = max_nj;
   h->info.max_bucket_keys = hmaxb;
@@ -1455,19 +1540,23 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   PHOBIC_HIP(S.get(&dmm, 2));
   const uint64_t R = (uint64_t)(((unsigned __int128)total << 32) / K);
   const long long init_mm[2] = {LLONG_MAX, LLONG_MIN};
-  PHOBIC_HIP(hipMemcpyAsync(dmm, init_mm, sizeof(init_mm), hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(S.upload(dmm, init_mm, 2));
   hipLaunchKernelGGL(k_encoder_stats, dim3(B), dim3(kBlock), 0, st, pilots, K, shsum, vmax);
   hipLaunchKernelGGL(k_offset_stats, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, toff, K, R, dmm);
   PHOBIC_HIP(hipGetLastError());
-  std::vector<uint64_t> hsh((size_t)B * 33);
-  std::vector<uint32_t> hmax(B);
-  long long hmm[2];
-  uint32_t herr = 0;
-  PHOBIC_HIP(hipMemcpyAsync(hsh.data(), shsum, hsh.size() * 8, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(hmax.data(), vmax, hmax.size() * 4, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(hmm, dmm, sizeof(hmm), hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(&herr, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  uint64_t* hsh;  // pinned
+  uint32_t *hmax, *herrp;
+  long long* hmm;
+  PHOBIC_HIP(S.host(&hsh, (uint64_t)B * 33));
+  PHOBIC_HIP(S.host(&hmax, B));
+  PHOBIC_HIP(S.host(&hmm, 2));
+  PHOBIC_HIP(S.host(&herrp, 1));
+  PHOBIC_HIP(hipMemcpyAsync(hsh, shsum, (size_t)B * 33 * 8, hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(hmax, vmax, (size_t)B * 4, hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(hmm, dmm, 2 * sizeof(long long), hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(herrp, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipStreamSynchronize(st));
+  const uint32_t herr = *herrp;
   if (herr & (1u << PHOBIC_E_DUPLICATE)) return fail(PHOBIC_E_DUPLICATE, "two keys share their 128-bit hash code");
   if (herr & (1u << PHOBIC_E_PILOT_OVERFLOW))
     return fail(PHOBIC_E_PILOT_OVERFLOW, "a bucket needs a pilot above " + std::to_string(limit));
@@ -1498,12 +1587,12 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   h->header = hdr;
   uint64_t* img = h->d_image;
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nwords)), dim3(kBlock), 0, st, img, nwords, (uint64_t)0);
-  PHOBIC_HIP(hipMemcpyAsync(img, hdr.data(), kHeaderWords * 8, hipMemcpyHostToDevice, st));
-  PHOBIC_HIP(hipMemcpyAsync(img + hdr[kHSecEnc], enc.data(), (size_t)B * 8, hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(S.upload(img, hdr.data(), (uint64_t)kHeaderWords));
+  PHOBIC_HIP(S.upload(img + hdr[kHSecEnc], enc.data(), (uint64_t)B));
   uint64_t* d_ubase = nullptr;
   if (rice) {
     PHOBIC_HIP(S.get(&d_ubase, B));
-    PHOBIC_HIP(hipMemcpyAsync(d_ubase, ubase.data(), (size_t)B * 8, hipMemcpyHostToDevice, st));
+    PHOBIC_HIP(S.upload(d_ubase, ubase.data(), (uint64_t)B));
   }
   if (woff)
     hipLaunchKernelGGL(k_pack_offsets, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, toff, K, R, dmin, woff,

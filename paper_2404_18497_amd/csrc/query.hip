@@ -39,9 +39,13 @@ __device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t r) {
 }
 
 // High part q of value t of the unary stream: q = (position of one t) - (position of one t-1) - 1,
-// with one -1 at position -1.  Starts from the sample of one number 256 floor((t-1)/256).
+// with one -1 at position -1.  The select sample of one number 256 floor((t-1)/256) is read without
+// a preceding branch, so its load can issue as soon as t is known.
 __device__ __forceinline__ uint64_t unary_high(const uint64_t* __restrict__ un, const uint32_t* __restrict__ sel,
                                                uint64_t t) {
+  const uint64_t ta = t ? t - 1 : 0;
+  const uint64_t s = ta / kSelEvery;
+  const uint64_t sample = sel[s];
   uint64_t prev;  // position of one t-1, or UINT64_MAX for t = 0
   uint64_t word;
   uint64_t bits;
@@ -50,12 +54,9 @@ __device__ __forceinline__ uint64_t unary_high(const uint64_t* __restrict__ un, 
     word = 0;
     bits = un[0];
   } else {
-    const uint64_t ta = t - 1;
-    const uint64_t s = ta / kSelEvery;
-    uint64_t pos = sel[s];
     uint32_t r = (uint32_t)(ta - s * kSelEvery);
-    word = pos >> 6;
-    bits = un[word] & (~0ULL << (pos & 63));
+    word = sample >> 6;
+    bits = un[word] & (~0ULL << (sample & 63));
     for (;;) {
       uint32_t c = __popcll(bits);
       if (r < c) break;
@@ -92,27 +93,28 @@ __device__ __forceinline__ void offset_pair(const uint64_t* __restrict__ offs, u
   }
 }
 
-// T: the bucket-function table, enc: the B encoder words, offs: the offset section; each either
-// in global memory or staged in LDS by the caller.
-__device__ __forceinline__ uint64_t query_code(const QueryArgs& a, const uint64_t* __restrict__ T,
-                                               const uint64_t* __restrict__ enc, const uint64_t* __restrict__ offs,
-                                               uint64_t hi, uint64_t lo) {
+__device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, uint64_t lo) {
   if (a.n == 0) return 0;
+  const uint64_t* __restrict__ T = a.table;
+  const uint64_t* __restrict__ enc = a.img + a.sec_enc;
+  const uint64_t* __restrict__ offs = a.img + a.sec_off;
+  // The pilot's fields depend on (i, j) only, not on the offsets: the offset pair, the low bits and
+  // the select sample are independent reads that are in flight together.
   const uint64_t j = __umul64hi(hi, a.K);
-  uint64_t r0, r1;
-  offset_pair(offs, j, a.woff, r0, r1);
-  const uint64_t o0 = expected_offset(j, a.R) + (uint64_t)a.dmin + r0;
-  const uint64_t o1 = expected_offset(j + 1, a.R) + (uint64_t)a.dmin + r1;
-  const uint32_t m = (uint32_t)(o1 - o0);
-  if (m == 0) return o0 < a.n ? o0 : a.n - 1;  // only a non-member reaches an empty partition
   const uint32_t i = bucket_of(lo, T, a.B);
   const uint64_t e = enc[i];
   const uint32_t w = (uint32_t)(e & 0xFF);
+  uint64_t r0, r1;
+  offset_pair(offs, j, a.woff, r0, r1);
   uint64_t p = get_bits(a.img + a.sec_data, (e >> 8) + j * w, w);
   if (a.coding == PHOBIC_IC_RICE) {
     const uint64_t q = unary_high(a.img + a.sec_unary, (const uint32_t*)(a.img + a.sec_sel), (uint64_t)i * a.K + j);
     p |= q << w;
   }
+  const uint64_t o0 = expected_offset(j, a.R) + (uint64_t)a.dmin + r0;
+  const uint64_t o1 = expected_offset(j + 1, a.R) + (uint64_t)a.dmin + r1;
+  const uint32_t m = (uint32_t)(o1 - o0);
+  if (m == 0) return o0 < a.n ? o0 : a.n - 1;  // only a non-member reaches an empty partition
   // pilots are at most 2^32 - 1, so 32-bit division is exact
   const uint32_t p32 = (uint32_t)p;
   const uint32_t s = p32 / m;
@@ -124,46 +126,12 @@ __device__ __forceinline__ uint64_t query_code(const QueryArgs& a, const uint64_
   return get_bits(a.img + a.sec_remap, (g - a.n) * a.wremap, a.wremap);
 }
 
-__device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, uint64_t lo) {
-  return query_code(a, a.table, a.img + a.sec_enc, a.img + a.sec_off, hi, lo);
-}
-
-__global__ __launch_bounds__(kQBlock) void k_query_u64_global(QueryArgs a, const uint64_t* __restrict__ keys,
-                                                              uint64_t n, uint64_t* __restrict__ out) {
+__global__ __launch_bounds__(kQBlock) void k_query_u64(QueryArgs a, const uint64_t* __restrict__ keys, uint64_t n,
+                                                       uint64_t* __restrict__ out) {
   for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t hi, lo;
     hash_key_u64(keys[x], a.seed, hi, lo);
     out[x] = query_code(a, hi, lo);
-  }
-}
-
-// Bulk u64 query with the bucket-function table and the encoder words staged in LDS (and the
-// offset section too when kOffLds): a grid of a few workgroups per CU strides over the keys, so
-// the per-key random reads left in global memory are the offsets (unless staged), the pilot's low
-// bits and, for Rice, one select sample and the unary words.
-constexpr int kQStageThreads = 512;
-constexpr uint32_t kTablePad = kTableIntervals + 2;  // 2049 entries, rounded up to 16 bytes
-constexpr uint64_t kQueryLdsBytes = 64 * 1024;
-
-template <bool kOffLds>
-__global__ __launch_bounds__(kQStageThreads) void k_query_u64(QueryArgs a, const uint64_t* __restrict__ keys,
-                                                             uint64_t n, uint64_t* __restrict__ out,
-                                                             uint32_t off_words) {
-  extern __shared__ __align__(16) uint64_t qs[];
-  uint64_t* sT = qs;
-  uint64_t* sE = qs + kTablePad;
-  uint64_t* sO = sE + a.B;
-  for (uint32_t x = threadIdx.x; x <= kTableIntervals; x += kQStageThreads) sT[x] = a.table[x];
-  for (uint32_t x = threadIdx.x; x < a.B; x += kQStageThreads) sE[x] = a.img[a.sec_enc + x];
-  if (kOffLds)
-    for (uint32_t x = threadIdx.x; x < off_words; x += kQStageThreads) sO[x] = a.img[a.sec_off + x];
-  __syncthreads();
-  const uint64_t* offs = kOffLds ? sO : a.img + a.sec_off;
-  for (uint64_t x = blockIdx.x * (uint64_t)kQStageThreads + threadIdx.x; x < n;
-       x += (uint64_t)gridDim.x * kQStageThreads) {
-    uint64_t hi, lo;
-    hash_key_u64(keys[x], a.seed, hi, lo);
-    out[x] = query_code(a, sT, sE, offs, hi, lo);
   }
 }
 
@@ -227,33 +195,8 @@ extern "C" phobic_status phobic_query_u64(const phobic_mphf* h, const uint64_t* 
   if (!h) return fail(PHOBIC_E_INVALID, "null handle");
   if (n == 0) return PHOBIC_OK;
   if (!d_keys || !d_pos) return fail(PHOBIC_E_INVALID, "null key or output pointer");
-  const QueryArgs& qa = h->qa;
-  // words of the offset section, its trailing pad word included
-  const uint64_t off_words = qa.sec_enc - qa.sec_off;
-  const uint64_t fixed = 8ULL * (kTablePad + qa.B);
-#ifndef PHOBIC_QEXP
-#define PHOBIC_QEXP 1
-#endif
-  if (PHOBIC_QEXP == 0 || fixed > kQueryLdsBytes) {  // very many buckets: everything from global memory
-    hipLaunchKernelGGL(k_query_u64_global, dim3(query_grid(n)), dim3(kQBlock), 0, (hipStream_t)hip_stream, qa, d_keys,
-                       n, d_pos);
-    PHOBIC_HIP(hipGetLastError());
-    return PHOBIC_OK;
-  }
-  const bool off_lds = fixed + 8 * off_words <= kQueryLdsBytes;
-  const size_t lds = (size_t)(fixed + (off_lds ? 8 * off_words : 0));
-  int dev = 0, cus = 0;
-  PHOBIC_HIP(hipGetDevice(&dev));
-  PHOBIC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const uint64_t want = (n + kQStageThreads - 1) / kQStageThreads;
-  const uint32_t grid = (uint32_t)std::max<uint64_t>(
-      1, PHOBIC_QEXP == 2 ? std::min<uint64_t>(want, 1u << 20) : std::min<uint64_t>(want, 4ULL * std::max(cus, 1)));
-  if (off_lds)
-    hipLaunchKernelGGL(k_query_u64<true>, dim3(grid), dim3(kQStageThreads), lds, (hipStream_t)hip_stream, qa, d_keys,
-                       n, d_pos, (uint32_t)off_words);
-  else
-    hipLaunchKernelGGL(k_query_u64<false>, dim3(grid), dim3(kQStageThreads), lds, (hipStream_t)hip_stream, qa, d_keys,
-                       n, d_pos, 0u);
+  hipLaunchKernelGGL(k_query_u64, dim3(query_grid(n)), dim3(kQBlock), 0, (hipStream_t)hip_stream, h->qa, d_keys, n,
+                     d_pos);
   PHOBIC_HIP(hipGetLastError());
   return PHOBIC_OK;
 }
