@@ -460,15 +460,36 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* 
   }
   if (tid == 0 && j0 + ghere == jend) off[jend] = kbase + base + ns;
   __syncthreads();
+  // destinations inside the bin, then the fingerprints through LDS (free again) in rounds of
+  // kSegLdsBytes / 8 so that the stores to global memory are contiguous
+  // (two 16-bit destinations per register: a bin holds fewer than 2^16 keys)
+  uint32_t dst2[(kItems + 1) / 2];
+#pragma unroll
+  for (int t = 0; t < (kItems + 1) / 2; t++) dst2[t] = 0;
 #pragma unroll
   for (int t = 0; t < kItems; t++) {
     const uint32_t i = tid + t * kSegThreads;
     if (i < ns) {
       const uint32_t r = rec[i];
-      const uint64_t dest = kbase + base + cnt[(r >> 29) * nbpad + ((r >> 16) & 0x1FFF)] + (r & 0xFFFF);
-      sortedf[dest] = fp[t];
-      if (dbg) dbg[dest] = codes[base + i];
+      const uint32_t d = cnt[(r >> 29) * nbpad + ((r >> 16) & 0x1FFF)] + (r & 0xFFFF);
+      dst2[t / 2] |= d << (16 * (t & 1));
+      if (dbg) dbg[kbase + base + d] = codes[base + i];
     }
+  }
+  __syncthreads();
+  uint64_t* stage = (uint64_t*)lds;
+  constexpr uint32_t kRound = (uint32_t)(kSegLdsBytes / 8);
+  for (uint32_t q0 = 0; q0 < ns; q0 += kRound) {
+#pragma unroll
+    for (int t = 0; t < kItems; t++) {
+      const uint32_t i = tid + t * kSegThreads;
+      const uint32_t d = (dst2[t / 2] >> (16 * (t & 1))) & 0xFFFFu;
+      if (i < ns && d - q0 < kRound) stage[d - q0] = fp[t];
+    }
+    __syncthreads();
+    const uint32_t cntq = min(kRound, ns - q0);
+    for (uint32_t x = tid; x < cntq; x += kSegThreads) sortedf[kbase + base + q0 + x] = stage[x];
+    __syncthreads();
   }
 }
 
