@@ -126,12 +126,136 @@ __device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, 
   return get_bits(a.img + a.sec_remap, (g - a.n) * a.wremap, a.wremap);
 }
 
+// kN lookups per thread in lockstep: every stage issues the reads of all kN lookups before any of
+// them is consumed, so one wavefront keeps kN times as many independent cache-line reads in flight
+// (the query is bound by the latency of its chain of dependent reads, not by bandwidth).  Same
+// arithmetic as query_code.
+template <int kN>
+__device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (&hi)[kN], const uint64_t (&lo)[kN],
+                                            uint64_t (&res)[kN]) {
+  const uint64_t* __restrict__ offs = a.img + a.sec_off;
+  const uint64_t* __restrict__ un = a.img + a.sec_unary;
+  const uint32_t* __restrict__ sel = (const uint32_t*)(a.img + a.sec_sel);
+  const bool rice = a.coding == PHOBIC_IC_RICE;
+  uint64_t j[kN], e[kN], p[kN], r0[kN], r1[kN];
+  uint32_t i[kN];
+#pragma unroll
+  for (int q = 0; q < kN; q++) {
+    j[q] = __umul64hi(hi[q], a.K);
+    i[q] = bucket_of(lo[q], a.table, a.B);
+  }
+#pragma unroll
+  for (int q = 0; q < kN; q++) e[q] = a.img[a.sec_enc + i[q]];
+  // offsets, low bits and select samples: independent of each other
+  uint64_t t[kN], ta[kN], sample[kN];
+#pragma unroll
+  for (int q = 0; q < kN; q++) {
+    offset_pair(offs, j[q], a.woff, r0[q], r1[q]);
+    const uint32_t w = (uint32_t)(e[q] & 0xFF);
+    p[q] = get_bits(a.img + a.sec_data, (e[q] >> 8) + j[q] * w, w);
+    t[q] = (uint64_t)i[q] * a.K + j[q];
+    ta[q] = t[q] ? t[q] - 1 : 0;
+    sample[q] = rice ? sel[ta[q] / kSelEvery] : 0;
+  }
+  if (rice) {
+    uint64_t word[kN], bits[kN], prev[kN];
+    uint32_t r[kN];
+    bool found[kN];
+#pragma unroll
+    for (int q = 0; q < kN; q++) {
+      r[q] = (uint32_t)(ta[q] % kSelEvery);
+      word[q] = t[q] ? sample[q] >> 6 : 0;
+      bits[q] = un[word[q]];
+      if (t[q]) bits[q] &= ~0ULL << (sample[q] & 63);
+      found[q] = t[q] == 0;
+    }
+    // the one of value t - 1: skip r ones from the sample
+    for (bool more = true; more;) {
+      more = false;
+#pragma unroll
+      for (int q = 0; q < kN; q++) {
+        if (!found[q]) {
+          const uint32_t c = __popcll(bits[q]);
+          if (r[q] < c) {
+            found[q] = true;
+          } else {
+            r[q] -= c;
+            bits[q] = un[++word[q]];
+            more = true;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kN; q++) {
+      if (t[q] == 0) {
+        prev[q] = ~0ULL;
+      } else {
+        prev[q] = word[q] * 64 + select_in_word(bits[q], r[q]);
+        const uint32_t b = (uint32_t)(prev[q] & 63);
+        bits[q] = b == 63 ? 0 : (bits[q] & (~0ULL << (b + 1)));
+      }
+    }
+    // the one of value t: the next set bit
+    for (bool more = true; more;) {
+      more = false;
+#pragma unroll
+      for (int q = 0; q < kN; q++) {
+        if (bits[q] == 0) {
+          bits[q] = un[++word[q]];
+          more = true;
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kN; q++) {
+      const uint64_t cur = word[q] * 64 + (uint32_t)(__ffsll((long long)bits[q]) - 1);
+      p[q] |= (cur - prev[q] - 1) << (uint32_t)(e[q] & 0xFF);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kN; q++) {
+    const uint64_t o0 = expected_offset(j[q], a.R) + (uint64_t)a.dmin + r0[q];
+    const uint64_t o1 = expected_offset(j[q] + 1, a.R) + (uint64_t)a.dmin + r1[q];
+    const uint32_t m = (uint32_t)(o1 - o0);
+    if (m == 0) {  // only a non-member reaches an empty partition
+      res[q] = o0 < a.n ? o0 : a.n - 1;
+      continue;
+    }
+    const uint32_t p32 = (uint32_t)p[q];
+    const uint32_t s = p32 / m;
+    const uint32_t d = p32 - s * m;
+    uint32_t pos = pos_hash(fingerprint(hi[q], lo[q]), (uint64_t)(s + 1) * kPhi64, m) + d;
+    if (pos >= m) pos -= m;
+    const uint64_t g = o0 + pos;
+    res[q] = g < a.n ? g : get_bits(a.img + a.sec_remap, (g - a.n) * a.wremap, a.wremap);
+  }
+}
+
+constexpr int kQN = 4;
+
+// Thread x handles keys x, x + stride, ..., kQN of them per round.
 __global__ __launch_bounds__(kQBlock) void k_query_u64(QueryArgs a, const uint64_t* __restrict__ keys, uint64_t n,
                                                        uint64_t* __restrict__ out) {
-  for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t hi, lo;
-    hash_key_u64(keys[x], a.seed, hi, lo);
-    out[x] = query_code(a, hi, lo);
+  if (a.n == 0) {
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x)
+      out[x] = 0;
+    return;
+  }
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x0 < n; x0 += stride * kQN) {
+    uint64_t hi[kQN], lo[kQN], res[kQN];
+#pragma unroll
+    for (int q = 0; q < kQN; q++) {
+      const uint64_t x = x0 + q * stride;
+      hash_key_u64(keys[x < n ? x : x0], a.seed, hi[q], lo[q]);
+    }
+    query_codes<kQN>(a, hi, lo, res);
+#pragma unroll
+    for (int q = 0; q < kQN; q++) {
+      const uint64_t x = x0 + q * stride;
+      if (x < n) out[x] = res[q];
+    }
   }
 }
 
@@ -180,8 +304,8 @@ __global__ __launch_bounds__(kQBlock) void k_query_multi(const QueryJob* __restr
   }
 }
 
-uint32_t query_grid(uint64_t n) {
-  uint64_t g = (n + kQBlock - 1) / kQBlock;
+uint32_t query_grid(uint64_t n, uint32_t per_thread = 1) {
+  uint64_t g = (n + (uint64_t)kQBlock * per_thread - 1) / ((uint64_t)kQBlock * per_thread);
   return (uint32_t)(g < 1 ? 1 : (g > 1048576 ? 1048576 : g));
 }
 
@@ -195,7 +319,7 @@ extern "C" phobic_status phobic_query_u64(const phobic_mphf* h, const uint64_t* 
   if (!h) return fail(PHOBIC_E_INVALID, "null handle");
   if (n == 0) return PHOBIC_OK;
   if (!d_keys || !d_pos) return fail(PHOBIC_E_INVALID, "null key or output pointer");
-  hipLaunchKernelGGL(k_query_u64, dim3(query_grid(n)), dim3(kQBlock), 0, (hipStream_t)hip_stream, h->qa, d_keys, n,
+  hipLaunchKernelGGL(k_query_u64, dim3(query_grid(n, kQN)), dim3(kQBlock), 0, (hipStream_t)hip_stream, h->qa, d_keys, n,
                      d_pos);
   PHOBIC_HIP(hipGetLastError());
   return PHOBIC_OK;
