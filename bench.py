@@ -95,6 +95,23 @@ def search_work(n, lam):
     return json.load(open(path))["counters"].get(f"{lam:g}")
 
 
+def measured_traffic(kernel: str, n: int, lam: float):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE / WRITE_SIZE summary of this
+    workload (copy-calibrated), or None if there is none or the kernel's source changed since."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"traffic_build_query_{n // 1_000_000}m_lambda{lam:g}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))["kernels"].get(kernel)
+    if not rec or not rec.get("source"):
+        return None
+    src = os.path.join(ROOT, "paper_2404_18497_amd", "csrc", rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
 def headline(args):
     import torch
 
@@ -152,15 +169,19 @@ def headline(args):
     nlaunch = (n + batch - 1) // batch
 
     # dominant kernel and its roofline (per launch; durations from HIP events on the launch stream)
+    cfg = binding.get_search_config()
+    search_kernel = (f"k_search_persistent<{cfg['waves_per_group']}>" if cfg["groups_per_cu"]
+                     else f"k_search<{cfg['waves_per_group']}>")
     per_step = {"k_search": phase["search_ms"], "k_query_u64": query_ms}
     dom = max(per_step, key=per_step.get)
     if dom == "k_search":
         w = search_work(n, args.lam)
         ops = HASH_OPS * w["hash_evals"] + PROBE_OPS * w["slot_probes"] if w else None
         achieved = ops / (phase["search_ms"] * 1e-3) / 1e12 if ops else None
-        roofline = {"kernel": "k_search", "bound": "alu", "achieved": None if achieved is None else round(achieved, 3),
+        roofline = {"kernel": search_kernel, "bound": "alu", "achieved": None if achieved is None else round(achieved, 3),
                     "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
-                    "frac": None if achieved is None else round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                    "frac": None if achieved is None else round(achieved / ALU_PEAK_TOPS, 4),
+                    "traffic": measured_traffic(search_kernel, n, args.lam),
                     "per_launch_ms": round(phase["search_ms"], 4), "launches_per_step": 1,
                     "algorithmic_ops_per_launch": ops,
                     "work": None if not w else {"hash_evals": w["hash_evals"], "slot_probes": w["slot_probes"]}}
@@ -168,7 +189,8 @@ def headline(args):
         per = query_ms / nlaunch
         achieved = 16.0 * min(batch, n) / (per * 1e-3) / 1e9
         roofline = {"kernel": "k_query_u64", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic("k_query_u64", n, args.lam),
                     "per_launch_ms": round(per, 4), "launches_per_step": nlaunch,
                     "algorithmic_bytes_per_launch": 16.0 * min(batch, n)}
     q_per = query_ms / nlaunch
@@ -319,7 +341,7 @@ def serve_mode(args):
                 "mean_batch": float(np.mean([r["batch"] for r in results.values()])), "stats": st}
 
     plain_kw = dict(workers=1, max_query_batch=1, max_build_batch=1)
-    served_kw = dict(workers=4, max_query_batch=64, max_build_batch=8)
+    served_kw = dict(workers=4, max_query_batch=64, max_build_batch=8, query_workers=1)
     log("plain capacity (all requests at once, FIFO, one at a time)")
     cap = run(plain_kw, None)
     rate = args.load * cap["throughput_rps"]

@@ -143,7 +143,8 @@ typedef struct {
   uint32_t reserved;
 } phobic_search_config;
 
-/* Sets the search shape used by later builds on the calling process (all devices). */
+/* Sets the search shape used by later builds on the calling process (all devices).  The default is
+ * two wavefronts per workgroup, one wavefront per partition ({2, 0, 1, 0}). */
 phobic_status phobic_set_search_config(const phobic_search_config* cfg);
 phobic_status phobic_get_search_config(phobic_search_config* out);
 
@@ -175,7 +176,7 @@ typedef struct {
   uint32_t workers;          /* requests in flight at once, one HIP stream each, >= 1 */
   uint32_t max_query_batch;  /* queries per launch, >= 1 (1 = no query batching) */
   uint32_t max_build_batch;  /* builds per batched build, >= 1 (1 = no build batching) */
-  uint32_t reserved;
+  uint32_t query_workers;    /* workers that take queries only, < workers (0 = every worker takes both) */
 } phobic_server_config;
 
 enum { PHOBIC_REQ_BUILD = 0, PHOBIC_REQ_QUERY = 1 };

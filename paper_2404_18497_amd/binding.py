@@ -50,7 +50,7 @@ class SearchConfig(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("workers", C.c_uint32), ("max_query_batch", C.c_uint32),
-                ("max_build_batch", C.c_uint32), ("reserved", C.c_uint32)]
+                ("max_build_batch", C.c_uint32), ("query_workers", C.c_uint32)]
 
 
 class RequestResult(C.Structure):
@@ -270,8 +270,8 @@ class Server:
     Keeps a reference to every tensor of a request until its completion is polled."""
 
     def __init__(self, prm: Params, budget_bytes: int, workers: int = 4, max_query_batch: int = 32,
-                 max_build_batch: int = 8):
-        cfg = ServerConfig(budget_bytes, workers, max_query_batch, max_build_batch, 0)
+                 max_build_batch: int = 8, query_workers: int = 0):
+        cfg = ServerConfig(budget_bytes, workers, max_query_batch, max_build_batch, query_workers)
         self.s = C.c_void_p()
         _check(lib().phobic_server_create(C.byref(cfg), C.byref(prm), C.byref(self.s)))
         self._live = {}

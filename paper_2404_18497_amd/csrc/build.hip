@@ -1124,7 +1124,7 @@ __global__ __launch_bounds__(kBlock) void k_remap_fill(const uint64_t* __restric
 // Search launch shape
 // ---------------------------------------------------------------------------------------------
 std::mutex g_cfg_mu;
-phobic_search_config g_cfg = {4, 0, 1, 0};
+phobic_search_config g_cfg = {2, 0, 1, 0};  // two partitions per workgroup, one per wavefront
 
 phobic_search_config search_config() {
   std::lock_guard<std::mutex> lock(g_cfg_mu);

@@ -65,8 +65,9 @@ struct phobic_server {
   void note_peak() { peak_bytes = std::max(peak_bytes, resident_bytes + reserved_bytes); }
 
   // Picks the next batch of work for a worker (lock held).  Queries first, in arrival order, up to
-  // max_query_batch whose MPHF is ready; otherwise builds in arrival order that fit the budget.
-  std::vector<phobic::Req*> pick() {
+  // max_query_batch whose MPHF is ready; otherwise builds in arrival order that fit the budget,
+  // unless the worker is one of the query_workers kept for queries only.
+  std::vector<phobic::Req*> pick(bool queries_only) {
     std::vector<phobic::Req*> got;
     for (auto it = pending.begin(); it != pending.end() && got.size() < cfg.max_query_batch;) {
       phobic::Req* r = *it;
@@ -80,7 +81,7 @@ struct phobic_server {
       }
       ++it;
     }
-    if (!got.empty()) return got;
+    if (!got.empty() || queries_only) return got;
     for (auto it = pending.begin(); it != pending.end() && got.size() < cfg.max_build_batch;) {
       phobic::Req* r = *it;
       if (r->kind == PHOBIC_REQ_BUILD) {
@@ -162,7 +163,8 @@ struct phobic_server {
     note_peak();
   }
 
-  void worker_main() {
+  void worker_main(uint32_t index) {
+    const bool queries_only = index < cfg.query_workers;
     (void)hipSetDevice(device);
     hipStream_t st = nullptr;
     (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -171,8 +173,9 @@ struct phobic_server {
       {
         std::unique_lock<std::mutex> lock(mu);
         for (;;) {
-          batch = pick();
+          batch = pick(queries_only);
           if (!batch.empty() || (stop && pending.empty())) break;
+          if (stop && queries_only) break;  // the other workers finish or fail what is left
           if (stop && running == 0) {  // shutting down and nothing can progress: fail what is left
             const double t = now();
             for (auto r : pending) {
@@ -242,8 +245,9 @@ extern "C" phobic_status phobic_server_create(const phobic_server_config* cfg, c
   phobic_status vs = validate_params(params, &B);
   if (vs != PHOBIC_OK) return vs;
   if (cfg->workers < 1 || cfg->workers > 64 || cfg->max_query_batch < 1 || cfg->max_build_batch < 1 ||
-      cfg->hbm_budget_bytes == 0)
-    return fail(PHOBIC_E_INVALID, "workers in [1, 64], batches >= 1 and a nonzero budget are required");
+      cfg->hbm_budget_bytes == 0 || cfg->query_workers >= cfg->workers)
+    return fail(PHOBIC_E_INVALID,
+                "workers in [1, 64], query_workers < workers, batches >= 1 and a nonzero budget are required");
   auto s = new (std::nothrow) phobic_server();
   if (!s) return fail(PHOBIC_E_OOM, "host allocation");
   s->cfg = *cfg;
@@ -254,7 +258,7 @@ extern "C" phobic_status phobic_server_create(const phobic_server_config* cfg, c
     delete s;
     return fail(PHOBIC_E_DEVICE, "no HIP device");
   }
-  for (uint32_t w = 0; w < cfg->workers; w++) s->workers.emplace_back([s] { s->worker_main(); });
+  for (uint32_t w = 0; w < cfg->workers; w++) s->workers.emplace_back([s, w] { s->worker_main(w); });
   *out = s;
   return PHOBIC_OK;
 }

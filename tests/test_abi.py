@@ -97,3 +97,16 @@ def test_batch_rejects_bad_arguments_on_host(lib):
     counts0 = (C.c_uint64 * 2)(0, 0)
     assert lib.phobic_build_batch_u64(ptrs, counts0, 2, C.byref(q), None, outs) == binding.E_INVALID
     assert not outs[0] and not outs[1]
+
+
+def test_server_config_rejected_on_host():
+    from paper_2404_18497_amd import binding
+
+    p = binding.params()
+    for bad in [dict(workers=0), dict(workers=2, query_workers=2), dict(max_query_batch=0), dict(max_build_batch=0)]:
+        kw = dict(workers=4, max_query_batch=8, max_build_batch=4, query_workers=0) | bad
+        with pytest.raises(binding.PhobicError) as e:
+            binding.Server(p, budget_bytes=1 << 30, **kw)
+        assert e.value.code == binding.E_INVALID
+    with pytest.raises(binding.PhobicError):
+        binding.Server(p, budget_bytes=0)

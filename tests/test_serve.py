@@ -59,9 +59,10 @@ def _trace(seed, nbuild=10, nquery=60):
     return keysets, queries
 
 
-def _run(torch, keysets, queries, workers, qb, bb, alone):
+def _run(torch, keysets, queries, workers, qb, bb, alone, query_workers=0):
     prm = binding.params(lam=7.0)
-    srv = binding.Server(prm, budget_bytes=8 << 30, workers=workers, max_query_batch=qb, max_build_batch=bb)
+    srv = binding.Server(prm, budget_bytes=8 << 30, workers=workers, max_query_batch=qb, max_build_batch=bb,
+                         query_workers=query_workers)
     dk = [_dev(torch, k) for k in keysets]
     dq = [(b, _dev(torch, q)) for b, q in queries]
     outs = [torch.full((q.numel(),), -1, dtype=torch.int64, device="cuda") for _, q in dq]
@@ -98,7 +99,8 @@ def test_server_same_alone_and_in_the_mix(torch):
     _say("alone")
     img_a, pos_a, batch_a, _ = _run(torch, keysets, queries, workers=1, qb=1, bb=1, alone=True)
     _say("mix")
-    img_m, pos_m, batch_m, stats = _run(torch, keysets, queries, workers=4, qb=16, bb=4, alone=False)
+    img_m, pos_m, batch_m, stats = _run(torch, keysets, queries, workers=4, qb=16, bb=4, alone=False,
+                                        query_workers=1)
     assert batch_a == 1 and batch_m > 1  # the mix really batched
     prm = binding.params(lam=7.0)
     for k, a, m in zip(keysets, img_a, img_m):
