@@ -25,6 +25,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "phobic_internal.h"
@@ -252,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2* __rest
 // No per-key global atomics: the only global atomics are one per (workgroup, bin).
 // ---------------------------------------------------------------------------------------------
 constexpr int kCoarseThreads = 1024;
-constexpr uint32_t kCoarseGroups = 512;
+constexpr uint32_t kCoarseGroups = 256;  // scatter workgroups; the count uses two per scatter range
 constexpr uint32_t kMaxCoarse = 14336;   // bins held by the LDS histogram (56 KB)
 constexpr int kSegThreads = 512;
 constexpr uint32_t kMaxG = 8;
@@ -327,8 +328,9 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_scatter(const uint64_
                                                                    ulonglong2* __restrict__ codes) {
   extern __shared__ __align__(16) uint32_t pos[];
   const uint32_t tid = threadIdx.x;
+  // the count ran two workgroups over the two halves of this workgroup's range
   for (uint32_t x = tid; x < C; x += kCoarseThreads) {
-    const uint32_t v = hrow[(uint64_t)blockIdx.x * C + x];
+    const uint32_t v = hrow[(2 * (uint64_t)blockIdx.x) * C + x] + hrow[(2 * (uint64_t)blockIdx.x + 1) * C + x];
     pos[x] = v ? atomicAdd(&cur[x], v) : 0u;
   }
   __syncthreads();
@@ -1217,6 +1219,27 @@ void return_workspace(Workspace* w) {
   g_ws_idle.push_back(w);
 }
 
+// Runs f(i) for i in [0, n) on up to 16 host threads (sequentially for small n).
+template <class F>
+void parallel_for(uint64_t n, F f) {
+  const uint32_t hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const uint32_t nt = n < 65536 ? 1 : hw;
+  if (nt == 1) {
+    for (uint64_t i = 0; i < n; i++) f(i);
+    return;
+  }
+  std::vector<std::thread> th;
+  const uint64_t per = (n + nt - 1) / nt;
+  for (uint32_t t = 0; t < nt; t++) {
+    const uint64_t a = t * per, b = std::min(n, a + per);
+    if (a >= b) break;
+    th.emplace_back([=, &f] {
+      for (uint64_t i = a; i < b; i++) f(i);
+    });
+  }
+  for (auto& x : th) x.join();
+}
+
 struct Scratch {
   hipStream_t st;
   Workspace* ws;
@@ -1409,10 +1432,12 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     uint32_t *ccnt, *hrow, *cur;
     uint64_t* cbase;
     ulonglong2 *codes, *stage = nullptr;
-    const uint32_t ngrp = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kCoarseGroups, (n + 4095) / 4096));
-    const uint64_t per = (n + ngrp - 1) / ngrp;
+    // ngrp scatter workgroups over ranges of 2 * per keys; the count runs 2 * ngrp workgroups over
+    // the halves, so it keeps twice as many loads in flight
+    const uint32_t ngrp = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kCoarseGroups, (n + 8191) / 8192));
+    const uint64_t per = (n + 2 * (uint64_t)ngrp - 1) / (2 * (uint64_t)ngrp);
     PHOBIC_HIP(S.get(&ccnt, C));
-    PHOBIC_HIP(S.get(&hrow, (uint64_t)ngrp * C));
+    PHOBIC_HIP(S.get(&hrow, 2 * (uint64_t)ngrp * C));
     PHOBIC_HIP(S.get(&cur, C));
     PHOBIC_HIP(S.get(&cbase, C + 1));
     PHOBIC_HIP(S.get(&codes, n));
@@ -1421,20 +1446,20 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     const size_t hist_lds = C * sizeof(uint32_t);
     tm.mark();  // 0
     if (str)
-      hipLaunchKernelGGL(k_coarse_count<true>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, in.bytes,
+      hipLaunchKernelGGL(k_coarse_count<true>, dim3(2 * ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, in.bytes,
                          in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, ccnt, hrow);
     else
-      hipLaunchKernelGGL(k_coarse_count<false>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, in.bytes,
-                         in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, ccnt, hrow);
+      hipLaunchKernelGGL(k_coarse_count<false>, dim3(2 * ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys,
+                         in.bytes, in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, ccnt, hrow);
     tm.mark();  // 1
     hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1024), 0, st, ccnt, (uint32_t)C, cbase, cur);
     tm.mark();  // 2
     if (str)
       hipLaunchKernelGGL(k_coarse_scatter<true>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, stage, n,
-                         per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
+                         2 * per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
     else
       hipLaunchKernelGGL(k_coarse_scatter<false>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, stage, n,
-                         per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
+                         2 * per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
     tm.mark();  // 3
     hipLaunchKernelGGL(k_segment_sort<false>, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st, codes, cbase,
                        h->d_table, B, nbpad, (uint32_t)gshift, K, (uint64_t)0, K, (uint64_t)0, seg_cap, sortedf,
@@ -2055,14 +2080,17 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   hipLaunchKernelGGL(k_batch_stats, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, sum, mx);
   hipLaunchKernelGGL(k_batch_offstats, dim3(mphf_groups), dim3(256), 0, st, off, d_desc, count, dmm);
   PHOBIC_HIP(hipGetLastError());
-  std::vector<uint64_t> hsum(items);
-  std::vector<uint32_t> hmx(items);
-  std::vector<long long> hmm(2 * (size_t)count);
-  uint32_t herr[6];
-  PHOBIC_HIP(hipMemcpyAsync(hsum.data(), sum, items * 8, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(hmx.data(), mx, items * 4, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(hmm.data(), dmm, hmm.size() * 8, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(herr, err, sizeof(herr), hipMemcpyDeviceToHost, st));
+  uint64_t* hsum;  // pinned
+  uint32_t *hmx, *herr;
+  long long* hmm;
+  PHOBIC_HIP(S.host(&hsum, items));
+  PHOBIC_HIP(S.host(&hmx, items));
+  PHOBIC_HIP(S.host(&hmm, 2 * (uint64_t)count));
+  PHOBIC_HIP(S.host(&herr, 6));
+  PHOBIC_HIP(hipMemcpyAsync(hsum, sum, items * 8, hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(hmx, mx, items * 4, hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(hmm, dmm, 2 * (size_t)count * 8, hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(herr, err, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipStreamSynchronize(st));
   if (herr[0] & ((1u << PHOBIC_E_DUPLICATE) | (1u << PHOBIC_E_PILOT_OVERFLOW))) {
     const uint64_t J = (uint64_t)herr[4] | ((uint64_t)herr[5] << 32);
@@ -2072,21 +2100,29 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
                 "MPHF " + std::to_string(t) + (dup ? ": two keys share their hash code" : ": pilot overflow"));
   }
   const bool rice = prm.coding == PHOBIC_IC_RICE;
-  std::vector<uint8_t> hw(items);
-  for (uint64_t it = 0; it < items; it++)
+  uint8_t* hw;  // pinned
+  uint64_t* hub;
+  PHOBIC_HIP(S.host(&hw, items));
+  PHOBIC_HIP(S.host(&hub, items));
+  parallel_for(items, [&](uint64_t it) {
     hw[it] = (uint8_t)(rice ? rice_parameter(hsum[it], desc[it / B].K) : bit_length(hmx[it]));
-  std::vector<uint64_t> hub(items, 0);
+    hub[it] = 0;
+  });
   if (rice) {
     uint8_t* dw;
     uint64_t* dub;
     PHOBIC_HIP(S.get(&dw, items));
     PHOBIC_HIP(S.get(&dub, items));
-    PHOBIC_HIP(hipMemcpyAsync(dw, hw.data(), items, hipMemcpyHostToDevice, st));
+    PHOBIC_HIP(hipMemcpyAsync(dw, hw, items, hipMemcpyHostToDevice, st));
     hipLaunchKernelGGL(k_batch_unary, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, dw, dub);
-    PHOBIC_HIP(hipMemcpyAsync(hub.data(), dub, items * 8, hipMemcpyDeviceToHost, st));
+    PHOBIC_HIP(hipMemcpyAsync(hub, dub, items * 8, hipMemcpyDeviceToHost, st));
     PHOBIC_HIP(hipStreamSynchronize(st));
   }
-  std::vector<uint64_t> hdrs((size_t)count * kHeaderWords), encw(items), ubase(items), ibase(count);
+  uint64_t *hdrs, *encw, *ubase, *ibase;  // pinned
+  PHOBIC_HIP(S.host(&hdrs, (uint64_t)count * kHeaderWords));
+  PHOBIC_HIP(S.host(&encw, items));
+  PHOBIC_HIP(S.host(&ubase, items));
+  PHOBIC_HIP(S.host(&ibase, (uint64_t)count));
   uint64_t total_words = 0;
   for (uint32_t t = 0; t < count; t++) {
     uint64_t data_bits = 0, unary_bits = 0;
@@ -2101,7 +2137,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
     const long long dmin = hmm[2 * t], dmax = hmm[2 * t + 1];
     const std::vector<uint64_t> h = make_header(desc[t].n, desc[t].K, B, prm, desc[t].n, dmin,
                                                 bit_length((uint64_t)(dmax - dmin)), data_bits, unary_bits, desc[t].R);
-    std::copy(h.begin(), h.end(), hdrs.begin() + (size_t)t * kHeaderWords);
+    std::copy(h.begin(), h.end(), hdrs + (size_t)t * kHeaderWords);
     ibase[t] = total_words;
     total_words += h[kHWords];
   }
@@ -2109,14 +2145,14 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   PHOBIC_HIP(hipMallocAsync(&big, total_words * 8, st));
   std::shared_ptr<void> shared(big, [](void* p) { (void)hipFreeAsync(p, nullptr); });
   uint64_t *dh, *de, *du, *dib;
-  PHOBIC_HIP(S.get(&dh, hdrs.size()));
+  PHOBIC_HIP(S.get(&dh, (uint64_t)count * kHeaderWords));
   PHOBIC_HIP(S.get(&de, items));
   PHOBIC_HIP(S.get(&du, items));
   PHOBIC_HIP(S.get(&dib, count));
-  PHOBIC_HIP(hipMemcpyAsync(dh, hdrs.data(), hdrs.size() * 8, hipMemcpyHostToDevice, st));
-  PHOBIC_HIP(hipMemcpyAsync(de, encw.data(), items * 8, hipMemcpyHostToDevice, st));
-  PHOBIC_HIP(hipMemcpyAsync(du, ubase.data(), items * 8, hipMemcpyHostToDevice, st));
-  PHOBIC_HIP(hipMemcpyAsync(dib, ibase.data(), count * 8, hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(dh, hdrs, (size_t)count * kHeaderWords * 8, hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(de, encw, items * 8, hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(du, ubase, items * 8, hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(dib, ibase, (size_t)count * 8, hipMemcpyHostToDevice, st));
   uint64_t* bufw = (uint64_t*)big;
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(total_words)), dim3(kBlock), 0, st, bufw, total_words, (uint64_t)0);
   hipLaunchKernelGGL(k_batch_heads, dim3(count), dim3(256), 0, st, dh, de, dib, B, bufw);
@@ -2148,7 +2184,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
     h->prm = prm;
     h->d_table = tbl.d_table;
     h->d_image = bufw + ibase[t];
-    h->header.assign(hdrs.begin() + (size_t)t * kHeaderWords, hdrs.begin() + (size_t)(t + 1) * kHeaderWords);
+    h->header.assign(hdrs + (size_t)t * kHeaderWords, hdrs + (size_t)(t + 1) * kHeaderWords);
     h->nwords = h->header[kHWords];
     h->shared = shared;
     h->info = info;
