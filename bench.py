@@ -401,8 +401,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU: this library has no multi-GPU path (how it would shard is described "
-              "in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU: this library has no multi-GPU path; partitions are independent, so a "
+              "multi-GPU build would give each GPU a range of partitions", file=sys.stderr)
         sys.exit(2)
     {"build_query": headline, "batch": batch_mode, "serve": serve_mode, "copy": copy_mode}[args.workload](args)
 

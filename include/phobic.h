@@ -58,12 +58,12 @@ typedef struct phobic_mphf phobic_mphf;
 
 /* Per-phase device times of one build, in milliseconds, from HIP events on the build stream. */
 typedef struct {
-  double hash_count_ms;  /* hash + partition histogram (a1, a2) */
-  double scan_ms;        /* partition offsets (a2) */
-  double scatter_ms;     /* hash + scatter into partitions (a1, a2) */
-  double bucket_sort_ms; /* bucket mapping and ordering (a3, a4) */
-  double search_ms;      /* pilot search (a5) */
-  double encode_ms;      /* statistics, packing, remap (a6, a8) */
+  double hash_count_ms;  /* hash + partition histogram */
+  double scan_ms;        /* partition offsets */
+  double scatter_ms;     /* hash + scatter into partitions */
+  double bucket_sort_ms; /* bucket mapping and ordering */
+  double search_ms;      /* pilot search */
+  double encode_ms;      /* statistics, packing, remap */
   double total_ms;       /* first kernel to last, host round trips included */
   uint64_t max_partition_keys;
   uint32_t max_bucket_keys;
@@ -126,7 +126,7 @@ phobic_status phobic_serialize(const phobic_mphf* h, void* h_buf, uint64_t* inou
 /* Rebuilds a handle on the current device from an image made by phobic_serialize. */
 phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, void* hip_stream, phobic_mphf** out);
 
-/* Stages a1-a2 alone, for parity checks: hashes and partitions the keys.  d_offsets gets K + 1
+/* Hashing and partitioning alone, for parity checks: hashes and partitions the keys.  d_offsets gets K + 1
  * key offsets, d_codes gets 2 n words: partition j's codes (hi, lo) at [2 d_offsets[j], 2
  * d_offsets[j+1]) in unspecified order.  K = max(1, ceil(n / P)). */
 phobic_status phobic_partition_u64(const uint64_t* d_keys, uint64_t n, const phobic_params* params,

@@ -78,8 +78,7 @@ def lib() -> C.CDLL:
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
-                               "python -m paper_2404_18497_amd.build_lib")
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2404_18497_amd.build_lib")
         L = C.CDLL(LIB_PATH)
         vp, u64, u32 = C.c_void_p, C.c_uint64, C.c_uint32
         P = C.POINTER(Params)
@@ -346,7 +345,7 @@ def deserialize(image: np.ndarray, stream=None) -> MPHF:
 
 
 def partition_u64(keys, prm: Params, stream=None):
-    """Stages a1-a2 only: (offsets[K+1], codes[n, 2]) as device tensors."""
+    """Hashing and partitioning only: (offsets[K+1], codes[n, 2]) as device tensors."""
     import torch
 
     n = keys.numel()

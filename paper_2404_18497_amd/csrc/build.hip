@@ -1,7 +1,7 @@
 // Construction of a PHOBIC MPHF on one MI355X (gfx950, wave64).
 //
 // Pipeline (one stream):
-//   k_hash_count_*  : hash every key (a1) and histogram its partition j = mulhi(hi, K) (a2)
+//   k_hash_count_*  : hash every key and histogram its partition j = mulhi(hi, K)
 //   k_scan_offsets  : one workgroup: partition key offsets and table offsets (prefix sums, Sec. 4)
 //   k_scatter_*     : hash again and scatter the 128-bit codes into their partition (order free)
 //   k_bucket_sort   : one workgroup per partition: bucket of every key by the tabulated beta_eps
@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "phobic_internal.h"
+#include "search.h"
 
 namespace phobic {
 namespace {
@@ -46,7 +47,7 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// a1 + a2: hashing and partitioning
+// Hashing and partitioning
 // ---------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_hash_count_u64(const uint64_t* __restrict__ keys, uint64_t n,
                                                            uint64_t seed, uint64_t K, uint32_t* __restrict__ cnt) {
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(1024) void k_scan_offsets(uint32_t* __restrict__ cn
 }
 
 // ---------------------------------------------------------------------------------------------
-// a3 + a4: bucket mapping and ordering, one workgroup (256 threads) per partition.
+// Bucket mapping and ordering, one workgroup (256 threads) per partition.
 // LDS: cnt[nbpad] counts then start offsets, key[nbpad] sort keys (size << 16 | id), rec[n_j]
 // per-key (bucket << 16 | rank in bucket).
 // ---------------------------------------------------------------------------------------------
@@ -238,7 +239,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2* __rest
 }
 
 // ---------------------------------------------------------------------------------------------
-// a1-a4, main path: coarse bins of G = 2^gshift consecutive partitions.
+// Hash, partition, bucket and order, main path: coarse bins of G = 2^gshift consecutive partitions.
 //
 //   k_coarse_count   : 512 workgroups, each over a contiguous range of keys, histogram the coarse bin
 //                      c = j >> gshift of every key in LDS; the row is saved and added to the bin
@@ -535,338 +536,7 @@ __global__ __launch_bounds__(1024) void k_table_offsets(const uint64_t* __restri
 }
 
 // ---------------------------------------------------------------------------------------------
-// a5: pilot search, one wavefront per partition, four partitions per workgroup.
-//
-// F2 holds the free-slot bitmap twice in a row (bit t and bit t + m both mean "slot t is free", in
-// 32-bit words), so the displacements [d, d + 64) of a key at position r are bits [r + d, r + d + 64)
-// of F2 with no wrap-around.  For one seed the lanes cover displacement windows [64 l, 64 l + 64);
-// each key of the bucket ANDs its shifted window into the lane's accumulator; when every
-// accumulator is zero no displacement of this seed works.  The lowest lane with a surviving bit
-// holds the smallest d, and seeds are tried in increasing order, so the first hit is the smallest
-// pilot p = s m + d (Sec. 4; the same minimum as the sequential nested loop, Sec. 4.2).
-//
-// The key loop is pure vector/LDS work: positions are kept encoded as e = (r >> 5) << 7 | (r & 31),
-// so (e >> 5) is the byte offset of the word holding bit r and the low five bits are the funnel
-// shift; the list is padded to a multiple of four with copies of its last entry (AND is
-// idempotent), and lanes whose window lies beyond m read in-bounds words into an accumulator that
-// is already zero.
-//
-// Two keys of a bucket at the same position under s rule out every d.  Buckets of more than
-// kSmallBucket keys test this first (scratch bitmap, atomic OR); smaller ones find it while marking
-// their slots (a slot already cleared by the same bucket) and undo the marks.  A repeat at s = 0
-// between equal fingerprints means the bucket can never be placed: PHOBIC_E_DUPLICATE.
-// ---------------------------------------------------------------------------------------------
-constexpr uint32_t kSmallBucket = 24;
-
-struct SearchArgs {
-  const uint64_t* fp;     // fingerprints in processing order, partition-contiguous
-  const uint64_t* off;    // key offsets, K + 1
-  const uint64_t* toff;   // table offsets, K + 1
-  const uint32_t* blist;  // per partition: (size << 16 | bucket) in processing order
-  const uint32_t* nbk;    // non-empty buckets per partition
-  uint32_t* pilots;       // encoder-major: pilots[i * K + j]
-  uint32_t* err;          // bit (1 << status) for every error met
-  uint64_t* taken;        // occupancy bitmap of all tables (alpha < 1), else null
-  uint64_t K;
-  uint64_t limit;
-  uint32_t B;
-  uint32_t f2_words;      // 32-bit words of F2 (multiple of 4)
-  uint32_t scr_words;     // 32-bit words of the collision scratch (multiple of 4)
-  uint32_t rb_cap;        // 32-bit position entries (multiple of 4)
-  uint32_t bl_cap;        // 32-bit bucket-list entries (multiple of 4)
-  uint32_t cm_cap;        // 64-bit collision masks
-  uint32_t wave_lds;      // bytes of LDS per wavefront (multiple of 16)
-  // several MPHFs at once: partition J belongs to MPHF owner[J], whose partitions start at
-  // Kbase[t] (K_t of them) and whose pilots start at B * Kbase[t]; null for a single MPHF
-  const uint32_t* owner;
-  const uint64_t* Kbase;
-  const uint64_t* Kt;
-  // persistent launch: partitions are taken grab at a time from *queue; null = one per wavefront
-  unsigned long long* queue;
-  uint32_t grab;
-  unsigned long long* fail_part;  // non-null: receives the lowest failing partition index (atomic min)
-};
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// Values that are the same on every lane of the wavefront, moved to scalar registers so that the
-// branches and loops that depend on them are scalar branches instead of exec-mask updates.
-__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
-  return ((uint64_t)uniform((uint32_t)(v >> 32)) << 32) | uniform((uint32_t)v);
-}
-__device__ __forceinline__ uint64_t lane_value64(uint64_t v, uint32_t lane) {
-  return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), lane) << 32) |
-         __builtin_amdgcn_readlane((uint32_t)v, lane);
-}
-
-__device__ __forceinline__ uint32_t enc_pos(uint32_t r) { return ((r >> 5) << 7) | (r & 31); }
-__device__ __forceinline__ uint32_t dec_pos(uint32_t e) { return ((e >> 7) << 5) | (e & 31); }
-
-// Marks the positions of rbuf[0..sz) in the scratch bitmap; cm[g] gets the lanes of group g whose
-// position was already marked.  Leaves the scratch clear.  Returns whether a position repeats.
-__device__ bool positions_repeat(uint32_t* scr, const uint32_t* rbuf, uint32_t sz, uint64_t* cm, uint32_t lane) {
-  bool any = false;
-  const uint32_t ng = (sz + 63) >> 6;
-  for (uint32_t g = 0; g < ng; g++) {
-    const uint32_t k = g * 64 + lane;
-    bool c = false;
-    if (k < sz) {
-      const uint32_t rr = dec_pos(rbuf[k]), bit = 1u << (rr & 31);
-      c = (atomicOr(&scr[rr >> 5], bit) & bit) != 0;
-    }
-    const uint64_t bm = __ballot(c);
-    if (lane == 0) cm[g] = bm;
-    any |= bm != 0;
-  }
-  wave_sync();
-  for (uint32_t k = lane; k < sz; k += 64) {
-    const uint32_t rr = dec_pos(rbuf[k]);
-    atomicAnd(&scr[rr >> 5], ~(1u << (rr & 31)));
-  }
-  wave_sync();
-  return any;
-}
-
-// After positions_repeat: whether a repeated position comes from two equal fingerprints.
-__device__ bool equal_fingerprints(const uint64_t* keys, const uint32_t* rbuf, uint32_t sz, const uint64_t* cm,
-                                   uint32_t lane) {
-  const uint32_t ng = (sz + 63) >> 6;
-  for (uint32_t g = 0; g < ng; g++) {
-    uint64_t bm = cm[g];
-    while (bm) {
-      const uint32_t c = g * 64 + (uint32_t)(__ffsll((long long)bm) - 1);
-      bm &= bm - 1;
-      const uint32_t rc = rbuf[c];
-      const uint64_t fc = keys[c];
-      bool f = false;
-      for (uint32_t k = lane; k < sz; k += 64)
-        if (k != c && rbuf[k] == rc) f |= keys[k] == fc;
-      if (__ballot(f)) return true;
-    }
-  }
-  return false;
-}
-
-// Positions of a bucket's keys under the seed value w, encoded into rbuf, padded to a multiple of
-// four with the last entry.  Returns lane k's position for k < 64 (the keys a small bucket marks).
-__device__ __forceinline__ uint32_t bucket_positions(uint32_t* rbuf, const uint64_t* keys, uint64_t f0, uint32_t sz,
-                                                     uint64_t w, uint32_t m, uint32_t lane) {
-  const uint32_t ng = (sz + 63) >> 6, szp = (sz + 3) & ~3u;
-  uint32_t r0 = 0;
-  for (uint32_t g = 0; g < ng; g++) {
-    const uint32_t k = g * 64 + lane;
-    uint32_t r = 0;
-    if (k < sz) {
-      r = pos_hash(g == 0 ? f0 : keys[k], w, m);
-      rbuf[k] = enc_pos(r);
-    }
-    if (g == 0) r0 = r;
-    if (g == ng - 1) {
-      const uint32_t last = __builtin_amdgcn_readlane(r, (sz - 1) & 63);
-      if (k >= sz && k < szp) rbuf[k] = enc_pos(last);
-    }
-  }
-  wave_sync();
-  return r0;
-}
-
-__device__ __forceinline__ void note_failure(const SearchArgs& a, uint64_t j, uint32_t status) {
-  atomicOr(a.err, 1u << status);
-  if (a.fail_part) atomicMin(a.fail_part, (unsigned long long)j);
-}
-
-// Places every bucket of partition j (global index).  Uniform across the wavefront.
-__device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, uint32_t lane) {
-  uint32_t* scr = F2 + a.f2_words;
-  uint32_t* rbuf = scr + a.scr_words;
-  uint32_t* bl = rbuf + a.rb_cap;
-  uint64_t* cm = (uint64_t*)(bl + a.bl_cap);
-
-  const uint64_t kb = uniform64(a.off[j]);
-  const uint32_t m = uniform((uint32_t)(a.toff[j + 1] - a.toff[j]));
-  const uint32_t twom = 2 * m;
-  for (uint32_t w = lane; w < a.f2_words; w += 64) {
-    const uint32_t lo = w * 32;
-    F2[w] = lo + 32 <= twom ? 0xFFFFFFFFu : (lo >= twom ? 0u : ((1u << (twom - lo)) - 1u));
-  }
-  for (uint32_t w = lane; w < a.scr_words; w += 64) scr[w] = 0;
-  const uint32_t nb = uniform(a.nbk[j]);
-  for (uint32_t x = lane; x < nb; x += 64) bl[x] = a.blist[j * a.B + x];
-  wave_sync();
-  const char* F2b = (const char*)F2;
-
-  // this lane's displacement window of the first pass (d0 = 0): its bits below m, its byte offset
-  const uint32_t dl0 = lane * 64;
-  const uint64_t acc_first = dl0 < m ? (m - dl0 >= 64 ? ~0ULL : ((1ULL << (m - dl0)) - 1)) : 0ULL;
-  const uint32_t loff_first = dl0 < m ? (dl0 >> 3) : 0u;
-
-  uint64_t kpos = kb;
-  uint32_t e = nb ? uniform(bl[0]) : 0;
-  uint64_t fnext = lane < (e >> 16) ? a.fp[kpos + lane] : 0;
-  bool overflow = false;
-  for (uint32_t r = 0; r < nb; r++) {
-    const uint32_t bid = e & 0xFFFF, sz = e >> 16;
-    const uint64_t* keys = a.fp + kpos;
-    const uint64_t f0 = fnext;
-    kpos += sz;
-    if (r + 1 < nb) {  // prefetch the next bucket's first 64 fingerprints
-      e = uniform(bl[r + 1]);
-      fnext = lane < (e >> 16) ? a.fp[kpos + lane] : 0;
-    }
-    const bool big = sz > kSmallBucket;
-    const uint32_t szp = (sz + 3) & ~3u;
-
-    if (overflow) {  // the partition has failed: only look for equal fingerprints
-      bucket_positions(rbuf, keys, f0, sz, kPhi64, m, lane);
-      if (positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
-        if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
-        return;
-      }
-      continue;
-    }
-
-    for (uint64_t s = 0;; s++) {
-      if (s * m > a.limit) {
-        overflow = true;
-        break;
-      }
-      const uint32_t rmine = bucket_positions(rbuf, keys, f0, sz, (s + 1) * kPhi64, m, lane);
-      if (big && positions_repeat(scr, rbuf, sz, cm, lane)) {
-        if (s == 0 && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
-          if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
-          return;
-        }
-        continue;
-      }
-
-      // displacement scan: the lowest d such that every key's slot (r + d) mod m is free
-      uint32_t d_found = 0xFFFFFFFFu;
-      for (uint32_t d0 = 0; d0 < m; d0 += 4096) {
-        uint64_t acc = acc_first;
-        uint32_t loff = loff_first;  // byte offset of this lane's window start
-        if (d0) {
-          const uint32_t dl = d0 + dl0;
-          const bool act = dl < m;
-          acc = act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL;
-          loff = act ? (dl >> 3) : 0u;
-        }
-        for (uint32_t k = 0; k < szp; k += 4) {
-          const uint4 e4 = *(const uint4*)(rbuf + k);
-          const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            const uint32_t* wp = (const uint32_t*)(F2b + (ev[t] >> 5) + loff);
-            const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
-            acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, ev[t]) << 32) |
-                   __builtin_amdgcn_alignbit(w1, w0, ev[t]);
-          }
-          if (__ballot(acc != 0) == 0) break;
-        }
-        const uint64_t bal = __ballot(acc != 0);
-        if (bal) {
-          const uint32_t L = (uint32_t)(__ffsll((long long)bal) - 1);
-          const uint64_t accL = lane_value64(acc, L);
-          d_found = d0 + L * 64 + (uint32_t)(__ffsll((long long)accL) - 1);
-          break;
-        }
-      }
-      if (d_found == 0xFFFFFFFFu) continue;
-      const uint64_t p = s * m + d_found;
-      if (p > a.limit) {
-        overflow = true;
-        break;
-      }
-      // mark the slots; a small bucket discovers here whether two of its keys share a slot
-      if (!big) {
-        bool mine = false;
-        uint32_t t = rmine + d_found;
-        if (t >= m) t -= m;
-        if (lane < sz) mine = (atomicAnd(&F2[t >> 5], ~(1u << (t & 31))) >> (t & 31)) & 1u;
-        wave_sync();
-        if (__ballot(lane < sz && !mine)) {
-          if (mine) atomicOr(&F2[t >> 5], 1u << (t & 31));  // undo
-          wave_sync();
-          if (s == 0 && positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
-            if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
-            return;
-          }
-          continue;
-        }
-        if (lane < sz) {
-          const uint32_t t2 = t + m;
-          atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
-        }
-      } else {
-        for (uint32_t k = lane; k < sz; k += 64) {
-          uint32_t t = dec_pos(rbuf[k]) + d_found;
-          if (t >= m) t -= m;
-          atomicAnd(&F2[t >> 5], ~(1u << (t & 31)));
-          const uint32_t t2 = t + m;
-          atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
-        }
-      }
-      if (lane == 0) {
-        if (a.owner) {
-          const uint32_t t = a.owner[j];
-          const uint64_t jb = a.Kbase[t];
-          a.pilots[(uint64_t)a.B * jb + (uint64_t)bid * a.Kt[t] + (j - jb)] = (uint32_t)p;
-        } else {
-          a.pilots[(uint64_t)bid * a.K + j] = (uint32_t)p;
-        }
-      }
-      wave_sync();
-      break;
-    }
-  }
-  if (overflow) {
-    if (lane == 0) note_failure(a, j, PHOBIC_E_PILOT_OVERFLOW);
-    return;
-  }
-  if (a.taken) {
-    const uint64_t tb = a.toff[j];
-    for (uint32_t w = lane; w * 32 < m; w += 64) {
-      const uint32_t nbits = min(32u, m - w * 32);
-      const uint32_t busy = ~F2[w] & (nbits == 32 ? 0xFFFFFFFFu : ((1u << nbits) - 1));
-      put_bits_atomic(a.taken, tb + (uint64_t)w * 32, busy, nbits);
-    }
-  }
-}
-
-// One wavefront per partition.
-template <int kWaves>
-__global__ __launch_bounds__(64 * kWaves) void k_search(SearchArgs a) {
-  extern __shared__ __align__(16) uint32_t lds32[];
-  const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const uint64_t j = (uint64_t)blockIdx.x * kWaves + wave;
-  if (j >= a.K) return;
-  search_partition(a, j, lds32 + (size_t)wave * (a.wave_lds / 4), lane);
-}
-
-// Persistent: every wavefront takes `grab` partitions at a time from the queue until none is left.
-template <int kWaves>
-__global__ __launch_bounds__(64 * kWaves) void k_search_persistent(SearchArgs a) {
-  extern __shared__ __align__(16) uint32_t lds32[];
-  const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  uint32_t* F2 = lds32 + (size_t)wave * (a.wave_lds / 4);
-  for (;;) {
-    unsigned long long item = 0;
-    if (lane == 0) item = atomicAdd(a.queue, (unsigned long long)a.grab);
-    item = lane_value64(item, 0);
-    if (item >= a.K) break;
-    const uint64_t end = min((uint64_t)item + a.grab, a.K);
-    for (uint64_t j = item; j < end; j++) {
-      search_partition(a, j, F2, lane);
-      wave_sync();
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------------------------
-// a6: interleaved coding
+// Interleaved coding
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -1044,7 +714,7 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __
 }
 
 // ---------------------------------------------------------------------------------------------
-// a8: remap for alpha < 1.  Table positions g >= n that hold a key, ascending, are paired with the
+// Remap for alpha < 1.  Table positions g >= n that hold a key, ascending, are paired with the
 // free positions < n, ascending; entries of unoccupied g >= n repeat the previous value (0 first).
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t low_mask(uint32_t b) { return b >= 64 ? ~0ULL : ((1ULL << b) - 1); }
@@ -1119,51 +789,6 @@ __global__ __launch_bounds__(kBlock) void k_remap_fill(const uint64_t* __restric
     const uint64_t r = ocx[w] + __popcll(taken[w] & sel);  // occupied positions in [n, g]
     const uint64_t v = r ? freeslot[r - 1] : 0;
     put_bits_atomic(sec, (g - n) * wr, v, wr);
-  }
-}
-
-// ---------------------------------------------------------------------------------------------
-// Search launch shape
-// ---------------------------------------------------------------------------------------------
-std::mutex g_cfg_mu;
-phobic_search_config g_cfg = {2, 0, 1, 0};  // two partitions per workgroup, one per wavefront
-
-phobic_search_config search_config() {
-  std::lock_guard<std::mutex> lock(g_cfg_mu);
-  return g_cfg;
-}
-
-template <int W>
-hipError_t launch_search_w(SearchArgs& sa, uint64_t items, const phobic_search_config& cfg, hipStream_t st,
-                           unsigned long long* queue) {
-  const size_t lds = (size_t)sa.wave_lds * W;
-  if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
-  if (cfg.groups_per_cu == 0) {
-    sa.queue = nullptr;
-    hipLaunchKernelGGL(k_search<W>, dim3((uint32_t)((items + W - 1) / W)), dim3(64 * W), lds, st, sa);
-    return hipGetLastError();
-  }
-  int dev = 0, cus = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (e != hipSuccess) return e;
-  sa.queue = queue;
-  sa.grab = std::max<uint32_t>(1, cfg.items_per_grab);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, (uint64_t*)queue, (uint64_t)1, (uint64_t)0);
-  const uint64_t groups = std::min<uint64_t>((uint64_t)cus * cfg.groups_per_cu, (items + W - 1) / W);
-  hipLaunchKernelGGL(k_search_persistent<W>, dim3((uint32_t)std::max<uint64_t>(groups, 1)), dim3(64 * W), lds, st,
-                     sa);
-  return hipGetLastError();
-}
-
-// Launches the search over `items` partitions (sa.K) with the configured shape.
-hipError_t launch_search(SearchArgs& sa, uint64_t items, hipStream_t st, unsigned long long* queue) {
-  const phobic_search_config cfg = search_config();
-  switch (cfg.waves_per_group) {
-    case 1: return launch_search_w<1>(sa, items, cfg, st, queue);
-    case 2: return launch_search_w<2>(sa, items, cfg, st, queue);
-    case 8: return launch_search_w<8>(sa, items, cfg, st, queue);
-    default: return launch_search_w<4>(sa, items, cfg, st, queue);
   }
 }
 
@@ -1388,7 +1013,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     if (ts != PHOBIC_OK) return ts;
   }
 
-  // ---- a1-a4: hash, partition, bucket, order -------------------------------------------------
+  // ---- hash, partition, bucket, order -----------------------------------------------------------
   uint64_t *off, *toff = nullptr, *sortedf, *d64;
   uint32_t *blist, *nbk, *pilots, *err;  // err[0] error bits, [1] max bucket, [2] max n_j, [3] max m_j
   PHOBIC_HIP(S.get(&off, K + 1));
@@ -1523,7 +1148,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   PHOBIC_HIP(hipStreamSynchronize(st));
   if (hinfo[0] & (1u << PHOBIC_E_CAPACITY))
     return fail(PHOBIC_E_CAPACITY, "a group of partitions exceeds the LDS of the bucket-sort workgroup");
-  if (part_offsets_out) {  // stages a1-a2 only
+  if (part_offsets_out) {  // hashing and partitioning only
     PHOBIC_HIP(hipMemcpyAsync(part_offsets_out, off, (K + 1) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
     PHOBIC_HIP(hipStreamSynchronize(st));
     return PHOBIC_OK;
@@ -1538,7 +1163,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     return fail(PHOBIC_E_CAPACITY, "a partition needs " + std::to_string(max_m) + " slots; the device path holds " +
                                        std::to_string(kMaxTableSlots));
 
-  // a5
+  // pilot search
   uint64_t* taken = nullptr;
   const uint64_t taken_words = (total + 63) / 64 + 1;
   if (total > n) {
@@ -1577,7 +1202,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   PHOBIC_HIP(launch_search(sa, K, st, queue));
   tm.mark();  // 6
 
-  // a6: statistics -> host parameters
+  // encoding: statistics -> host parameters
   uint64_t* shsum;
   uint32_t* vmax;
   long long* dmm;
@@ -2008,7 +1633,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err, (uint64_t)4, 0u);
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err + 4, (uint64_t)2, 0xFFFFFFFFu);
 
-  // a1-a4 chunk by chunk
+  // hash, partition, bucket and order, chunk by chunk
   tm.mark();  // 0
   for (const Chunk& c : chunks) {
     const uint64_t Jc0 = desc[c.t0].Kbase, Jc1 = desc[c.t1 - 1].Kbase + desc[c.t1 - 1].K;
@@ -2039,7 +1664,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
     return fail(PHOBIC_E_CAPACITY, "a partition holds " + std::to_string(hinfo[2]) + " keys; the device path holds " +
                                        std::to_string(kMaxTableSlots));
 
-  // a5: one search over every (MPHF, partition)
+  // one pilot search over every (MPHF, partition)
   SearchArgs sa;
   sa.fp = fp;
   sa.off = off;
@@ -2068,7 +1693,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   PHOBIC_HIP(launch_search(sa, Ktot, st, queue));
   tm.mark();  // 3
 
-  // a6: statistics, parameters on the host, then packing
+  // encoding: statistics, parameters on the host, then packing
   const uint64_t items = (uint64_t)count * B;
   uint64_t* sum;
   uint32_t* mx;
@@ -2219,25 +1844,6 @@ extern "C" phobic_status phobic_partition_u64(const uint64_t* d_keys, uint64_t n
   if (!d_offsets || (n && !d_codes)) return fail(PHOBIC_E_INVALID, "null output pointer");
   BuildInput in{Src::U64, d_keys, nullptr, nullptr, n};
   return build_impl(in, params, (hipStream_t)hip_stream, nullptr, d_offsets, d_codes);
-}
-
-extern "C" phobic_status phobic_set_search_config(const phobic_search_config* cfg) {
-  if (!cfg) return fail(PHOBIC_E_INVALID, "cfg is null");
-  const uint32_t w = cfg->waves_per_group;
-  if (w != 1 && w != 2 && w != 4 && w != 8) return fail(PHOBIC_E_INVALID, "waves_per_group must be 1, 2, 4 or 8");
-  if (cfg->groups_per_cu > 64) return fail(PHOBIC_E_INVALID, "groups_per_cu must be at most 64");
-  if (cfg->groups_per_cu && (cfg->items_per_grab < 1 || cfg->items_per_grab > 4096))
-    return fail(PHOBIC_E_INVALID, "items_per_grab must be in [1, 4096]");
-  std::lock_guard<std::mutex> lock(g_cfg_mu);
-  g_cfg = *cfg;
-  g_cfg.reserved = 0;
-  return PHOBIC_OK;
-}
-
-extern "C" phobic_status phobic_get_search_config(phobic_search_config* out) {
-  if (!out) return fail(PHOBIC_E_INVALID, "out is null");
-  *out = search_config();
-  return PHOBIC_OK;
 }
 
 extern "C" phobic_status phobic_build_batch_u64(const uint64_t* const* h_key_ptrs, const uint64_t* h_counts,

@@ -1,0 +1,46 @@
+// Pilot search (Sec. 4, Sec. 4.2; Alg. 1): the interface between the build orchestration and the
+// search kernels.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "phobic.h"
+
+namespace phobic {
+
+struct SearchArgs {
+  const uint64_t* fp;     // fingerprints in processing order, partition-contiguous
+  const uint64_t* off;    // key offsets, K + 1
+  const uint64_t* toff;   // table offsets, K + 1
+  const uint32_t* blist;  // per partition: (size << 16 | bucket) in processing order
+  const uint32_t* nbk;    // non-empty buckets per partition
+  uint32_t* pilots;       // encoder-major: pilots[i * K + j]
+  uint32_t* err;          // bit (1 << status) for every error met
+  uint64_t* taken;        // occupancy bitmap of all tables (alpha < 1), else null
+  uint64_t K;
+  uint64_t limit;
+  uint32_t B;
+  uint32_t f2_words;      // 32-bit words of F2 (multiple of 4)
+  uint32_t scr_words;     // 32-bit words of the collision scratch (multiple of 4)
+  uint32_t rb_cap;        // 32-bit position entries (multiple of 4)
+  uint32_t bl_cap;        // 32-bit bucket-list entries (multiple of 4)
+  uint32_t cm_cap;        // 64-bit collision masks
+  uint32_t wave_lds;      // bytes of LDS per wavefront (multiple of 16)
+  // several MPHFs at once: partition J belongs to MPHF owner[J], whose partitions start at
+  // Kbase[t] (K_t of them) and whose pilots start at B * Kbase[t]; null for a single MPHF
+  const uint32_t* owner;
+  const uint64_t* Kbase;
+  const uint64_t* Kt;
+  // persistent launch: partitions are taken grab at a time from *queue; null = one per wavefront
+  unsigned long long* queue;
+  uint32_t grab;
+  unsigned long long* fail_part;  // non-null: receives the lowest failing partition index (atomic min)
+};
+
+// Launches the search over `items` partitions (sa.K of them in the partition index space) on the
+// stream with the configured launch shape; `queue` is one device word used by the persistent shape.
+hipError_t launch_search(SearchArgs& sa, uint64_t items, hipStream_t st, unsigned long long* queue);
+
+}  // namespace phobic

@@ -1,7 +1,8 @@
 """GPU parity: the HIP library against the CPU oracle, bit for bit, through the C ABI.
 
-Compared on the same seeded keys: partition offsets and per-partition code multisets (a1-a2), the
-pilot array (a3-a5), the serialized image word for word (a6), and query outputs (a7); at the
+Compared on the same seeded keys: partition offsets and per-partition code multisets (hashing and
+partitioning), the pilot array (bucketing, ordering, search), the serialized image word for word
+(encoding), and query outputs; at the
 1M-key workload in full, on edge shapes, and at the 100M-key benchmark workload on sampled
 partitions and keys plus properties that hold at any size (bijection onto [0, n)).
 """
