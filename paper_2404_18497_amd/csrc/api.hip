@@ -287,10 +287,8 @@ extern "C" phobic_status phobic_get_pilots(const phobic_mphf* h, uint32_t* h_out
   if (!h->d_pilots) return fail(PHOBIC_E_INVALID, "the handle was built without PHOBIC_FLAG_KEEP_PILOTS");
   const uint64_t K = h->K, B = h->B;
   if (cap < K * B) return fail(PHOBIC_E_INVALID, "output buffer too small");
-  std::vector<uint32_t> em(K * B);
-  PHOBIC_HIP(hipMemcpy(em.data(), h->d_pilots, em.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
-  for (uint64_t i = 0; i < B; i++)
-    for (uint64_t j = 0; j < K; j++) h_out[j * B + i] = em[i * K + j];
+  // the kept array is partition-major already
+  PHOBIC_HIP(hipMemcpy(h_out, h->d_pilots, K * B * sizeof(uint32_t), hipMemcpyDeviceToHost));
   return PHOBIC_OK;
 }
 

@@ -46,6 +46,28 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
     p[i] = v;
 }
 
+// out[c][r] = in[r][c] for an R x Cn array of u32, in 64 x 64 tiles staged through LDS so that both
+// the reads (along a row of `in`) and the writes (along a row of `out`) are contiguous.
+constexpr uint32_t kTile = 64;
+__global__ __launch_bounds__(kTile * kTile / 16) void k_transpose_u32(const uint32_t* __restrict__ in, uint64_t R,
+                                                                      uint64_t Cn, uint32_t* __restrict__ out) {
+  __shared__ uint32_t tile[kTile][kTile + 1];
+  const uint64_t tr = (R + kTile - 1) / kTile, tc = (Cn + kTile - 1) / kTile;
+  for (uint64_t t = blockIdx.x; t < tr * tc; t += gridDim.x) {
+    const uint64_t r0 = (t / tc) * kTile, c0 = (t % tc) * kTile;
+    for (uint32_t y = threadIdx.y; y < kTile; y += kTile / 16) {
+      const uint64_t r = r0 + y, c = c0 + threadIdx.x;
+      tile[y][threadIdx.x] = (r < R && c < Cn) ? in[r * Cn + c] : 0u;
+    }
+    __syncthreads();
+    for (uint32_t y = threadIdx.y; y < kTile; y += kTile / 16) {
+      const uint64_t c = c0 + y, r = r0 + threadIdx.x;
+      if (c < Cn && r < R) out[c * R + r] = tile[threadIdx.x][y];
+    }
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // Hashing and partitioning
 // ---------------------------------------------------------------------------------------------
@@ -1022,13 +1044,14 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   PHOBIC_HIP(S.get(&nbk, K));
   PHOBIC_HIP(S.get(&err, 4));
   PHOBIC_HIP(S.get(&d64, 8));
+  uint32_t* pilots_pm;  // partition-major rows from the search (every row written whole)
   if (keep) {
     PHOBIC_HIP(hipMalloc(&h->d_pilots, std::max<uint64_t>(1, K * B) * sizeof(uint32_t)));
-    pilots = h->d_pilots;
+    pilots_pm = h->d_pilots;
   } else {
-    PHOBIC_HIP(S.get(&pilots, K * B));
+    PHOBIC_HIP(S.get(&pilots_pm, K * B));
   }
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(K * B)), dim3(kBlock), 0, st, pilots, K * B, 0u);
+  PHOBIC_HIP(S.get(&pilots, K * B));  // encoder-major copy for the encoders
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err, (uint64_t)4, 0u);
   hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, d64, (uint64_t)8, (uint64_t)0);
   const uint32_t nbpad = next_pow2(B);
@@ -1177,7 +1200,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   sa.toff = toff;
   sa.blist = blist;
   sa.nbk = nbk;
-  sa.pilots = pilots;
+  sa.pilots = pilots_pm;
   sa.err = err;
   sa.taken = taken;
   sa.K = K;
@@ -1191,7 +1214,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   sa.rb_cap = up4(mb) + 4;
   sa.bl_cap = up4(B);
   sa.cm_cap = (mb + 63) / 64 + 1;
-  sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
+  sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
   sa.owner = nullptr;
   sa.Kbase = nullptr;
   sa.Kt = nullptr;
@@ -1202,7 +1225,13 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   PHOBIC_HIP(launch_search(sa, K, st, queue));
   tm.mark();  // 6
 
-  // encoding: statistics -> host parameters
+  // encoding: the encoders read column i (bucket i of every partition), so transpose first
+  {
+    const uint64_t tiles = ((K + kTile - 1) / kTile) * ((B + kTile - 1) / kTile);
+    hipLaunchKernelGGL(k_transpose_u32, dim3((uint32_t)std::min<uint64_t>(tiles, 65536)), dim3(kTile, kTile / 16),
+                       0, st, pilots_pm, K, (uint64_t)B, pilots);
+  }
+  // statistics -> host parameters
   uint64_t* shsum;
   uint32_t* vmax;
   long long* dmm;
@@ -1684,7 +1713,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   sa.rb_cap = up4(mb) + 4;
   sa.bl_cap = up4(B);
   sa.cm_cap = (mb + 63) / 64 + 1;
-  sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
+  sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
   sa.owner = owner;
   sa.Kbase = d_Kbase;
   sa.Kt = d_Kt;

@@ -55,7 +55,7 @@ struct phobic_mphf {
   uint64_t nwords = 0;
   std::vector<uint64_t> header;   // host copy of the header words
   uint64_t* d_table = nullptr;   // borrowed from the per-device table cache
-  uint32_t* d_pilots = nullptr;   // encoder-major (i * K + j), only with PHOBIC_FLAG_KEEP_PILOTS
+  uint32_t* d_pilots = nullptr;   // partition-major (j * B + i), only with PHOBIC_FLAG_KEEP_PILOTS
   phobic_build_info info{};
   phobic::QueryArgs qa{};
   std::shared_ptr<void> shared;   // set when d_image lives inside one allocation shared by a batch

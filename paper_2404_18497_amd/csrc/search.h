@@ -16,7 +16,7 @@ struct SearchArgs {
   const uint64_t* toff;   // table offsets, K + 1
   const uint32_t* blist;  // per partition: (size << 16 | bucket) in processing order
   const uint32_t* nbk;    // non-empty buckets per partition
-  uint32_t* pilots;       // encoder-major: pilots[i * K + j]
+  uint32_t* pilots;       // one MPHF: partition-major, pilots[j * B + i]; several: see owner
   uint32_t* err;          // bit (1 << status) for every error met
   uint64_t* taken;        // occupancy bitmap of all tables (alpha < 1), else null
   uint64_t K;
@@ -25,9 +25,10 @@ struct SearchArgs {
   uint32_t f2_words;      // 32-bit words of F2 (multiple of 4)
   uint32_t scr_words;     // 32-bit words of the collision scratch (multiple of 4)
   uint32_t rb_cap;        // 32-bit position entries (multiple of 4)
-  uint32_t bl_cap;        // 32-bit bucket-list entries (multiple of 4)
+  uint32_t bl_cap;        // 32-bit bucket-list entries (multiple of 4); also the size of the pilot row
   uint32_t cm_cap;        // 64-bit collision masks
-  uint32_t wave_lds;      // bytes of LDS per wavefront (multiple of 16)
+  uint32_t wave_lds;      // bytes of LDS per wavefront (multiple of 16): F2, scratch, positions,
+                          // bucket list, pilot row, collision masks
   // several MPHFs at once: partition J belongs to MPHF owner[J], whose partitions start at
   // Kbase[t] (K_t of them) and whose pilots start at B * Kbase[t]; null for a single MPHF
   const uint32_t* owner;

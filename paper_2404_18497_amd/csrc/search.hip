@@ -140,7 +140,8 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   uint32_t* scr = F2 + a.f2_words;
   uint32_t* rbuf = scr + a.scr_words;
   uint32_t* bl = rbuf + a.rb_cap;
-  uint64_t* cm = (uint64_t*)(bl + a.bl_cap);
+  uint32_t* pil = bl + a.bl_cap;  // the partition's pilots, by bucket index
+  uint64_t* cm = (uint64_t*)(pil + a.bl_cap);
 
   const uint64_t kb = uniform64(a.off[j]);
   const uint32_t m = uniform((uint32_t)(a.toff[j + 1] - a.toff[j]));
@@ -152,6 +153,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   for (uint32_t w = lane; w < a.scr_words; w += 64) scr[w] = 0;
   const uint32_t nb = uniform(a.nbk[j]);
   for (uint32_t x = lane; x < nb; x += 64) bl[x] = a.blist[j * a.B + x];
+  for (uint32_t x = lane; x < a.B; x += 64) pil[x] = 0;  // empty buckets keep pilot 0
   wave_sync();
   const char* F2b = (const char*)F2;
 
@@ -160,19 +162,35 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   const uint64_t acc_first = dl0 < m ? (m - dl0 >= 64 ? ~0ULL : ((1ULL << (m - dl0)) - 1)) : 0ULL;
   const uint32_t loff_first = dl0 < m ? (dl0 >> 3) : 0u;
 
-  uint64_t kpos = kb;
-  uint32_t e = nb ? uniform(bl[0]) : 0;
-  uint64_t fnext = lane < (e >> 16) ? a.fp[kpos + lane] : 0;
+  // Fingerprints arrive through a sliding window: lane l of win0 holds key wbase + l of the partition
+  // (processing order), win1 the next 64.  The keys of consecutive buckets are consecutive, so one
+  // load serves many small buckets, and the next window is in flight while the current one is used.
+  const uint32_t nj = uniform((uint32_t)(a.off[j + 1] - kb));
+  const uint64_t smax = m ? a.limit / m : 0;  // s m > limit exactly when s > floor(limit / m)
+  const uint32_t dlast = m ? (uint32_t)(a.limit - smax * m) : 0;  // largest d allowed with s = smax
+  uint32_t wbase = 0, o = 0;  // o: first key of the current bucket
+  uint64_t win0 = lane < nj ? a.fp[kb + lane] : 0;
+  uint64_t win1 = 64 + lane < nj ? a.fp[kb + 64 + lane] : 0;
   bool overflow = false;
   for (uint32_t r = 0; r < nb; r++) {
+    const uint32_t e = uniform(bl[r]);
     const uint32_t bid = e & 0xFFFF, sz = e >> 16;
-    const uint64_t* keys = a.fp + kpos;
-    const uint64_t f0 = fnext;
-    kpos += sz;
-    if (r + 1 < nb) {  // prefetch the next bucket's first 64 fingerprints
-      e = uniform(bl[r + 1]);
-      fnext = lane < (e >> 16) ? a.fp[kpos + lane] : 0;
+    const uint64_t* keys = a.fp + kb + o;
+    if (o >= wbase + 64) {
+      if (o < wbase + 128) {
+        win0 = win1;
+        wbase += 64;
+      } else {  // past both windows (after a big bucket)
+        wbase = o;
+        win0 = wbase + lane < nj ? a.fp[kb + wbase + lane] : 0;
+      }
+      win1 = wbase + 64 + lane < nj ? a.fp[kb + wbase + 64 + lane] : 0;
     }
+    // key k < 64 of the bucket is window entry o - wbase + k < 128
+    const uint32_t widx = o - wbase + lane;
+    const uint64_t f0a = __shfl(win0, (int)(widx & 63)), f0b = __shfl(win1, (int)(widx & 63));
+    const uint64_t f0 = widx < 64 ? f0a : f0b;
+    o += sz;
     const bool big = sz > kSmallBucket;
     const uint32_t szp = (sz + 3) & ~3u;
 
@@ -186,7 +204,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
     }
 
     for (uint64_t s = 0;; s++) {
-      if (s * m > a.limit) {
+      if (s > smax) {  // every pilot s m + d of this seed exceeds the limit
         overflow = true;
         break;
       }
@@ -232,7 +250,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       }
       if (d_found == 0xFFFFFFFFu) continue;
       const uint64_t p = s * m + d_found;
-      if (p > a.limit) {
+      if (s == smax && d_found > dlast) {  // p > limit, with s <= smax
         overflow = true;
         break;
       }
@@ -265,15 +283,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
           atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
         }
       }
-      if (lane == 0) {
-        if (a.owner) {
-          const uint32_t t = a.owner[j];
-          const uint64_t jb = a.Kbase[t];
-          a.pilots[(uint64_t)a.B * jb + (uint64_t)bid * a.Kt[t] + (j - jb)] = (uint32_t)p;
-        } else {
-          a.pilots[(uint64_t)bid * a.K + j] = (uint32_t)p;
-        }
-      }
+      if (lane == 0) pil[bid] = (uint32_t)p;
       wave_sync();
       break;
     }
@@ -281,6 +291,17 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   if (overflow) {
     if (lane == 0) note_failure(a, j, PHOBIC_E_PILOT_OVERFLOW);
     return;
+  }
+  wave_sync();
+  if (a.owner) {  // several MPHFs: MPHF t's pilots, encoder-major, at B Kbase_t (zero-filled before)
+    const uint32_t t = a.owner[j];
+    const uint64_t jb = a.Kbase[t], kt = a.Kt[t];
+    for (uint32_t x = lane; x < a.B; x += 64) {
+      const uint32_t v = pil[x];
+      if (v) a.pilots[(uint64_t)a.B * jb + (uint64_t)x * kt + (j - jb)] = v;
+    }
+  } else {  // one MPHF: row j of the partition-major array, written whole
+    for (uint32_t x = lane; x < a.B; x += 64) a.pilots[j * a.B + x] = pil[x];
   }
   if (a.taken) {
     const uint64_t tb = a.toff[j];
