@@ -58,6 +58,7 @@ def lib():
         L.phobic_ref_query_u64.argtypes = [vp, u64p, C.c_uint64, u64p]
         L.phobic_ref_query_str.argtypes = [vp, u8p, u64p, C.c_uint64, u64p]
         L.phobic_ref_query_image_u64.argtypes = [u64p, C.c_uint64, u64p, C.c_uint64, u64p]
+        L.phobic_ref_query_image_str.argtypes = [u64p, C.c_uint64, u8p, u64p, C.c_uint64, u64p]
         L.phobic_ref_num_words.argtypes = [vp]
         L.phobic_ref_num_words.restype = C.c_uint64
         L.phobic_ref_words.argtypes = [vp]
@@ -220,6 +221,18 @@ def query_image_u64(image: np.ndarray, keys: np.ndarray) -> np.ndarray:
     out = np.zeros(keys.size, dtype=np.uint64)
     st = lib().phobic_ref_query_image_u64(_p(image, C.c_uint64), image.size, _p(keys, C.c_uint64), keys.size,
                                           _p(out, C.c_uint64))
+    if st != 0:
+        raise OracleError(st)
+    return out
+
+
+def query_image_str(image: np.ndarray, buf: np.ndarray, offs: np.ndarray) -> np.ndarray:
+    image = np.ascontiguousarray(image, dtype=np.uint64)
+    buf = np.ascontiguousarray(buf, dtype=np.uint8)
+    offs = np.ascontiguousarray(offs, dtype=np.uint64)
+    out = np.zeros(offs.size - 1, dtype=np.uint64)
+    st = lib().phobic_ref_query_image_str(_p(image, C.c_uint64), image.size, _p(buf, C.c_uint8), _p(offs, C.c_uint64),
+                                          offs.size - 1, _p(out, C.c_uint64))
     if st != 0:
         raise OracleError(st)
     return out

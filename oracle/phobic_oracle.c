@@ -807,6 +807,20 @@ void phobic_ref_query_str(const ref_mphf *h, const uint8_t *bytes, const uint64_
   }
 }
 
+/* query straight from an image (e.g. one the GPU library serialized), byte-string keys */
+int phobic_ref_query_image_str(const uint64_t *words, uint64_t nwords, const uint8_t *bytes, const uint64_t *offs,
+                               uint64_t n, uint64_t *out) {
+  if (nwords < HDR_WORDS || words[H_MAGIC] != MAGIC || words[H_WORDS] != nwords) return REF_E_FORMAT;
+  uint64_t T[TABLE_SIZE + 1];
+  image_table(words, T);
+  for (uint64_t i = 0; i < n; i++) {
+    uint64_t hi, lo;
+    hash_str(bytes + offs[i], offs[i + 1] - offs[i], words[H_SEED], &hi, &lo);
+    out[i] = query_hash(words, T, hi, lo);
+  }
+  return REF_OK;
+}
+
 /* query straight from an image (e.g. one the GPU library serialized) */
 int phobic_ref_query_image_u64(const uint64_t *words, uint64_t nwords, const uint64_t *keys, uint64_t n,
                                uint64_t *out) {

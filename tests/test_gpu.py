@@ -235,6 +235,60 @@ def test_full_size_100m_sampled(torch):
     assert 1.75 < bits < 1.9
 
 
+@pytest.fixture(scope="module")
+def strings_100m():
+    _say("100M strings: generate")
+    buf, offs = synth.ascii_strings(100_000_000, 3)
+    _say("100M strings: oracle hashes")
+    hi, lo = oracle.hash_str(buf, offs, 0x5EED)
+    return buf, offs, hi, lo
+
+
+@pytest.mark.parametrize("alpha", [(1, 1), (99, 100)])
+def test_full_size_strings_100m_sampled(torch, strings_100m, alpha):
+    """The 100M-string workload (lengths 10-50, [a-z0-9], lambda 7) with alpha 1 and 0.99: bijection
+    over all strings; pilots of sampled partitions against the oracle's search on the oracle's hashes
+    of their members; sampled queries against the oracle reading the GPU image."""
+    buf, offs, hi, lo = strings_100m
+    n = offs.size - 1
+    db, do = torch.from_numpy(buf).cuda(), _dev(torch, offs)
+    prm = binding.params(lam=7.0, alpha=alpha, keep_pilots=True)
+    _say("100M strings: build", alpha)
+    g = binding.build_str(db, do, prm)
+    pos = g.query_str(db, do)
+    cnt = torch.zeros(n, dtype=torch.int32, device=db.device)
+    cnt.index_add_(0, pos, torch.ones(n, dtype=torch.int32, device=db.device))
+    assert int(cnt.min()) == 1 and int(cnt.max()) == 1, "not a bijection onto [0, n)"
+    del cnt
+    _say("100M strings: sampled partitions")
+    K = g.K
+    part = ((hi >> np.uint64(32)) * np.uint64(K)
+            + (((hi & np.uint64(0xFFFFFFFF)) * np.uint64(K)) >> np.uint64(32))) >> np.uint64(32)
+    pil = g.pilots()
+    rp = oracle.params(lam=7.0, alpha=alpha)
+    rng = np.random.default_rng(5)
+    for j in rng.integers(0, K, 12):
+        idx = np.nonzero(part == np.uint64(j))[0]
+        m = -(-idx.size * alpha[1] // alpha[0])  # table slots ceil(n_j / alpha)
+        want, _ = oracle.search_partition(hi[idx], lo[idx], m, rp)
+        assert np.array_equal(pil[j], want), f"partition {j}"
+    del part
+    _say("100M strings: sampled queries vs oracle decoding of the image")
+    sample = np.sort(rng.integers(0, n, 100_000))
+    lens = (offs[sample + 1] - offs[sample]).astype(np.int64)
+    sub_offs = np.zeros(sample.size + 1, dtype=np.uint64)
+    np.cumsum(lens, out=sub_offs[1:])
+    idx = np.repeat(offs[sample].astype(np.int64), lens) + (np.arange(int(sub_offs[-1])) -
+                                                            np.repeat(sub_offs[:-1].astype(np.int64), lens))
+    got = pos[torch.from_numpy(sample).cuda()].cpu().numpy().view(np.uint64)
+    assert np.array_equal(oracle.query_image_str(g.serialize(), buf[idx], sub_offs), got)
+    bits = g.size_bits() / n
+    _say("100M strings: bits/key", bits)
+    # the remap table (alpha < 1) adds (T - n) / n entries of bitlen(n - 1) bits per key
+    remap = (-(-n * alpha[1] // alpha[0]) - n) / n * (n - 1).bit_length()
+    assert 1.7 + remap < bits < 1.9 + remap
+
+
 BATCH_SIZES = [0, 1, 2, 5, 63, 2500, 2501, 10_007, 50_000, 123_456, 7, 300_000, 1, 0, 40_000]
 
 

@@ -207,6 +207,15 @@ def test_bijection_nonminimal_remap(ref, alpha):
             assert _is_perm(h.query_u64(keys), n), (n, P, alpha)
 
 
+def test_strings_bijection_and_image_query(ref):
+    buf, offs = synth.ascii_strings(20_000, 31)
+    for alpha in [(1, 1), (99, 100)]:
+        h = ref.build_str(buf, offs, ref.params(alpha=alpha, partition_size=500))
+        pos = h.query_str(buf, offs)
+        assert _is_perm(pos, offs.size - 1), alpha
+        assert np.array_equal(ref.query_image_str(h.image(), buf, offs), pos), alpha
+
+
 def _replay_and_check_minimal(ref, keys, prm):
     """Re-derive every bucket's processing order and taken set, and check by brute force over all
     p' <= p that the oracle's pilot p is the smallest admissible one."""
