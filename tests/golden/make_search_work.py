@@ -4,10 +4,14 @@ workload (100,000,000 distinct uniform u64 keys, seed 1, P 2500, alpha 1) at lam
 Calls only the oracle. The counters are the nested-loop search's work measures: hash evaluations
 h(x, s), slot probes (the key checks of the loop over displacements, the paper's work measure in
 Sec. 3), seeds tried, and buckets placed. The benchmark divides them by the measured search time.
+It also records the SHA-256 of the oracle's whole interleaved-Rice image and of its pilot array
+(partition-major u32, the same for either coding), which the full-size GPU parity test compares
+against the device build.
 
 Run: python tests/golden/make_search_work.py   (about 5 minutes on 8 cores)
 """
 
+import hashlib
 import json
 import os
 import sys
@@ -15,6 +19,8 @@ import time
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
 
 import oracle  # noqa: E402
 from paper_2404_18497_amd import synth  # noqa: E402
@@ -30,6 +36,8 @@ def main():
         h = oracle.build_u64(keys, oracle.params(lam=lam), threads=os.cpu_count() or 1)
         c = h.counters()
         c["bits_per_key_rice"] = h.size_bits() / n
+        c["image_sha256_rice"] = hashlib.sha256(h.image().tobytes()).hexdigest()
+        c["pilots_sha256"] = hashlib.sha256(np.ascontiguousarray(h.pilots(), dtype=np.uint32).tobytes()).hexdigest()
         out["counters"][f"{lam:g}"] = c
         print(lam, c, f"{time.time() - t:.1f}s", flush=True)
         del h

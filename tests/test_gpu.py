@@ -192,47 +192,69 @@ def test_determinism_and_order_independence(torch):
     assert np.array_equal(a, b) and np.array_equal(a, c)
 
 
-def test_full_size_100m_sampled(torch):
-    """The benchmark workload (100M keys, lambda 7, Rice): bijection over all keys; pilots of sampled
-    partitions against the oracle's search on the same codes; sampled queries against the oracle
-    reading the GPU image; encoder parameters against the pilot statistics."""
-    n = 100_000_000
+@pytest.fixture(scope="module")
+def keys_100m(torch):
     _say("100M keys: generate")
-    keys = synth.u64_keys(n, 1)
-    dk = _dev(torch, keys)
-    prm = binding.params(lam=7.0, keep_pilots=True)
-    _say("100M keys: build")
+    keys = synth.u64_keys(100_000_000, 1)
+    return keys, _dev(torch, keys)
+
+
+def _golden_100m(lam):
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "search_work_100m.json")
+    return json.load(open(path))["counters"][f"{lam:g}"]
+
+
+@pytest.mark.parametrize("lam,coding", [(7.0, "rice"), (5.0, "rice"), (9.0, "rice"), (7.0, "compact")])
+def test_full_size_100m(torch, keys_100m, lam, coding):
+    """The benchmark workload (100M keys, P 2500) at lambda 5, 7 and 9: the whole device image
+    (Rice) and the whole pilot array hash to the values the oracle's own 100M-key build produced
+    (tests/golden, written by a script that calls only the oracle); bijection over all keys; at
+    lambda 7 also pilots of sampled partitions against the oracle's search on the same codes,
+    sampled queries against the oracle reading the device image, and the encoder parameters."""
+    import hashlib
+
+    keys, dk = keys_100m
+    n = keys.size
+    golden = _golden_100m(lam)
+    prm = binding.params(lam=lam, coding=coding, keep_pilots=True)
+    _say("100M keys: build", lam, coding)
     g = binding.build_u64(dk, prm)
+    pil = g.pilots()
+    assert hashlib.sha256(np.ascontiguousarray(pil, dtype=np.uint32).tobytes()).hexdigest() == golden["pilots_sha256"]
+    img = g.serialize()
+    if coding == "rice":
+        assert hashlib.sha256(img.tobytes()).hexdigest() == golden["image_sha256_rice"]
+        assert g.size_bits() / n == golden["bits_per_key_rice"]
     _say("100M keys: query all")
     pos = g.query_u64(dk)
     cnt = torch.zeros(n, dtype=torch.int32, device=dk.device)
     cnt.index_add_(0, pos, torch.ones(n, dtype=torch.int32, device=dk.device))
     assert int(cnt.min()) == 1 and int(cnt.max()) == 1, "not a bijection onto [0, n)"
     del cnt
+    rng = np.random.default_rng(4)
+    _say("100M keys: sampled queries vs oracle decoding of the image")
+    sample = rng.integers(0, n, 200_000)
+    got = pos[torch.from_numpy(sample).cuda()].cpu().numpy().view(np.uint64)
+    assert np.array_equal(oracle.query_image_u64(img, keys[sample]), got)
+    if lam != 7.0 or coding != "rice":
+        return
     _say("100M keys: sampled partitions")
     offs, codes = binding.partition_u64(dk, prm)
     offs = offs.cpu().numpy().view(np.uint64)
-    pil = g.pilots()
-    rng = np.random.default_rng(4)
-    rp = oracle.params(lam=7.0)
+    rp = oracle.params(lam=lam)
     for j in rng.integers(0, g.K, 24):
         a, b = int(offs[j]), int(offs[j + 1])
         c = codes[a:b].cpu().numpy().view(np.uint64)
         want, _ = oracle.search_partition(c[:, 0], c[:, 1], b - a, rp)
         assert np.array_equal(pil[j], want), f"partition {j}"
-    _say("100M keys: sampled queries vs oracle decoding of the image")
-    img = g.serialize()
-    sample = rng.integers(0, n, 200_000)
-    got = pos[torch.from_numpy(sample).cuda()].cpu().numpy().view(np.uint64)
-    assert np.array_equal(oracle.query_image_u64(img, keys[sample]), got)
     _say("100M keys: encoder parameters")
     K, B = g.K, g.B
     enc = img[int(img[13]): int(img[13]) + B]
     for i in range(0, B, 7):
         assert int(enc[i]) & 0xFF == oracle.rice_param(int(pil[:, i].astype(np.uint64).sum()), K)
-    bits = g.size_bits() / n
-    _say("100M keys: bits/key", bits)
-    assert 1.75 < bits < 1.9
 
 
 @pytest.fixture(scope="module")
