@@ -144,7 +144,7 @@ typedef struct {
 } phobic_search_config;
 
 /* Sets the search shape used by later builds on the calling process (all devices).  The default is
- * two wavefronts per workgroup, one wavefront per partition ({2, 0, 1, 0}). */
+ * one wavefront per workgroup, one wavefront per partition ({1, 0, 1, 0}). */
 phobic_status phobic_set_search_config(const phobic_search_config* cfg);
 phobic_status phobic_get_search_config(phobic_search_config* out);
 

@@ -315,7 +315,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
 
 // One wavefront per partition.
 template <int kWaves>
-__global__ __launch_bounds__(64 * kWaves) void k_search(SearchArgs a) {
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search(SearchArgs a) {
   extern __shared__ __align__(16) uint32_t lds32[];
   const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const uint64_t j = (uint64_t)blockIdx.x * kWaves + wave;
@@ -325,7 +325,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_search(SearchArgs a) {
 
 // Persistent: every wavefront takes `grab` partitions at a time from the queue until none is left.
 template <int kWaves>
-__global__ __launch_bounds__(64 * kWaves) void k_search_persistent(SearchArgs a) {
+__global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search_persistent(SearchArgs a) {
   extern __shared__ __align__(16) uint32_t lds32[];
   const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   uint32_t* F2 = lds32 + (size_t)wave * (a.wave_lds / 4);
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_search_persistent(SearchArgs a)
 // Search launch shape
 // ---------------------------------------------------------------------------------------------
 std::mutex g_cfg_mu;
-phobic_search_config g_cfg = {2, 0, 1, 0};  // two partitions per workgroup, one per wavefront
+phobic_search_config g_cfg = {1, 0, 1, 0};  // one partition per workgroup
 
 phobic_search_config search_config() {
   std::lock_guard<std::mutex> lock(g_cfg_mu);
