@@ -1511,19 +1511,45 @@ __global__ __launch_bounds__(256) void k_batch_pack_off(const uint64_t* __restri
 }
 
 // One wavefront per (t, i): values (Compact) or low bits and unary stream with select samples (Rice).
+// One wavefront per (MPHF t, encoder i), 64 values at a time: the chunk's low bits (64 fields of at
+// most 32 bits) and, when they fit, its unary bits are assembled in the wavefront's LDS and written
+// as whole words, with an atomic OR only on the two end words a neighbouring chunk or item may share
+// (the same scheme as k_pack_values).
+constexpr uint32_t kBatchDataWords = 34;   // 64 x 32 bits + two partial words
+constexpr uint32_t kBatchUnaryWords = 64;  // unary runs of up to 64 x 64 - 63 bits are staged
+
+__device__ __forceinline__ void wave_flush_words(const uint64_t* lbuf, uint64_t* __restrict__ dst, uint64_t first,
+                                                 uint32_t last, uint32_t lane) {
+  for (uint32_t x = lane; x <= last; x += 64) {
+    const uint64_t v = lbuf[x];
+    if (x == 0 || x == last) {
+      if (v) atomicOr((unsigned long long*)&dst[first + x], (unsigned long long)v);
+    } else {
+      dst[first + x] = v;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_batch_pack_vals(const uint32_t* __restrict__ pilots,
                                                          const BatchDesc* __restrict__ d, uint32_t count, uint32_t B,
                                                          const uint64_t* __restrict__ hdrs,
                                                          const uint64_t* __restrict__ encw,
                                                          const uint64_t* __restrict__ ubase,
                                                          const uint64_t* __restrict__ ibase, uint64_t* __restrict__ buf) {
-  const uint64_t item = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  __shared__ uint64_t lds_d[4][kBatchDataWords];
+  __shared__ uint64_t lds_u[4][kBatchUnaryWords];
+  const uint32_t wv = threadIdx.x >> 6;
+  uint64_t* dbuf = lds_d[wv];
+  uint64_t* ubuf = lds_u[wv];
+  const uint64_t item = (uint64_t)blockIdx.x * 4 + wv;
   const uint32_t lane = threadIdx.x & 63;
   if (item >= (uint64_t)count * B) return;
   const uint32_t t = (uint32_t)(item / B), i = (uint32_t)(item % B);
   const uint64_t K = d[t].K;
   const uint64_t* h = hdrs + (uint64_t)t * kHeaderWords;
   uint64_t* img = buf + ibase[t];
+  uint64_t* data = img + h[kHSecData];
+  uint64_t* unary = img + h[kHSecUnary];
   const bool rice = h[kHCoding] == PHOBIC_IC_RICE;
   const uint64_t e = encw[item];
   const uint32_t w = (uint32_t)(e & 0xFF);
@@ -1534,22 +1560,45 @@ __global__ __launch_bounds__(256) void k_batch_pack_vals(const uint32_t* __restr
     const uint64_t j = j0 + lane;
     const bool in = j < K;
     const uint64_t v = in ? col[j] : 0;
-    put_bits_atomic(img + h[kHSecData], base + j * w, w >= 64 ? v : (v & ((1ULL << w) - 1)), in ? w : 0);
+    if (lane < kBatchDataWords) dbuf[lane] = 0;
+    ubuf[lane] = 0;
+    const uint64_t jend = min(K, j0 + 64);
+    uint64_t incl = 0, tot = 0;
     if (rice) {
-      const uint64_t len = in ? (v >> w) + 1 : 0;
-      uint64_t incl = len;
+      incl = in ? (v >> w) + 1 : 0;
       for (int o = 1; o < 64; o <<= 1) {
         const uint64_t y = __shfl_up(incl, o);
         if (lane >= (uint32_t)o) incl += y;
       }
-      if (in) {
-        const uint64_t pos = carry + incl - 1;  // this value's one
-        atomicOr((unsigned long long*)&img[h[kHSecUnary] + (pos >> 6)], 1ULL << (pos & 63));
-        const uint64_t tg = (uint64_t)i * K + j;
-        if ((tg & (kSelEvery - 1)) == 0) ((uint32_t*)(img + h[kHSecSel]))[tg / kSelEvery] = (uint32_t)pos;
-      }
-      carry += __shfl(incl, 63);
+      tot = __shfl(incl, 63);
     }
+    const uint64_t d_first = (base + j0 * w) >> 6, u_first = carry >> 6;
+    const bool u_lds = tot == 0 || ((carry + tot - 1) >> 6) - u_first < kBatchUnaryWords;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (in && w) {
+      const uint64_t rel = base + j * w - d_first * 64;
+      const uint32_t idx = (uint32_t)(rel >> 6), sh = (uint32_t)(rel & 63);
+      const uint64_t f = v & ((1ULL << w) - 1);
+      atomicOr((unsigned long long*)&dbuf[idx], (unsigned long long)(f << sh));
+      if (sh + w > 64) atomicOr((unsigned long long*)&dbuf[idx + 1], (unsigned long long)(f >> (64 - sh)));
+    }
+    if (rice && in) {
+      const uint64_t pos = carry + incl - 1;  // this value's one
+      if (u_lds)
+        atomicOr((unsigned long long*)&ubuf[(pos >> 6) - u_first], 1ULL << (pos & 63));
+      else
+        atomicOr((unsigned long long*)&unary[pos >> 6], 1ULL << (pos & 63));
+      const uint64_t tg = (uint64_t)i * K + j;
+      if ((tg & (kSelEvery - 1)) == 0) ((uint32_t*)(img + h[kHSecSel]))[tg / kSelEvery] = (uint32_t)pos;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (w) wave_flush_words(dbuf, data, d_first, (uint32_t)(((base + jend * w - 1) >> 6) - d_first), lane);
+    if (rice && u_lds && tot) wave_flush_words(ubuf, unary, u_first, (uint32_t)(((carry + tot - 1) >> 6) - u_first), lane);
+    carry += tot;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
