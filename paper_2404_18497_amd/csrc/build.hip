@@ -372,6 +372,59 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_scatter(const uint64_
   }
 }
 
+// Descending bitonic sort of keys[0, n) (n a power of two; entries beyond are zero) by one wavefront
+// in registers: element i = lane * E + r; sub-stages with distance below E stay inside a lane, the
+// others exchange with lane ^ (distance / E).  No workgroup barrier.
+template <int E>
+__device__ __forceinline__ void wave_bitonic_desc(uint32_t* keys, uint32_t n, uint32_t lane) {
+  constexpr uint32_t N = 64 * E;
+  uint32_t v[E];
+#pragma unroll
+  for (int r = 0; r < E; r++) {
+    const uint32_t i = lane * E + r;
+    v[r] = i < n ? keys[i] : 0u;
+  }
+#pragma unroll
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= (uint32_t)E) {
+        const uint32_t jl = j / E;
+        const bool lower = (lane & jl) == 0;
+#pragma unroll
+        for (int r = 0; r < E; r++) {
+          const bool desc = ((lane * E + r) & k) == 0;
+          const uint32_t pv = __shfl_xor(v[r], (int)jl);
+          v[r] = (lower == desc) ? max(v[r], pv) : min(v[r], pv);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < E; r++) {
+          if ((r & j) == 0) {
+            const bool desc = ((lane * E + r) & k) == 0;
+            const uint32_t a = v[r], b = v[r ^ j];
+            v[r] = desc ? max(a, b) : min(a, b);
+            v[r ^ j] = desc ? min(a, b) : max(a, b);
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < E; r++) {
+    const uint32_t i = lane * E + r;
+    if (i < n) keys[i] = v[r];
+  }
+}
+
+// nbpad <= 512 (at most 8 keys per lane, so the registers do not limit the kernel's occupancy)
+__device__ __forceinline__ void wave_sort_keys(uint32_t* keys, uint32_t nbpad, uint32_t lane) {
+  if (nbpad <= 64) wave_bitonic_desc<1>(keys, nbpad, lane);
+  else if (nbpad == 128) wave_bitonic_desc<2>(keys, nbpad, lane);
+  else if (nbpad == 256) wave_bitonic_desc<4>(keys, nbpad, lane);
+  else wave_bitonic_desc<8>(keys, nbpad, lane);
+}
+
 // One workgroup per coarse bin of up to kMaxG partitions.  info[0] |= error bits, info[1] = max
 // bucket size, info[2] = max partition size.
 //
@@ -435,21 +488,26 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* 
     }
   }
   __syncthreads();
-  // bitonic sort of every partition's nbpad keys into descending order (size, then bucket index)
-  for (uint32_t k = 2; k <= nbpad; k <<= 1) {
-    for (uint32_t sd = k >> 1; sd > 0; sd >>= 1) {
-      for (uint32_t x = tid; x < span; x += kSegThreads) {
-        const uint32_t y = x ^ sd;
-        if (y > x) {
-          const uint32_t a = key[x], b = key[y];
-          // direction from the index inside the partition's block, so every block ends descending
-          if (((x & (nbpad - 1)) & k) == 0 ? (a < b) : (a > b)) {
-            key[x] = b;
-            key[y] = a;
+  // every partition's nbpad keys into descending order (size, then bucket index)
+  if (nbpad <= 512) {  // wavefront p sorts partition p (G <= kMaxG <= the workgroup's wavefronts)
+    if ((tid >> 6) < G) wave_sort_keys(key + (tid >> 6) * nbpad, nbpad, tid & 63);
+    __syncthreads();
+  } else {  // many buckets: bitonic over the whole workgroup
+    for (uint32_t k = 2; k <= nbpad; k <<= 1) {
+      for (uint32_t sd = k >> 1; sd > 0; sd >>= 1) {
+        for (uint32_t x = tid; x < span; x += kSegThreads) {
+          const uint32_t y = x ^ sd;
+          if (y > x) {
+            const uint32_t a = key[x], b = key[y];
+            // direction from the index inside the partition's block, so every block ends descending
+            if (((x & (nbpad - 1)) & k) == 0 ? (a < b) : (a > b)) {
+              key[x] = b;
+              key[y] = a;
+            }
           }
         }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
   // exclusive prefix of the sizes over [G][nbpad] in order = start of every bucket inside the bin
