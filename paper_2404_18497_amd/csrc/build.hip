@@ -341,6 +341,8 @@ __global__ __launch_bounds__(1024) void k_coarse_scan(const uint32_t* __restrict
   if (t == 1023) cbase[C] = sp[1023];
 }
 
+// kStr: the codes of the staged string hashes go out; otherwise the u64 keys themselves (8 bytes
+// instead of 16; the bucket sort hashes them again).
 template <bool kStr>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_scatter(const uint64_t* __restrict__ keys,
                                                                    const ulonglong2* __restrict__ stage, uint64_t n,
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_scatter(const uint64_
                                                                    uint32_t gshift, uint32_t C,
                                                                    const uint32_t* __restrict__ hrow,
                                                                    uint32_t* __restrict__ cur,
-                                                                   ulonglong2* __restrict__ codes) {
+                                                                   void* __restrict__ out) {
   extern __shared__ __align__(16) uint32_t pos[];
   const uint32_t tid = threadIdx.x;
   // the count ran two workgroups over the two halves of this workgroup's range
@@ -359,16 +361,15 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_scatter(const uint64_
   __syncthreads();
   const uint64_t a = (uint64_t)blockIdx.x * per, b = min(n, a + per);
   for (uint64_t i = a + tid; i < b; i += kCoarseThreads) {
-    ulonglong2 code;
     if (kStr) {
-      code = stage[i];
+      const ulonglong2 code = stage[i];
+      const uint32_t c = (uint32_t)__umul64hi(code.x, K) >> gshift;
+      ((ulonglong2*)out)[atomicAdd(&pos[c], 1u)] = code;
     } else {
-      uint64_t hi, lo;
-      hash_key_u64(keys[i], seed, hi, lo);
-      code = make_ulonglong2(hi, lo);
+      const uint64_t key = keys[i];
+      const uint32_t c = (uint32_t)__umul64hi(mix_a(key ^ seed), K) >> gshift;
+      ((uint64_t*)out)[atomicAdd(&pos[c], 1u)] = key;
     }
-    const uint32_t c = (uint32_t)__umul64hi(code.x, K) >> gshift;
-    codes[atomicAdd(&pos[c], 1u)] = code;
   }
 }
 
@@ -428,12 +429,15 @@ __device__ __forceinline__ void wave_sort_keys(uint32_t* keys, uint32_t nbpad, u
 // One workgroup per coarse bin of up to kMaxG partitions.  info[0] |= error bits, info[1] = max
 // bucket size, info[2] = max partition size.
 //
-// kRecords = false: codes are (hi, lo) of one MPHF with K partitions; the partition is mulhi(hi, K).
-// kRecords = true (batches): codes are (fingerprint, lo with the partition's slot in the bin in its
+// kIn = kInCodes: src holds (hi, lo) of one MPHF with K partitions; the partition is mulhi(hi, K).
+// kIn = kInKeys: src holds the u64 keys of one MPHF, hashed here with `seed` (half the bytes of codes
+// through the scatter and this kernel's reads).
+// kIn = kInRecords (batches): src holds (fingerprint, lo with the partition's slot in the bin in its
 // low three bits, which the bucket function never reads); partitions are global indices of the
 // batch, this launch covers [jbase, jend), and kbase is the global index of its first key.
-template <bool kRecords>
-__global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* __restrict__ codes,
+enum { kInCodes = 0, kInKeys = 1, kInRecords = 2 };
+template <int kIn>
+__global__ __launch_bounds__(kSegThreads) void k_segment_sort(const void* __restrict__ src, uint64_t seed,
                                                               const uint64_t* __restrict__ cbase,
                                                               const uint64_t* __restrict__ T, uint32_t B,
                                                               uint32_t nbpad, uint32_t gshift, uint64_t K,
@@ -469,12 +473,20 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* 
   for (int t = 0; t < kItems; t++) {
     const uint32_t i = tid + t * kSegThreads;
     if (i < ns) {
-      const ulonglong2 cd = codes[base + i];
-      const uint32_t p = kRecords ? (uint32_t)(cd.y & 7) : (uint32_t)(__umul64hi(cd.x, K) - j0);
+      ulonglong2 cd;
+      if (kIn == kInKeys) {
+        uint64_t hi, lo;
+        hash_key_u64(((const uint64_t*)src)[base + i], seed, hi, lo);
+        cd = make_ulonglong2(hi, lo);
+      } else {
+        cd = ((const ulonglong2*)src)[base + i];
+      }
+      const bool records = kIn == kInRecords;
+      const uint32_t p = records ? (uint32_t)(cd.y & 7) : (uint32_t)(__umul64hi(cd.x, K) - j0);
       const uint32_t b = bucket_of(cd.y, T, B);
       const uint32_t r = atomicAdd(&cnt[p * nbpad + b], 1u);
       rec[i] = (p << 29) | (b << 16) | r;
-      fp[t] = kRecords ? (uint64_t)cd.x : fingerprint(cd.x, cd.y);
+      fp[t] = records ? (uint64_t)cd.x : fingerprint(cd.x, cd.y);
     }
   }
   __syncthreads();
@@ -556,7 +568,17 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const ulonglong2* 
       const uint32_t r = rec[i];
       const uint32_t d = cnt[(r >> 29) * nbpad + ((r >> 16) & 0x1FFF)] + (r & 0xFFFF);
       dst2[t / 2] |= d << (16 * (t & 1));
-      if (dbg) dbg[kbase + base + d] = codes[base + i];
+      if (dbg) {
+        ulonglong2 cd;
+        if (kIn == kInKeys) {
+          uint64_t hi, lo;
+          hash_key_u64(((const uint64_t*)src)[base + i], seed, hi, lo);
+          cd = make_ulonglong2(hi, lo);
+        } else {
+          cd = ((const ulonglong2*)src)[base + i];
+        }
+        dbg[kbase + base + d] = cd;
+      }
     }
   }
   __syncthreads();
@@ -1137,7 +1159,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   if (coarse_path) {
     uint32_t *ccnt, *hrow, *cur;
     uint64_t* cbase;
-    ulonglong2 *codes, *stage = nullptr;
+    ulonglong2 *codes = nullptr, *stage = nullptr;
     // ngrp scatter workgroups over ranges of 2 * per keys; the count runs 2 * ngrp workgroups over
     // the halves, so it keeps twice as many loads in flight
     const uint32_t ngrp = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kCoarseGroups, (n + 8191) / 8192));
@@ -1146,8 +1168,13 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     PHOBIC_HIP(S.get(&hrow, 2 * (uint64_t)ngrp * C));
     PHOBIC_HIP(S.get(&cur, C));
     PHOBIC_HIP(S.get(&cbase, C + 1));
-    PHOBIC_HIP(S.get(&codes, n));
-    if (str) PHOBIC_HIP(S.get(&stage, n));
+    uint64_t* kcodes = nullptr;  // u64 keys: the keys themselves travel through the scatter
+    if (str) {
+      PHOBIC_HIP(S.get(&codes, n));
+      PHOBIC_HIP(S.get(&stage, n));
+    } else {
+      PHOBIC_HIP(S.get(&kcodes, n));
+    }
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(C)), dim3(kBlock), 0, st, ccnt, C, 0u);
     const size_t hist_lds = C * sizeof(uint32_t);
     tm.mark();  // 0
@@ -1165,11 +1192,18 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
                          2 * per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
     else
       hipLaunchKernelGGL(k_coarse_scatter<false>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, stage, n,
-                         2 * per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
+                         2 * per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, kcodes);
     tm.mark();  // 3
-    hipLaunchKernelGGL(k_segment_sort<false>, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st, codes, cbase,
-                       h->d_table, B, nbpad, (uint32_t)gshift, K, (uint64_t)0, K, (uint64_t)0, seg_cap, sortedf,
-                       blist, nbk, off, err, (ulonglong2*)part_codes_out);
+    if (str)
+      hipLaunchKernelGGL(k_segment_sort<kInCodes>, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st,
+                         (const void*)codes, prm.hash_seed, cbase, h->d_table, B, nbpad, (uint32_t)gshift, K,
+                         (uint64_t)0, K, (uint64_t)0, seg_cap, sortedf, blist, nbk, off, err,
+                         (ulonglong2*)part_codes_out);
+    else
+      hipLaunchKernelGGL(k_segment_sort<kInKeys>, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st,
+                         (const void*)kcodes, prm.hash_seed, cbase, h->d_table, B, nbpad, (uint32_t)gshift, K,
+                         (uint64_t)0, K, (uint64_t)0, seg_cap, sortedf, blist, nbk, off, err,
+                         (ulonglong2*)part_codes_out);
     if (an != ad) {
       PHOBIC_HIP(S.get(&toff, K + 1));
       hipLaunchKernelGGL(k_table_offsets, dim3(1), dim3(1024), 0, st, off, K, an, ad, toff, err, d64);
@@ -1784,9 +1818,9 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
     hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1024), 0, st, ccnt, (uint32_t)C, cbase, cur);
     hipLaunchKernelGGL(k_batch_coarse<true>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, d_desc, c.t0, c.t1, nb0,
                        nchunk, per, prm.hash_seed, Jc0, (uint32_t)gshift, (uint32_t)C, ccnt, hrow, cur, codes);
-    hipLaunchKernelGGL(k_segment_sort<true>, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st, codes, cbase,
-                       tbl.d_table, B, nbpad, (uint32_t)gshift, (uint64_t)0, Jc0, Jc1, nb0, seg_cap, fp, blist, nbk,
-                       off, err, (ulonglong2*)nullptr);
+    hipLaunchKernelGGL(k_segment_sort<kInRecords>, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st,
+                       (const void*)codes, prm.hash_seed, cbase, tbl.d_table, B, nbpad, (uint32_t)gshift, (uint64_t)0,
+                       Jc0, Jc1, nb0, seg_cap, fp, blist, nbk, off, err, (ulonglong2*)nullptr);
     PHOBIC_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_batch_owner, dim3(grid_for(Ktot)), dim3(kBlock), 0, st, d_desc, count, Ktot, owner);
