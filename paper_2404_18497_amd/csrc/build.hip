@@ -261,23 +261,30 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2* __rest
 }
 
 // ---------------------------------------------------------------------------------------------
-// Hash, partition, bucket and order, main path: coarse bins of G = 2^gshift consecutive partitions.
+// Hash, partition, bucket and order, main path: coarse bins of G = 2^gshift consecutive partitions,
+// and digits of 2^dshift consecutive coarse bins (at most kMaxDigits digits).
 //
-//   k_coarse_count   : 512 workgroups, each over a contiguous range of keys, histogram the coarse bin
-//                      c = j >> gshift of every key in LDS; the row is saved and added to the bin
-//                      totals with one atomic per bin and workgroup
-//   k_coarse_scan    : bin offsets (one workgroup)
-//   k_coarse_scatter : each workgroup reserves its chunk of every bin with one atomic, then places its
-//                      codes through LDS cursors; every chunk is written by one workgroup
-//   k_segment_sort   : one workgroup per coarse bin: partition of every key, bucket by the tabulated
-//                      bucket function, ranks within (partition, bucket), buckets of every partition
-//                      ordered by size desc and index desc, partition offsets, fingerprints written
-//                      in processing order
-// No per-key global atomics: the only global atomics are one per (workgroup, bin).
+//   k_coarse_count    : R workgroups (rows), each over a contiguous range of keys, histogram the
+//                       coarse bin c = j >> gshift of every key in LDS; the row and its digit sums are
+//                       saved and the row is added to the bin totals with one atomic per bin
+//   k_coarse_scan     : bin offsets (one workgroup)
+//   k_digit_offsets   : per digit, the offset of every row's share (rows in order)
+//   k_split_digits    : row r moves its keys to its share of every digit
+//   k_split_bins      : each slice of a digit (the shares of g consecutive rows) moves its keys to
+//                       its bins, reserving its chunk of every bin with one atomic
+//   k_segment_sort    : one workgroup per coarse bin: partition of every key, bucket by the tabulated
+//                       bucket function, ranks within (partition, bucket), buckets of every partition
+//                       ordered by size desc and index desc, partition offsets, fingerprints written
+//                       in processing order
+// Both splits go tile by tile: a tile is grouped by destination in LDS, then written in runs, so
+// every store of a wavefront lands in a few cache lines.  One split straight to the bins would
+// scatter single 8-byte stores over R x C open lines, far more than L2 holds, and every store
+// would leave the chip as a partial line.  No per-key global atomics.
 // ---------------------------------------------------------------------------------------------
 constexpr int kCoarseThreads = 1024;
-constexpr uint32_t kCoarseGroups = 256;  // scatter workgroups; the count uses two per scatter range
+constexpr uint32_t kCoarseGroups = 256;  // half the number of rows
 constexpr uint32_t kMaxCoarse = 14336;   // bins held by the LDS histogram (56 KB)
+constexpr uint32_t kMaxDigits = 256;     // destinations of one split (a byte each in LDS)
 constexpr int kSegThreads = 512;
 constexpr uint32_t kMaxG = 8;
 constexpr size_t kSegLdsBytes = 61440;   // dynamic LDS of k_segment_sort
@@ -288,8 +295,10 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_count(const uint64_t*
                                                                  const uint64_t* __restrict__ offs,
                                                                  ulonglong2* __restrict__ stage, uint64_t n,
                                                                  uint64_t per, uint64_t seed, uint64_t K,
-                                                                 uint32_t gshift, uint32_t C,
-                                                                 uint32_t* __restrict__ ccnt, uint32_t* __restrict__ hrow) {
+                                                                 uint32_t gshift, uint32_t C, uint32_t dshift,
+                                                                 uint32_t D, uint32_t* __restrict__ ccnt,
+                                                                 uint32_t* __restrict__ hrow,
+                                                                 uint32_t* __restrict__ drow) {
   extern __shared__ __align__(16) uint32_t hist[];
   const uint32_t tid = threadIdx.x;
   for (uint32_t x = tid; x < C; x += kCoarseThreads) hist[x] = 0;
@@ -312,6 +321,12 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_count(const uint64_t*
     const uint32_t v = hist[x];
     hrow[(uint64_t)blockIdx.x * C + x] = v;
     if (v) atomicAdd(&ccnt[x], v);
+  }
+  for (uint32_t d = tid; d < D; d += kCoarseThreads) {
+    const uint32_t c0 = d << dshift, c1 = min(C, (d + 1) << dshift);
+    uint32_t s = 0;
+    for (uint32_t c = c0; c < c1; c++) s += hist[c];
+    drow[(uint64_t)blockIdx.x * D + d] = s;
   }
 }
 
@@ -341,36 +356,184 @@ __global__ __launch_bounds__(1024) void k_coarse_scan(const uint32_t* __restrict
   if (t == 1023) cbase[C] = sp[1023];
 }
 
-// kStr: the codes of the staged string hashes go out; otherwise the u64 keys themselves (8 bytes
-// instead of 16; the bucket sort hashes them again).
-template <bool kStr>
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_scatter(const uint64_t* __restrict__ keys,
-                                                                   const ulonglong2* __restrict__ stage, uint64_t n,
-                                                                   uint64_t per, uint64_t seed, uint64_t K,
-                                                                   uint32_t gshift, uint32_t C,
-                                                                   const uint32_t* __restrict__ hrow,
-                                                                   uint32_t* __restrict__ cur,
-                                                                   void* __restrict__ out) {
-  extern __shared__ __align__(16) uint32_t pos[];
+// One workgroup per digit d (R <= 1024 rows): doff[d (R + 1) + r] = where row r's share of digit d
+// starts, rows in order; doff[d (R + 1) + R] = where the digit ends.
+__global__ __launch_bounds__(1024) void k_digit_offsets(const uint32_t* __restrict__ drow,
+                                                        const uint64_t* __restrict__ cbase, uint32_t R,
+                                                        uint32_t D, uint32_t dshift, uint32_t* __restrict__ doff) {
+  __shared__ uint32_t sp[1024];
+  const uint32_t t = threadIdx.x, d = blockIdx.x;
+  const uint32_t v = t < R ? drow[(uint64_t)t * D + d] : 0u;
+  sp[t] = v;
+  __syncthreads();
+  for (uint32_t k = 1; k < 1024; k <<= 1) {
+    const uint32_t u = t >= k ? sp[t - k] : 0u;
+    __syncthreads();
+    sp[t] += u;
+    __syncthreads();
+  }
+  const uint32_t base = (uint32_t)cbase[d << dshift];
+  if (t < R) doff[(uint64_t)d * (R + 1) + t] = base + sp[t] - v;
+  if (t == R - 1) doff[(uint64_t)d * (R + 1) + R] = base + sp[t];
+}
+
+// Elements of the splits: the u64 keys themselves (the bin is hashed again from the key), or the
+// 128-bit codes of hashed strings (the bin comes from the high word).
+template <typename E> struct SplitElem;
+template <> struct SplitElem<uint64_t> {
+  static constexpr int kPer = 6;  // elements per thread and tile (the LDS stays under 64 KB)
+  __device__ static uint32_t bin(uint64_t v, uint64_t seed, uint64_t K, uint32_t gshift) {
+    return (uint32_t)__umul64hi(mix_a(v ^ seed), K) >> gshift;
+  }
+};
+template <> struct SplitElem<ulonglong2> {
+  static constexpr int kPer = 3;
+  __device__ static uint32_t bin(ulonglong2 v, uint64_t, uint64_t K, uint32_t gshift) {
+    return (uint32_t)__umul64hi(v.x, K) >> gshift;
+  }
+};
+template <typename E>
+constexpr uint32_t split_tile() { return (uint32_t)kCoarseThreads * SplitElem<E>::kPer; }
+template <typename E>
+constexpr size_t split_lds_bytes() {
+  return split_tile<E>() * (sizeof(E) + 1) + 4 * kMaxDigits * sizeof(uint32_t);
+}
+
+static_assert(split_lds_bytes<uint64_t>() <= 65536 && split_lds_bytes<ulonglong2>() <= 65536, "split LDS");
+static_assert(kMaxDigits == 4 * 64, "the tile scan takes four counts per lane of one wavefront");
+
+// LDS of a split: tile | dest byte per tile slot | count | tile base | write offset | cursor.
+template <typename E>
+struct SplitLds {
+  E* tile;
+  uint8_t* dst;
+  uint32_t *cnt, *tb, *wofs, *gpos;
+  __device__ explicit SplitLds(uint32_t* lds) {
+    constexpr uint32_t T = split_tile<E>();
+    tile = (E*)lds;
+    cnt = (uint32_t*)(tile + T);
+    tb = cnt + kMaxDigits;
+    wofs = tb + kMaxDigits;
+    gpos = wofs + kMaxDigits;
+    dst = (uint8_t*)(gpos + kMaxDigits);
+  }
+};
+
+// Moves in[a, b) to out, destination q of element v = dest(v) < nd: the elements with destination q
+// go to out[gpos[q]], out[gpos[q] + 1], ... in the order they are met; gpos advances.  cnt[0, nd)
+// must be zero on entry and is zero on exit.  Every thread of the workgroup calls it.
+template <typename E, class Dest>
+__device__ __forceinline__ void split_range(const E* __restrict__ in, uint64_t a, uint64_t b, uint32_t nd,
+                                            Dest dest, SplitLds<E>& L, E* __restrict__ out) {
+  constexpr int kPer = SplitElem<E>::kPer;
+  constexpr uint32_t T = split_tile<E>();
   const uint32_t tid = threadIdx.x;
-  // the count ran two workgroups over the two halves of this workgroup's range
-  for (uint32_t x = tid; x < C; x += kCoarseThreads) {
-    const uint32_t v = hrow[(2 * (uint64_t)blockIdx.x) * C + x] + hrow[(2 * (uint64_t)blockIdx.x + 1) * C + x];
-    pos[x] = v ? atomicAdd(&cur[x], v) : 0u;
+  for (uint64_t t0 = a; t0 < b; t0 += T) {
+    const uint32_t tn = (uint32_t)min<uint64_t>(T, b - t0);
+    E v[kPer];
+    uint32_t q[kPer], rk[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+      const uint32_t i = (uint32_t)r * kCoarseThreads + tid;
+      if (i < tn) v[r] = in[t0 + i];
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+      const uint32_t i = (uint32_t)r * kCoarseThreads + tid;
+      if (i < tn) {
+        q[r] = dest(v[r]);
+        rk[r] = atomicAdd(&L.cnt[q[r]], 1u);
+      }
+    }
+    __syncthreads();
+    if (tid < 64) {  // exclusive scan of the tile's counts by one wavefront, four per lane
+      uint32_t c[4], s = 0;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const uint32_t x = tid * 4 + k;
+        c[k] = x < nd ? L.cnt[x] : 0u;
+        s += c[k];
+      }
+      uint32_t inc = s;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d);
+        if (tid >= (uint32_t)d) inc += y;
+      }
+      uint32_t run = inc - s;
+#pragma unroll
+      for (int k = 0; k < 4; k++) {
+        const uint32_t x = tid * 4 + k;
+        if (x < nd) {
+          L.tb[x] = run;
+          L.wofs[x] = L.gpos[x] - run;  // modulo 2^32: slot s of destination x goes to wofs[x] + s
+          L.gpos[x] += c[k];
+          L.cnt[x] = 0;
+        }
+        run += c[k];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+      const uint32_t i = (uint32_t)r * kCoarseThreads + tid;
+      if (i < tn) {
+        const uint32_t s = L.tb[q[r]] + rk[r];
+        L.tile[s] = v[r];
+        L.dst[s] = (uint8_t)q[r];
+      }
+    }
+    __syncthreads();
+    for (uint32_t s = tid; s < tn; s += kCoarseThreads) out[L.wofs[L.dst[s]] + s] = L.tile[s];
+    __syncthreads();
+  }
+}
+
+// Row r (the count's workgroup r, keys [r per, (r + 1) per)) to its share of every digit.
+template <typename E>
+__global__ __launch_bounds__(kCoarseThreads) void k_split_digits(const E* __restrict__ in, uint64_t n, uint64_t per,
+                                                                 uint64_t seed, uint64_t K, uint32_t gshift,
+                                                                 uint32_t dshift, uint32_t D, uint32_t R,
+                                                                 const uint32_t* __restrict__ doff,
+                                                                 E* __restrict__ out) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  SplitLds<E> L(lds);
+  const uint32_t tid = threadIdx.x, r = blockIdx.x;
+  for (uint32_t d = tid; d < D; d += kCoarseThreads) {
+    L.cnt[d] = 0;
+    L.gpos[d] = doff[(uint64_t)d * (R + 1) + r];
   }
   __syncthreads();
-  const uint64_t a = (uint64_t)blockIdx.x * per, b = min(n, a + per);
-  for (uint64_t i = a + tid; i < b; i += kCoarseThreads) {
-    if (kStr) {
-      const ulonglong2 code = stage[i];
-      const uint32_t c = (uint32_t)__umul64hi(code.x, K) >> gshift;
-      ((ulonglong2*)out)[atomicAdd(&pos[c], 1u)] = code;
-    } else {
-      const uint64_t key = keys[i];
-      const uint32_t c = (uint32_t)__umul64hi(mix_a(key ^ seed), K) >> gshift;
-      ((uint64_t*)out)[atomicAdd(&pos[c], 1u)] = key;
-    }
+  const uint64_t a = (uint64_t)r * per, b = min(n, a + per);
+  split_range<E>(
+      in, a, b, D, [=](const E& v) { return SplitElem<E>::bin(v, seed, K, gshift) >> dshift; }, L, out);
+}
+
+// Workgroup d Q + s: slice s of digit d (the shares of rows [s g, s g + g)) to its 2^dshift bins.
+template <typename E>
+__global__ __launch_bounds__(kCoarseThreads) void k_split_bins(const E* __restrict__ in, uint64_t seed, uint64_t K,
+                                                               uint32_t gshift, uint32_t dshift, uint32_t C,
+                                                               uint32_t R, uint32_t g, uint32_t Q,
+                                                               const uint32_t* __restrict__ doff,
+                                                               const uint32_t* __restrict__ hrow,
+                                                               uint32_t* __restrict__ cur, E* __restrict__ out) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  SplitLds<E> L(lds);
+  const uint32_t tid = threadIdx.x, d = blockIdx.x / Q, s = blockIdx.x % Q;
+  const uint32_t r0 = s * g, r1 = min(R, r0 + g), nb = 1u << dshift;
+  for (uint32_t x = tid; x < nb; x += kCoarseThreads) {
+    const uint32_t c = (d << dshift) + x;
+    uint32_t v = 0;
+    if (c < C)
+      for (uint32_t r = r0; r < r1; r++) v += hrow[(uint64_t)r * C + c];
+    L.cnt[x] = 0;
+    L.gpos[x] = v ? atomicAdd(&cur[c], v) : 0u;
   }
+  __syncthreads();
+  const uint64_t a = doff[(uint64_t)d * (R + 1) + r0], b = doff[(uint64_t)d * (R + 1) + r1];
+  const uint32_t mask = nb - 1;
+  split_range<E>(
+      in, a, b, nb, [=](const E& v) { return SplitElem<E>::bin(v, seed, K, gshift) & mask; }, L, out);
 }
 
 // Descending bitonic sort of keys[0, n) (n a power of two; entries beyond are zero) by one wavefront
@@ -1157,18 +1320,23 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   old_info[0] = old_info[1] = old_info[2] = 0;
 
   if (coarse_path) {
-    uint32_t *ccnt, *hrow, *cur;
+    uint32_t *ccnt, *hrow, *drow, *doff, *cur;
     uint64_t* cbase;
     ulonglong2 *codes = nullptr, *stage = nullptr;
-    // ngrp scatter workgroups over ranges of 2 * per keys; the count runs 2 * ngrp workgroups over
-    // the halves, so it keeps twice as many loads in flight
+    // R = 2 ngrp rows of per keys each (the count and the first split run one workgroup per row)
     const uint32_t ngrp = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kCoarseGroups, (n + 8191) / 8192));
-    const uint64_t per = (n + 2 * (uint64_t)ngrp - 1) / (2 * (uint64_t)ngrp);
+    const uint32_t R = 2 * ngrp;
+    const uint64_t per = std::max<uint64_t>(1, (n + R - 1) / R);  // at least 1: empty inputs divide by it
+    uint32_t dshift = 0;
+    while (((C + (1ULL << dshift) - 1) >> dshift) > kMaxDigits) dshift++;
+    const uint32_t D = (uint32_t)((C + (1ULL << dshift) - 1) >> dshift);
     PHOBIC_HIP(S.get(&ccnt, C));
-    PHOBIC_HIP(S.get(&hrow, 2 * (uint64_t)ngrp * C));
+    PHOBIC_HIP(S.get(&hrow, (uint64_t)R * C));
+    PHOBIC_HIP(S.get(&drow, (uint64_t)R * D));
+    PHOBIC_HIP(S.get(&doff, (uint64_t)D * (R + 1)));
     PHOBIC_HIP(S.get(&cur, C));
     PHOBIC_HIP(S.get(&cbase, C + 1));
-    uint64_t* kcodes = nullptr;  // u64 keys: the keys themselves travel through the scatter
+    uint64_t* kcodes = nullptr;  // u64 keys: the keys themselves travel through the splits
     if (str) {
       PHOBIC_HIP(S.get(&codes, n));
       PHOBIC_HIP(S.get(&stage, n));
@@ -1179,20 +1347,46 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     const size_t hist_lds = C * sizeof(uint32_t);
     tm.mark();  // 0
     if (str)
-      hipLaunchKernelGGL(k_coarse_count<true>, dim3(2 * ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, in.bytes,
-                         in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, ccnt, hrow);
+      hipLaunchKernelGGL(k_coarse_count<true>, dim3(R), dim3(kCoarseThreads), hist_lds, st, in.keys, in.bytes,
+                         in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, dshift, D, ccnt,
+                         hrow, drow);
     else
-      hipLaunchKernelGGL(k_coarse_count<false>, dim3(2 * ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys,
-                         in.bytes, in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, ccnt, hrow);
+      hipLaunchKernelGGL(k_coarse_count<false>, dim3(R), dim3(kCoarseThreads), hist_lds, st, in.keys, in.bytes,
+                         in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, dshift, D, ccnt,
+                         hrow, drow);
     tm.mark();  // 1
     hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1024), 0, st, ccnt, (uint32_t)C, cbase, cur);
+    hipLaunchKernelGGL(k_digit_offsets, dim3(D), dim3(1024), 0, st, drow, cbase, R, D, dshift, doff);
     tm.mark();  // 2
-    if (str)
-      hipLaunchKernelGGL(k_coarse_scatter<true>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, stage, n,
-                         2 * per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, codes);
-    else
-      hipLaunchKernelGGL(k_coarse_scatter<false>, dim3(ngrp), dim3(kCoarseThreads), hist_lds, st, in.keys, stage, n,
-                         2 * per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, hrow, cur, kcodes);
+    // With one bin per digit the first split already leaves every bin in place.  The slices of the
+    // second split hold the shares of g rows, about three quarters of a tile.
+    const bool two = dshift > 0;
+    if (str) {
+      constexpr uint32_t T = split_tile<ulonglong2>();
+      const uint32_t g = (uint32_t)std::min<uint64_t>(R, std::max<uint64_t>(1, (uint64_t)T * 3 * D / (4 * per)));
+      const uint32_t Q = (R + g - 1) / g;
+      hipLaunchKernelGGL(k_split_digits<ulonglong2>, dim3(R), dim3(kCoarseThreads), split_lds_bytes<ulonglong2>(),
+                         st, (const ulonglong2*)stage, n, per, prm.hash_seed, K, (uint32_t)gshift, dshift, D, R,
+                         doff, codes);
+      if (two) {
+        hipLaunchKernelGGL(k_split_bins<ulonglong2>, dim3(D * Q), dim3(kCoarseThreads),
+                           split_lds_bytes<ulonglong2>(), st, (const ulonglong2*)codes, prm.hash_seed, K,
+                           (uint32_t)gshift, dshift, (uint32_t)C, R, g, Q, doff, hrow, cur, stage);
+        std::swap(codes, stage);  // the bins are in `codes` from here on
+      }
+    } else {
+      constexpr uint32_t T = split_tile<uint64_t>();
+      const uint32_t g = (uint32_t)std::min<uint64_t>(R, std::max<uint64_t>(1, (uint64_t)T * 3 * D / (4 * per)));
+      const uint32_t Q = (R + g - 1) / g;
+      // the fingerprint array is free until the bucket sort and holds the digits in between
+      uint64_t* mid = two ? sortedf : kcodes;
+      hipLaunchKernelGGL(k_split_digits<uint64_t>, dim3(R), dim3(kCoarseThreads), split_lds_bytes<uint64_t>(), st,
+                         in.keys, n, per, prm.hash_seed, K, (uint32_t)gshift, dshift, D, R, doff, mid);
+      if (two)
+        hipLaunchKernelGGL(k_split_bins<uint64_t>, dim3(D * Q), dim3(kCoarseThreads), split_lds_bytes<uint64_t>(),
+                           st, (const uint64_t*)mid, prm.hash_seed, K, (uint32_t)gshift, dshift, (uint32_t)C, R, g,
+                           Q, doff, hrow, cur, kcodes);
+    }
     tm.mark();  // 3
     if (str)
       hipLaunchKernelGGL(k_segment_sort<kInCodes>, dim3((uint32_t)C), dim3(kSegThreads), kSegLdsBytes, st,
