@@ -285,6 +285,7 @@ constexpr int kCoarseThreads = 1024;
 constexpr uint32_t kCoarseGroups = 256;  // half the number of rows
 constexpr uint32_t kMaxCoarse = 14336;   // bins held by the LDS histogram (56 KB)
 constexpr uint32_t kMaxDigits = 256;     // destinations of one split (a byte each in LDS)
+constexpr uint32_t kMaxSliceBins = 16384; // (slice, bin) starts of one digit (64 KB of LDS)
 constexpr int kSegThreads = 512;
 constexpr uint32_t kMaxG = 8;
 constexpr size_t kSegLdsBytes = 61440;   // dynamic LDS of k_segment_sort
@@ -419,121 +420,184 @@ struct SplitLds {
   }
 };
 
-// Moves in[a, b) to out, destination q of element v = dest(v) < nd: the elements with destination q
-// go to out[gpos[q]], out[gpos[q] + 1], ... in the order they are met; gpos advances.  cnt[0, nd)
-// must be zero on entry and is zero on exit.  Every thread of the workgroup calls it.
-template <typename E, class Dest>
+// Workgroup barrier that orders LDS only: global loads stay in flight across it (a prefetch of the
+// next tile survives) and stores are not waited for.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// threadIdx.x, hidden from the optimiser: addresses derived from it are then formed where they are
+// used instead of being hoisted out of the tile loop, where a dozen 64-bit pointers would spill (and
+// a reload from scratch makes every following store wait for all memory operations in flight).
+__device__ __forceinline__ uint32_t opaque_tid() {
+  uint32_t t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
+// The tile of the split that starts at t0 (< b), in registers: element i = r threads + tid; the
+// slots past the end repeat the last element, so that every load is unconditional.
+template <typename E>
+__device__ __forceinline__ void split_load(const E* __restrict__ in, uint64_t t0, uint64_t b,
+                                           E (&v)[SplitElem<E>::kPer]) {
+  constexpr uint32_t T = split_tile<E>();
+  const uint32_t last = (uint32_t)min<uint64_t>(T, b - t0) - 1;
+  const uint32_t tid = opaque_tid();
+#pragma unroll
+  for (int r = 0; r < SplitElem<E>::kPer; r++) v[r] = in[t0 + min((uint32_t)r * kCoarseThreads + tid, last)];
+}
+
+// One tile of tn elements held in v: grouped by destination in LDS, then written out in runs.
+// `prefetch` runs once the tile sits in LDS, so that the next tile's loads overlap the writes.
+template <typename E, bool kFull, class Dest, class Prefetch>
+__device__ __forceinline__ void split_tile_step(const E (&v)[SplitElem<E>::kPer], uint32_t tn, uint32_t nd,
+                                                Dest dest, SplitLds<E>& L, E* __restrict__ out, Prefetch prefetch) {
+  constexpr int kPer = SplitElem<E>::kPer;
+  const uint32_t tid = opaque_tid();
+  uint32_t qr[kPer];  // destination | rank within the tile << 8
+#pragma unroll
+  for (int r = 0; r < kPer; r++) {
+    const uint32_t q = dest(v[r]);
+    qr[r] = q;
+    if (kFull || (uint32_t)r * kCoarseThreads + tid < tn) qr[r] |= atomicAdd(&L.cnt[q], 1u) << 8;
+  }
+  lds_barrier();
+  if (tid < 64) {  // exclusive scan of the tile's counts by one wavefront, four per lane
+    uint32_t c[4], s = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint32_t x = tid * 4 + k;
+      c[k] = x < nd ? L.cnt[x] : 0u;
+      s += c[k];
+    }
+    uint32_t inc = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t y = __shfl_up(inc, d);
+      if (tid >= (uint32_t)d) inc += y;
+    }
+    uint32_t run = inc - s;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+      const uint32_t x = tid * 4 + k;
+      if (x < nd) {
+        L.tb[x] = run;
+        L.wofs[x] = L.gpos[x] - run;  // modulo 2^32: slot s of destination x goes to wofs[x] + s
+        L.gpos[x] += c[k];
+        L.cnt[x] = 0;
+      }
+      run += c[k];
+    }
+  }
+  lds_barrier();
+#pragma unroll
+  for (int r = 0; r < kPer; r++) {
+    if (kFull || (uint32_t)r * kCoarseThreads + tid < tn) {
+      const uint32_t s = L.tb[qr[r] & 0xFF] + (qr[r] >> 8);
+      L.tile[s] = v[r];
+      L.dst[s] = (uint8_t)qr[r];
+    }
+  }
+  prefetch();
+  lds_barrier();
+#pragma unroll
+  for (int r = 0; r < kPer; r++) {
+    const uint32_t s = (uint32_t)r * kCoarseThreads + tid;
+    if (kFull || s < tn) out[L.wofs[L.dst[s]] + s] = L.tile[s];
+  }
+  lds_barrier();
+}
+
+// Moves in[a, b) to out, destination q of element v = dest(v) < nd <= kMaxDigits: the elements with
+// destination q go to out[start], out[start + 1], ... in the order they are met, where thread q
+// passes its destination's start.  Every thread of the workgroup calls it.  The first tile's loads
+// are issued before the starts go to LDS.  kPrefetch: the next tile is loaded while this one is
+// written (for long ranges; it costs registers).
+template <typename E, bool kPrefetch, class Dest>
 __device__ __forceinline__ void split_range(const E* __restrict__ in, uint64_t a, uint64_t b, uint32_t nd,
-                                            Dest dest, SplitLds<E>& L, E* __restrict__ out) {
+                                            uint32_t start, Dest dest, SplitLds<E>& L, E* __restrict__ out) {
   constexpr int kPer = SplitElem<E>::kPer;
   constexpr uint32_t T = split_tile<E>();
-  const uint32_t tid = threadIdx.x;
+  E v[kPer], w[kPer];
+  if (a < b) split_load<E>(in, a, b, v);
+  if (threadIdx.x < nd) {
+    L.cnt[threadIdx.x] = 0;
+    L.gpos[threadIdx.x] = start;
+  }
+  lds_barrier();
   for (uint64_t t0 = a; t0 < b; t0 += T) {
-    const uint32_t tn = (uint32_t)min<uint64_t>(T, b - t0);
-    E v[kPer];
-    uint32_t q[kPer], rk[kPer];
+    const uint64_t t1 = t0 + T;
+    if (!kPrefetch && t0 != a) split_load<E>(in, t0, b, v);
+    auto prefetch = [&]() {
+      if (kPrefetch && t1 < b) split_load<E>(in, t1, b, w);
+    };
+    if (t1 <= b)
+      split_tile_step<E, true>(v, T, nd, dest, L, out, prefetch);
+    else
+      split_tile_step<E, false>(v, (uint32_t)(b - t0), nd, dest, L, out, prefetch);
+    if (kPrefetch)
 #pragma unroll
-    for (int r = 0; r < kPer; r++) {
-      const uint32_t i = (uint32_t)r * kCoarseThreads + tid;
-      if (i < tn) v[r] = in[t0 + i];
-    }
-#pragma unroll
-    for (int r = 0; r < kPer; r++) {
-      const uint32_t i = (uint32_t)r * kCoarseThreads + tid;
-      if (i < tn) {
-        q[r] = dest(v[r]);
-        rk[r] = atomicAdd(&L.cnt[q[r]], 1u);
-      }
-    }
-    __syncthreads();
-    if (tid < 64) {  // exclusive scan of the tile's counts by one wavefront, four per lane
-      uint32_t c[4], s = 0;
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const uint32_t x = tid * 4 + k;
-        c[k] = x < nd ? L.cnt[x] : 0u;
-        s += c[k];
-      }
-      uint32_t inc = s;
-#pragma unroll
-      for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(inc, d);
-        if (tid >= (uint32_t)d) inc += y;
-      }
-      uint32_t run = inc - s;
-#pragma unroll
-      for (int k = 0; k < 4; k++) {
-        const uint32_t x = tid * 4 + k;
-        if (x < nd) {
-          L.tb[x] = run;
-          L.wofs[x] = L.gpos[x] - run;  // modulo 2^32: slot s of destination x goes to wofs[x] + s
-          L.gpos[x] += c[k];
-          L.cnt[x] = 0;
-        }
-        run += c[k];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < kPer; r++) {
-      const uint32_t i = (uint32_t)r * kCoarseThreads + tid;
-      if (i < tn) {
-        const uint32_t s = L.tb[q[r]] + rk[r];
-        L.tile[s] = v[r];
-        L.dst[s] = (uint8_t)q[r];
-      }
-    }
-    __syncthreads();
-    for (uint32_t s = tid; s < tn; s += kCoarseThreads) out[L.wofs[L.dst[s]] + s] = L.tile[s];
-    __syncthreads();
+      for (int r = 0; r < kPer; r++) v[r] = w[r];
   }
 }
 
 // Row r (the count's workgroup r, keys [r per, (r + 1) per)) to its share of every digit.
 template <typename E>
-__global__ __launch_bounds__(kCoarseThreads) void k_split_digits(const E* __restrict__ in, uint64_t n, uint64_t per,
-                                                                 uint64_t seed, uint64_t K, uint32_t gshift,
-                                                                 uint32_t dshift, uint32_t D, uint32_t R,
-                                                                 const uint32_t* __restrict__ doff,
-                                                                 E* __restrict__ out) {
+__global__ __launch_bounds__(kCoarseThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_split_digits(
+    const E* __restrict__ in, uint64_t n, uint64_t per, uint64_t seed, uint64_t K, uint32_t gshift, uint32_t dshift,
+    uint32_t D, uint32_t R, const uint32_t* __restrict__ doff, E* __restrict__ out) {
   extern __shared__ __align__(16) uint32_t lds[];
   SplitLds<E> L(lds);
-  const uint32_t tid = threadIdx.x, r = blockIdx.x;
-  for (uint32_t d = tid; d < D; d += kCoarseThreads) {
-    L.cnt[d] = 0;
-    L.gpos[d] = doff[(uint64_t)d * (R + 1) + r];
-  }
-  __syncthreads();
-  const uint64_t a = (uint64_t)r * per, b = min(n, a + per);
-  split_range<E>(
-      in, a, b, D, [=](const E& v) { return SplitElem<E>::bin(v, seed, K, gshift) >> dshift; }, L, out);
+  const uint32_t r = blockIdx.x;
+  const uint64_t a = min(n, (uint64_t)r * per), b = min(n, a + per);
+  const uint32_t start = threadIdx.x < D ? doff[(uint64_t)threadIdx.x * (R + 1) + r] : 0u;
+  split_range<E, true>(
+      in, a, b, D, start, [=](const E& v) { return SplitElem<E>::bin(v, seed, K, gshift) >> dshift; }, L, out);
 }
 
-// Workgroup d Q + s: slice s of digit d (the shares of rows [s g, s g + g)) to its 2^dshift bins.
-template <typename E>
-__global__ __launch_bounds__(kCoarseThreads) void k_split_bins(const E* __restrict__ in, uint64_t seed, uint64_t K,
-                                                               uint32_t gshift, uint32_t dshift, uint32_t C,
-                                                               uint32_t R, uint32_t g, uint32_t Q,
-                                                               const uint32_t* __restrict__ doff,
-                                                               const uint32_t* __restrict__ hrow,
-                                                               uint32_t* __restrict__ cur, E* __restrict__ out) {
-  extern __shared__ __align__(16) uint32_t lds[];
-  SplitLds<E> L(lds);
-  const uint32_t tid = threadIdx.x, d = blockIdx.x / Q, s = blockIdx.x % Q;
-  const uint32_t r0 = s * g, r1 = min(R, r0 + g), nb = 1u << dshift;
-  for (uint32_t x = tid; x < nb; x += kCoarseThreads) {
-    const uint32_t c = (d << dshift) + x;
+// One workgroup per digit d: spos[(d Q + s) 2^dshift + x] = where slice s of digit d (the shares of
+// rows [s g, s g + g)) starts in bin c = d 2^dshift + x; slices in order.
+__global__ __launch_bounds__(1024) void k_slice_offsets(const uint32_t* __restrict__ hrow,
+                                                        const uint64_t* __restrict__ cbase, uint32_t C, uint32_t R,
+                                                        uint32_t g, uint32_t Q, uint32_t dshift,
+                                                        uint32_t* __restrict__ spos) {
+  extern __shared__ __align__(16) uint32_t sv[];  // Q 2^dshift slice counts
+  const uint32_t d = blockIdx.x, nb = 1u << dshift, tid = threadIdx.x;
+  for (uint32_t e = tid; e < Q * nb; e += 1024) {
+    const uint32_t sl = e >> dshift, c = (d << dshift) + (e & (nb - 1));
+    const uint32_t r0 = sl * g, r1 = min(R, r0 + g);
     uint32_t v = 0;
     if (c < C)
       for (uint32_t r = r0; r < r1; r++) v += hrow[(uint64_t)r * C + c];
-    L.cnt[x] = 0;
-    L.gpos[x] = v ? atomicAdd(&cur[c], v) : 0u;
+    sv[e] = v;
   }
   __syncthreads();
+  for (uint32_t x = tid; x < nb; x += 1024) {
+    const uint32_t c = (d << dshift) + x;
+    uint32_t run = c < C ? (uint32_t)cbase[c] : 0u;
+    for (uint32_t sl = 0; sl < Q; sl++) {
+      spos[((uint64_t)d * Q + sl) * nb + x] = run;
+      run += sv[sl * nb + x];
+    }
+  }
+}
+
+// Workgroup d Q + s: slice s of digit d to its 2^dshift bins.
+template <typename E>
+__global__ __launch_bounds__(kCoarseThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_split_bins(
+    const E* __restrict__ in, uint64_t seed, uint64_t K, uint32_t gshift, uint32_t dshift, uint32_t R, uint32_t g,
+    uint32_t Q, const uint32_t* __restrict__ doff, const uint32_t* __restrict__ spos, E* __restrict__ out) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  SplitLds<E> L(lds);
+  const uint32_t d = blockIdx.x / Q, s = blockIdx.x % Q;
+  const uint32_t r0 = s * g, r1 = min(R, r0 + g), nb = 1u << dshift;
   const uint64_t a = doff[(uint64_t)d * (R + 1) + r0], b = doff[(uint64_t)d * (R + 1) + r1];
+  const uint32_t start = threadIdx.x < nb ? spos[(uint64_t)blockIdx.x * nb + threadIdx.x] : 0u;
   const uint32_t mask = nb - 1;
-  split_range<E>(
-      in, a, b, nb, [=](const E& v) { return SplitElem<E>::bin(v, seed, K, gshift) & mask; }, L, out);
+  split_range<E, false>(
+      in, a, b, nb, start, [=](const E& v) { return SplitElem<E>::bin(v, seed, K, gshift) & mask; }, L, out);
 }
 
 // Descending bitonic sort of keys[0, n) (n a power of two; entries beyond are zero) by one wavefront
@@ -1320,7 +1384,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   old_info[0] = old_info[1] = old_info[2] = 0;
 
   if (coarse_path) {
-    uint32_t *ccnt, *hrow, *drow, *doff, *cur;
+    uint32_t *ccnt, *hrow, *drow, *doff, *spos, *cur;
     uint64_t* cbase;
     ulonglong2 *codes = nullptr, *stage = nullptr;
     // R = 2 ngrp rows of per keys each (the count and the first split run one workgroup per row)
@@ -1330,10 +1394,19 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     uint32_t dshift = 0;
     while (((C + (1ULL << dshift) - 1) >> dshift) > kMaxDigits) dshift++;
     const uint32_t D = (uint32_t)((C + (1ULL << dshift) - 1) >> dshift);
+    // With one bin per digit the first split already leaves every bin in place.  Otherwise the
+    // second split takes slices of g rows' shares of a digit, about seven eighths of a tile, with
+    // at most kMaxSliceBins (slice, bin) starts per digit.
+    const bool two = dshift > 0;
+    const uint64_t T = str ? split_tile<ulonglong2>() : split_tile<uint64_t>();
+    uint32_t g = (uint32_t)std::min<uint64_t>(R, std::max<uint64_t>(1, T * 7 * D / (8 * per)));
+    g = std::max<uint32_t>(g, (uint32_t)(((uint64_t)R << dshift) + kMaxSliceBins - 1) / kMaxSliceBins);
+    const uint32_t Q = (R + g - 1) / g;
     PHOBIC_HIP(S.get(&ccnt, C));
     PHOBIC_HIP(S.get(&hrow, (uint64_t)R * C));
     PHOBIC_HIP(S.get(&drow, (uint64_t)R * D));
     PHOBIC_HIP(S.get(&doff, (uint64_t)D * (R + 1)));
+    PHOBIC_HIP(S.get(&spos, ((uint64_t)D * Q) << dshift));
     PHOBIC_HIP(S.get(&cur, C));
     PHOBIC_HIP(S.get(&cbase, C + 1));
     uint64_t* kcodes = nullptr;  // u64 keys: the keys themselves travel through the splits
@@ -1357,35 +1430,29 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     tm.mark();  // 1
     hipLaunchKernelGGL(k_coarse_scan, dim3(1), dim3(1024), 0, st, ccnt, (uint32_t)C, cbase, cur);
     hipLaunchKernelGGL(k_digit_offsets, dim3(D), dim3(1024), 0, st, drow, cbase, R, D, dshift, doff);
+    if (two)
+      hipLaunchKernelGGL(k_slice_offsets, dim3(D), dim3(1024), ((size_t)Q << dshift) * sizeof(uint32_t), st, hrow,
+                         cbase, (uint32_t)C, R, g, Q, dshift, spos);
     tm.mark();  // 2
-    // With one bin per digit the first split already leaves every bin in place.  The slices of the
-    // second split hold the shares of g rows, about three quarters of a tile.
-    const bool two = dshift > 0;
     if (str) {
-      constexpr uint32_t T = split_tile<ulonglong2>();
-      const uint32_t g = (uint32_t)std::min<uint64_t>(R, std::max<uint64_t>(1, (uint64_t)T * 3 * D / (4 * per)));
-      const uint32_t Q = (R + g - 1) / g;
       hipLaunchKernelGGL(k_split_digits<ulonglong2>, dim3(R), dim3(kCoarseThreads), split_lds_bytes<ulonglong2>(),
                          st, (const ulonglong2*)stage, n, per, prm.hash_seed, K, (uint32_t)gshift, dshift, D, R,
                          doff, codes);
       if (two) {
         hipLaunchKernelGGL(k_split_bins<ulonglong2>, dim3(D * Q), dim3(kCoarseThreads),
                            split_lds_bytes<ulonglong2>(), st, (const ulonglong2*)codes, prm.hash_seed, K,
-                           (uint32_t)gshift, dshift, (uint32_t)C, R, g, Q, doff, hrow, cur, stage);
+                           (uint32_t)gshift, dshift, R, g, Q, doff, spos, stage);
         std::swap(codes, stage);  // the bins are in `codes` from here on
       }
     } else {
-      constexpr uint32_t T = split_tile<uint64_t>();
-      const uint32_t g = (uint32_t)std::min<uint64_t>(R, std::max<uint64_t>(1, (uint64_t)T * 3 * D / (4 * per)));
-      const uint32_t Q = (R + g - 1) / g;
       // the fingerprint array is free until the bucket sort and holds the digits in between
       uint64_t* mid = two ? sortedf : kcodes;
       hipLaunchKernelGGL(k_split_digits<uint64_t>, dim3(R), dim3(kCoarseThreads), split_lds_bytes<uint64_t>(), st,
                          in.keys, n, per, prm.hash_seed, K, (uint32_t)gshift, dshift, D, R, doff, mid);
       if (two)
         hipLaunchKernelGGL(k_split_bins<uint64_t>, dim3(D * Q), dim3(kCoarseThreads), split_lds_bytes<uint64_t>(),
-                           st, (const uint64_t*)mid, prm.hash_seed, K, (uint32_t)gshift, dshift, (uint32_t)C, R, g,
-                           Q, doff, hrow, cur, kcodes);
+                           st, (const uint64_t*)mid, prm.hash_seed, K, (uint32_t)gshift, dshift, R, g, Q, doff, spos,
+                           kcodes);
     }
     tm.mark();  // 3
     if (str)
