@@ -289,6 +289,8 @@ constexpr uint32_t kMaxSliceBins = 16384; // (slice, bin) starts of one digit (6
 constexpr int kSegThreads = 512;
 constexpr uint32_t kMaxG = 8;
 constexpr size_t kSegLdsBytes = 61440;   // dynamic LDS of k_segment_sort
+constexpr int kSegBatch = 6;             // items of a k_segment_sort thread loaded together (5 for
+                                         // 16-byte records: their registers would spill)
 
 template <bool kStr>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_count(const uint64_t* __restrict__ keys,
@@ -664,7 +666,7 @@ __device__ __forceinline__ void wave_sort_keys(uint32_t* keys, uint32_t nbpad, u
 // batch, this launch covers [jbase, jend), and kbase is the global index of its first key.
 enum { kInCodes = 0, kInKeys = 1, kInRecords = 2 };
 template <int kIn>
-__global__ __launch_bounds__(kSegThreads) void k_segment_sort(const void* __restrict__ src, uint64_t seed,
+__global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_segment_sort(const void* __restrict__ src, uint64_t seed,
                                                               const uint64_t* __restrict__ cbase,
                                                               const uint64_t* __restrict__ T, uint32_t B,
                                                               uint32_t nbpad, uint32_t gshift, uint64_t K,
@@ -695,25 +697,45 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const void* __rest
   for (uint32_t x = tid; x < span; x += kSegThreads) cnt[x] = 0;
   if (tid < kMaxG) { psize[tid] = 0; nonempty[tid] = 0; }
   __syncthreads();
+  // Items in batches of kSegBatch: the batch's loads are unconditional (the index clamped to the
+  // bin), then its hashes and bucket-table reads, so each batch costs one round trip of each
+  // instead of one per item; only the LDS ranking is guarded.
+  constexpr int kBat = kIn == kInRecords ? kSegBatch - 1 : kSegBatch;
   uint64_t fp[kItems];
+  const uint32_t nit = (ns + kSegThreads - 1) / kSegThreads;
 #pragma unroll
-  for (int t = 0; t < kItems; t++) {
-    const uint32_t i = tid + t * kSegThreads;
-    if (i < ns) {
-      ulonglong2 cd;
+  for (int t0 = 0; t0 < kItems; t0 += kBat) {
+    if ((uint32_t)t0 >= nit) break;
+    ulonglong2 cd[kBat];
+#pragma unroll
+    for (int u = 0; u < kBat; u++) {
+      const uint32_t i = min(tid + (uint32_t)(t0 + u) * kSegThreads, ns - 1);
+      if (kIn == kInKeys) {
+        cd[u].x = ((const uint64_t*)src)[base + i];
+      } else {
+        cd[u] = ((const ulonglong2*)src)[base + i];
+      }
+    }
+    uint32_t pb[kBat];  // partition << 16 | bucket
+#pragma unroll
+    for (int u = 0; u < kBat; u++) {
       if (kIn == kInKeys) {
         uint64_t hi, lo;
-        hash_key_u64(((const uint64_t*)src)[base + i], seed, hi, lo);
-        cd = make_ulonglong2(hi, lo);
-      } else {
-        cd = ((const ulonglong2*)src)[base + i];
+        hash_key_u64(cd[u].x, seed, hi, lo);
+        cd[u] = make_ulonglong2(hi, lo);
       }
-      const bool records = kIn == kInRecords;
-      const uint32_t p = records ? (uint32_t)(cd.y & 7) : (uint32_t)(__umul64hi(cd.x, K) - j0);
-      const uint32_t b = bucket_of(cd.y, T, B);
-      const uint32_t r = atomicAdd(&cnt[p * nbpad + b], 1u);
-      rec[i] = (p << 29) | (b << 16) | r;
-      fp[t] = records ? (uint64_t)cd.x : fingerprint(cd.x, cd.y);
+      const uint32_t p = kIn == kInRecords ? (uint32_t)(cd[u].y & 7) : (uint32_t)(__umul64hi(cd[u].x, K) - j0);
+      pb[u] = (p << 16) | bucket_of(cd[u].y, T, B);
+    }
+#pragma unroll
+    for (int u = 0; u < kBat; u++) {
+      const uint32_t i = tid + (uint32_t)(t0 + u) * kSegThreads;
+      if (t0 + u < kItems && i < ns) {
+        const uint32_t p = pb[u] >> 16, b = pb[u] & 0xFFFF;
+        const uint32_t r = atomicAdd(&cnt[p * nbpad + b], 1u);
+        rec[i] = (p << 29) | (b << 16) | r;
+        fp[t0 + u] = kIn == kInRecords ? (uint64_t)cd[u].x : fingerprint(cd[u].x, cd[u].y);
+      }
     }
   }
   __syncthreads();
