@@ -250,9 +250,9 @@ uint32_t phobic_ref_rice_param(uint64_t sum, uint64_t count) {
 /* ----------------------------------------------------------------------------------------------
  * The image: header words, then sections (each followed by one zero word).
  * -------------------------------------------------------------------------------------------- */
-#define MAGIC 0x31304349424F4850ULL /* "PHOBIC01" */
+#define MAGIC 0x32304349424F4850ULL /* "PHOBIC02" */
 #define HDR_WORDS 24
-#define SEL_EVERY 256 /* one select sample per 256 ones of the unary stream */
+#define SEL_EVERY 128 /* one select sample per 128 ones of the unary stream */
 enum {
   H_MAGIC = 0, H_N, H_K, H_B, H_P, H_LAMBDA, H_ALPHA, H_CODING, H_SEED, H_TOTAL, H_DMIN, H_WOFF,
   H_SEC_OFF, H_SEC_ENC, H_SEC_DATA, H_SEC_UNARY, H_SEC_SEL, H_SEC_REMAP, H_WREMAP, H_NREMAP,

@@ -951,7 +951,7 @@ __global__ __launch_bounds__(kBlock) void k_pack_offsets(const uint64_t* __restr
 
 // One workgroup of 1024 threads per encoder i: low bits (or Compact values) at base_i + j w_i; for
 // Rice the unary stream of q = v >> w_i (q zeros then a one), whose one for value t = i K + j sits at
-// ubase_i + sum_{j' < j} (q_j' + 1) + q_j, and a select sample for every 256th one.
+// ubase_i + sum_{j' < j} (q_j' + 1) + q_j, and a select sample for every 128th one.
 //
 // Values go through in chunks of 4096.  A chunk's low bits (at most 4096 x 32 bits) and, when they
 // fit, its unary bits are assembled in LDS and written out as whole words: plain stores for the

@@ -23,7 +23,7 @@ constexpr uint32_t kMaxPartitionKeys = 8192;  // n_j
 constexpr uint32_t kMaxTableSlots = 16384;    // m_j (alpha < 1 enlarges n_j)
 constexpr uint32_t kMaxBuckets = 2048;        // B
 constexpr uint32_t kTableIntervals = 2048;    // bucket-function table: 2048 intervals, 2049 points
-constexpr uint32_t kSelEvery = 256;           // one select sample per 256 ones
+constexpr uint32_t kSelEvery = 128;           // one select sample per 128 ones
 
 // Image header word indices (little-endian 64-bit words).
 enum : uint32_t {
@@ -31,7 +31,7 @@ enum : uint32_t {
   kHSecOff, kHSecEnc, kHSecData, kHSecUnary, kHSecSel, kHSecRemap, kHWremap, kHNremap, kHUbits,
   kHWords, kHR, kHSpare, kHeaderWords
 };
-constexpr uint64_t kMagic = 0x31304349424F4850ULL;  // "PHOBIC01"
+constexpr uint64_t kMagic = 0x32304349424F4850ULL;  // "PHOBIC02"
 
 // Everything a query kernel needs, passed by value.
 struct QueryArgs {
