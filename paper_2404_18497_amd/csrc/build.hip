@@ -306,18 +306,28 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_count(const uint64_t*
   const uint32_t tid = threadIdx.x;
   for (uint32_t x = tid; x < C; x += kCoarseThreads) hist[x] = 0;
   __syncthreads();
-  const uint64_t a = (uint64_t)blockIdx.x * per, b = min(n, a + per);
-  for (uint64_t i = a + tid; i < b; i += kCoarseThreads) {
-    uint64_t hi;
-    if (kStr) {
-      uint64_t lo;
+  const uint64_t a = min(n, (uint64_t)blockIdx.x * per), b = min(n, a + per);
+  if (kStr) {
+    for (uint64_t i = a + tid; i < b; i += kCoarseThreads) {
+      uint64_t hi, lo;
       const uint64_t s0 = offs[i], s1 = offs[i + 1];
       hash_key_str(bytes + s0, s1 - s0, seed, hi, lo);
       stage[i] = make_ulonglong2(hi, lo);
-    } else {
-      hi = mix_a(keys[i] ^ seed);
+      atomicAdd(&hist[(uint32_t)__umul64hi(hi, K) >> gshift], 1u);
     }
-    atomicAdd(&hist[(uint32_t)__umul64hi(hi, K) >> gshift], 1u);
+  } else {
+    // four keys per thread and round, loaded unconditionally (index clamped to the range) so that
+    // they are in flight together
+    constexpr int kU = 4;
+    for (uint64_t i0 = a + tid; i0 < b; i0 += (uint64_t)kU * kCoarseThreads) {
+      uint64_t v[kU];
+#pragma unroll
+      for (int u = 0; u < kU; u++) v[u] = keys[min(i0 + (uint64_t)u * kCoarseThreads, b - 1)];
+#pragma unroll
+      for (int u = 0; u < kU; u++)
+        if (i0 + (uint64_t)u * kCoarseThreads < b)
+          atomicAdd(&hist[(uint32_t)__umul64hi(mix_a(v[u] ^ seed), K) >> gshift], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t x = tid; x < C; x += kCoarseThreads) {
