@@ -250,9 +250,15 @@ uint32_t phobic_ref_rice_param(uint64_t sum, uint64_t count) {
 /* ----------------------------------------------------------------------------------------------
  * The image: header words, then sections (each followed by one zero word).
  * -------------------------------------------------------------------------------------------- */
-#define MAGIC 0x32304349424F4850ULL /* "PHOBIC02" */
+#define MAGIC 0x33304349424F4850ULL /* "PHOBIC03" */
 #define HDR_WORDS 24
-#define SEL_EVERY 128 /* one select sample per 128 ones of the unary stream */
+/* Select samples of the unary stream: one 64-bit entry per SEL_BLOCK ones.  Entry s holds the
+ * position of one number SEL_BLOCK*s in its low 32 bits, and for k = 1, 2, 3 the distance from there
+ * to one number SEL_BLOCK*s + SEL_SUB*k in the 10-bit field at bit 32 + 10(k-1); SEL_REL_NONE when
+ * the distance does not fit (and 0 for ones past the end of the stream). */
+#define SEL_BLOCK 256
+#define SEL_SUB 64
+#define SEL_REL_NONE 1023
 enum {
   H_MAGIC = 0, H_N, H_K, H_B, H_P, H_LAMBDA, H_ALPHA, H_CODING, H_SEED, H_TOTAL, H_DMIN, H_WOFF,
   H_SEC_OFF, H_SEC_ENC, H_SEC_DATA, H_SEC_UNARY, H_SEC_SEL, H_SEC_REMAP, H_WREMAP, H_NREMAP,
@@ -500,9 +506,9 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
   uint64_t sec_data = sec_enc + B + 1;
   uint64_t sec_unary = sec_data + (data_bits + 63) / 64 + 1;
   uint64_t nvals = K * B;
-  uint64_t nsel = rice ? (nvals + SEL_EVERY - 1) / SEL_EVERY : 0;
+  uint64_t nsel = rice ? (nvals + SEL_BLOCK - 1) / SEL_BLOCK : 0;
   uint64_t sec_sel = sec_unary + (rice ? (unary_bits + 63) / 64 + 1 : 0);
-  uint64_t sec_remap = sec_sel + (rice ? (nsel + 1) / 2 + 1 : 0);
+  uint64_t sec_remap = sec_sel + (rice ? nsel + 1 : 0);
   uint64_t total = sec_remap + (nremap ? (nremap * wremap + 63) / 64 + 1 : 0);
 
   uint64_t *w = calloc(total, sizeof(uint64_t));
@@ -549,9 +555,15 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
       if (rice) {
         upos += v >> wd;
         w[sec_unary + (upos >> 6)] |= (uint64_t)1 << (upos & 63);
-        if (ones % SEL_EVERY == 0) {
-          uint64_t t = ones / SEL_EVERY;
-          w[sec_sel + t / 2] |= (upos & 0xFFFFFFFFULL) << (32 * (t & 1));
+        if (ones % SEL_SUB == 0) {
+          uint64_t *e = &w[sec_sel + ones / SEL_BLOCK];
+          unsigned k = (unsigned)(ones % SEL_BLOCK / SEL_SUB);
+          if (k == 0) {
+            *e = upos & 0xFFFFFFFFULL;
+          } else {
+            uint64_t rel = upos - (*e & 0xFFFFFFFFULL);
+            *e |= (rel < SEL_REL_NONE ? rel : SEL_REL_NONE) << (32 + 10 * (k - 1));
+          }
         }
         ones++;
         upos++;
@@ -677,10 +689,17 @@ fail:
  * 8. Query, reading only the image.
  * -------------------------------------------------------------------------------------------- */
 static uint64_t select_one(const uint64_t *unary, const uint64_t *sel, uint64_t t) {
-  /* position of the t-th one (t counted from 0) of the unary stream */
-  uint64_t s = t / SEL_EVERY;
-  uint64_t pos = (sel[s / 2] >> (32 * (s & 1))) & 0xFFFFFFFFULL;
-  uint64_t left = t - s * SEL_EVERY;
+  /* position of the t-th one (t counted from 0) of the unary stream: from the nearest sample at or
+   * before it, then one bit at a time */
+  uint64_t e = sel[t / SEL_BLOCK];
+  uint64_t pos = e & 0xFFFFFFFFULL;
+  uint64_t left = t % SEL_BLOCK;
+  unsigned k = (unsigned)(left / SEL_SUB);
+  uint64_t rel = k ? (e >> (32 + 10 * (k - 1))) & 1023 : SEL_REL_NONE;
+  if (rel != SEL_REL_NONE) {
+    pos += rel;
+    left %= SEL_SUB;
+  }
   for (;;) {
     if ((unary[pos >> 6] >> (pos & 63)) & 1) {
       if (left == 0) return pos;

@@ -8,6 +8,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <algorithm>
 #include <vector>
 
 #include "phobic_internal.h"
@@ -122,7 +123,7 @@ std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phob
   const bool rice = prm.coding == PHOBIC_IC_RICE;
   const uint64_t nremap = total - n;
   const uint32_t wremap = n > 1 ? host_bit_length_pub(n - 1) : 0;
-  const uint64_t nsel = rice ? (K * B + kSelEvery - 1) / kSelEvery : 0;
+  const uint64_t nsel = rice ? (K * B + kSelBlock - 1) / kSelBlock : 0;
   std::vector<uint64_t> hdr(kHeaderWords, 0);
   hdr[kHMagic] = kMagic;
   hdr[kHN] = n;
@@ -141,7 +142,7 @@ std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phob
   hdr[kHSecData] = hdr[kHSecEnc] + B + 1;
   hdr[kHSecUnary] = hdr[kHSecData] + (data_bits + 63) / 64 + 1;
   hdr[kHSecSel] = hdr[kHSecUnary] + (rice ? (unary_bits + 63) / 64 + 1 : 0);
-  hdr[kHSecRemap] = hdr[kHSecSel] + (rice ? (nsel + 1) / 2 + 1 : 0);
+  hdr[kHSecRemap] = hdr[kHSecSel] + (rice ? nsel + 1 : 0);
   hdr[kHWremap] = wremap;
   hdr[kHNremap] = nremap;
   hdr[kHUbits] = rice ? unary_bits : 0;
@@ -226,29 +227,40 @@ static phobic_status check_image(const uint64_t* w, uint64_t nwords) {
     uint64_t ones = 0;
     for (uint64_t i = 0; i < (ubits + 63) / 64; i++) ones += __builtin_popcountll(w[su + i]);
     if (ones != nvals || w[ss - 1] != 0) return bad("unary stream");
-    const uint64_t nsel = (nvals + kSelEvery - 1) / kSelEvery;
-    if (ss + (nsel + 1) / 2 + 1 != sr) return bad("select length");
-    // every sample must be exactly the position of one number 256 s
-    const uint32_t* sel = (const uint32_t*)(w + ss);
+    const uint64_t nsel = (nvals + kSelBlock - 1) / kSelBlock;
+    if (ss + nsel + 1 != sr) return bad("select length");
+    // every entry must hold exactly the position of one number kSelBlock s and the distances to ones
+    // kSelBlock s + kSelSub k: positions of every kSelSub-th one first
+    std::vector<uint64_t> p64((nvals + kSelSub - 1) / kSelSub);
     uint64_t seen = 0, s_next = 0;
-    for (uint64_t i = 0; i < (ubits + 63) / 64 && s_next < nsel; i++) {
+    for (uint64_t i = 0; i < (ubits + 63) / 64 && s_next < p64.size(); i++) {
       uint64_t x = w[su + i];
-      while (x && s_next < nsel) {
+      while (x && s_next < p64.size()) {
         const uint64_t c = (uint64_t)__builtin_popcountll(x);
-        const uint64_t want = s_next * kSelEvery;
+        const uint64_t want = s_next * kSelSub;
         if (seen + c <= want) {
           seen += c;
           break;
         }
         for (uint64_t skip = want - seen; skip; skip--) x &= x - 1;  // drop ones before the target
-        const uint64_t pos = i * 64 + (uint64_t)__builtin_ctzll(x);
-        if (sel[s_next] != pos) return bad("select samples");
+        p64[s_next++] = i * 64 + (uint64_t)__builtin_ctzll(x);
         seen = want + 1;
         x &= x - 1;
-        s_next++;
       }
     }
-    if (s_next != nsel) return bad("select samples");
+    if (s_next != p64.size()) return bad("select samples");
+    constexpr uint32_t per = kSelBlock / kSelSub;
+    for (uint64_t sb = 0; sb < nsel; sb++) {
+      const uint64_t a0 = p64[sb * per];
+      if (a0 >> 32) return bad("select range");
+      uint64_t want = a0;
+      for (uint32_t k = 1; k < per; k++) {
+        const uint64_t idx = sb * per + k;
+        const uint64_t rel = idx < p64.size() ? std::min<uint64_t>(p64[idx] - a0, kSelRelNone) : 0;
+        want |= rel << (32 + 10 * (k - 1));
+      }
+      if (w[ss + sb] != want) return bad("select samples");
+    }
   } else if (su != ss || ss != sr) {
     return bad("compact layout");
   }

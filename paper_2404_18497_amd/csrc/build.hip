@@ -979,6 +979,14 @@ __device__ __forceinline__ void lds_put_bits(uint64_t* buf, uint64_t rel, uint64
   if (sh + w > 64) atomicOr((unsigned long long*)&buf[idx + 1], (unsigned long long)(v >> (64 - sh)));
 }
 
+
+// Sub-sample distances of every select entry (the encoder wrote the samples), one thread per entry.
+__global__ __launch_bounds__(kBlock) void k_sel_fill(const uint64_t* __restrict__ un, uint64_t* __restrict__ sel,
+                                                     uint64_t nsel, uint64_t nvals) {
+  for (uint64_t s = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; s < nsel; s += (uint64_t)gridDim.x * blockDim.x)
+    sel_fill_entry(un, sel, s, nvals);
+}
+
 // Writes buf[0 .. last] to dst[first .. first + last]: interior words stored, the two end words ORed.
 __device__ __forceinline__ void flush_words(const uint64_t* buf, uint64_t* __restrict__ dst, uint64_t first,
                                             uint32_t last, uint32_t tid) {
@@ -996,7 +1004,7 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __
                                                               const uint64_t* __restrict__ enc,
                                                               const uint64_t* __restrict__ ubase, uint32_t rice,
                                                               uint64_t* __restrict__ data, uint64_t* __restrict__ unary,
-                                                              uint32_t* __restrict__ sel) {
+                                                              uint64_t* __restrict__ sel) {
   __shared__ uint64_t part[kPackThreads / 64];
   __shared__ uint64_t chunk_total;
   __shared__ uint64_t dbuf[kPackWords];
@@ -1061,7 +1069,7 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __
           else
             atomicOr((unsigned long long*)&unary[pos >> 6], 1ULL << (pos & 63));
           const uint64_t t_glob = (uint64_t)i * K + jj;
-          if ((t_glob & (kSelEvery - 1)) == 0) sel[t_glob / kSelEvery] = (uint32_t)pos;
+          if ((t_glob & (kSelBlock - 1)) == 0) sel[t_glob / kSelBlock] = pos;
           excl = pos + 1;
         }
       }
@@ -1683,8 +1691,10 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     hipLaunchKernelGGL(k_pack_offsets, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, toff, K, R, dmin, woff,
                        img + hdr[kHSecOff]);
   hipLaunchKernelGGL(k_pack_values, dim3(B), dim3(kPackThreads), 0, st, pilots, K, img + hdr[kHSecEnc], d_ubase,
-                     (uint32_t)rice, img + hdr[kHSecData], img + hdr[kHSecUnary],
-                     (uint32_t*)(img + hdr[kHSecSel]));
+                     (uint32_t)rice, img + hdr[kHSecData], img + hdr[kHSecUnary], img + hdr[kHSecSel]);
+  if (rice && K * B)
+    hipLaunchKernelGGL(k_sel_fill, dim3(grid_for((K * B + kSelBlock - 1) / kSelBlock)), dim3(kBlock), 0, st,
+                       img + hdr[kHSecUnary], img + hdr[kHSecSel], (K * B + kSelBlock - 1) / kSelBlock, K * B);
   PHOBIC_HIP(hipGetLastError());
   if (nremap && wremap) {
     uint32_t *fc, *oc, *freeslot;
@@ -1975,7 +1985,7 @@ __global__ __launch_bounds__(256) void k_batch_pack_vals(const uint32_t* __restr
       else
         atomicOr((unsigned long long*)&unary[pos >> 6], 1ULL << (pos & 63));
       const uint64_t tg = (uint64_t)i * K + j;
-      if ((tg & (kSelEvery - 1)) == 0) ((uint32_t*)(img + h[kHSecSel]))[tg / kSelEvery] = (uint32_t)pos;
+      if ((tg & (kSelBlock - 1)) == 0) img[h[kHSecSel] + tg / kSelBlock] = pos;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1985,6 +1995,17 @@ __global__ __launch_bounds__(256) void k_batch_pack_vals(const uint32_t* __restr
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
+}
+
+// Sub-sample distances of the select entries of every MPHF of a batch, one workgroup per MPHF.
+__global__ __launch_bounds__(256) void k_batch_sel_fill(const BatchDesc* __restrict__ d, uint32_t B,
+                                                        const uint64_t* __restrict__ hdrs,
+                                                        const uint64_t* __restrict__ ibase, uint64_t* __restrict__ buf) {
+  const uint32_t t = blockIdx.x;
+  const uint64_t* h = hdrs + (uint64_t)t * kHeaderWords;
+  uint64_t* img = buf + ibase[t];
+  const uint64_t nvals = d[t].K * B, nsel = (nvals + kSelBlock - 1) / kSelBlock;
+  for (uint64_t s = threadIdx.x; s < nsel; s += blockDim.x) sel_fill_entry(img + h[kHSecUnary], img + h[kHSecSel], s, nvals);
 }
 
 phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* counts, uint32_t count,
@@ -2247,6 +2268,8 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   hipLaunchKernelGGL(k_batch_pack_off, dim3(mphf_groups), dim3(256), 0, st, off, d_desc, count, dh, dib, bufw);
   hipLaunchKernelGGL(k_batch_pack_vals, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, dh, de, du,
                      dib, bufw);
+  if (prm.coding == PHOBIC_IC_RICE)
+    hipLaunchKernelGGL(k_batch_sel_fill, dim3(count), dim3(256), 0, st, d_desc, B, dh, dib, bufw);
   PHOBIC_HIP(hipGetLastError());
   tm.mark();  // 4
   PHOBIC_HIP(hipStreamSynchronize(st));

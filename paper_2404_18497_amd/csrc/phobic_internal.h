@@ -23,7 +23,13 @@ constexpr uint32_t kMaxPartitionKeys = 8192;  // n_j
 constexpr uint32_t kMaxTableSlots = 16384;    // m_j (alpha < 1 enlarges n_j)
 constexpr uint32_t kMaxBuckets = 2048;        // B
 constexpr uint32_t kTableIntervals = 2048;    // bucket-function table: 2048 intervals, 2049 points
-constexpr uint32_t kSelEvery = 128;           // one select sample per 128 ones
+// Select samples of the unary stream, one 64-bit entry per kSelBlock ones: entry s holds the position
+// of one number kSelBlock s in its low 32 bits and, for k = 1, 2, 3, the distance from there to one
+// number kSelBlock s + kSelSub k in the 10-bit field at bit 32 + 10 (k - 1); kSelRelNone when the
+// distance does not fit, 0 for ones past the end of the stream.
+constexpr uint32_t kSelBlock = 256;
+constexpr uint32_t kSelSub = 64;
+constexpr uint32_t kSelRelNone = 1023;
 
 // Image header word indices (little-endian 64-bit words).
 enum : uint32_t {
@@ -31,7 +37,7 @@ enum : uint32_t {
   kHSecOff, kHSecEnc, kHSecData, kHSecUnary, kHSecSel, kHSecRemap, kHWremap, kHNremap, kHUbits,
   kHWords, kHR, kHSpare, kHeaderWords
 };
-constexpr uint64_t kMagic = 0x32304349424F4850ULL;  // "PHOBIC02"
+constexpr uint64_t kMagic = 0x33304349424F4850ULL;  // "PHOBIC03"
 
 // Everything a query kernel needs, passed by value.
 struct QueryArgs {
@@ -148,6 +154,54 @@ __device__ __forceinline__ uint64_t fingerprint(uint64_t hi, uint64_t lo) { retu
 // Seeded position hash h(x, s) in [0, m): w = (s + 1) * phi is the seed's Weyl value.
 __device__ __forceinline__ uint32_t pos_hash(uint64_t f, uint64_t w, uint32_t m) {
   return mulhi_u32(mix_a(f ^ w), m);
+}
+
+// Position of the r-th set bit (r from 0) of a 64-bit word that has more than r set bits.
+__device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t r) {
+  uint32_t pos = 0;
+  uint32_t c = __popc((uint32_t)x);
+  if (r >= c) { r -= c; x >>= 32; pos += 32; }
+  c = __popc((uint32_t)x & 0xFFFFu);
+  if (r >= c) { r -= c; x >>= 16; pos += 16; }
+  c = __popc((uint32_t)x & 0xFFu);
+  if (r >= c) { r -= c; x >>= 8; pos += 8; }
+  c = __popc((uint32_t)x & 0xFu);
+  if (r >= c) { r -= c; x >>= 4; pos += 4; }
+  c = __popc((uint32_t)x & 0x3u);
+  if (r >= c) { r -= c; x >>= 2; pos += 2; }
+  c = (uint32_t)(x & 1u);
+  if (r >= c) { pos += 1; }
+  return pos;
+}
+
+// Select entry s (of kSelBlock ones) of a unary stream with nvals ones whose low 32 bits already hold
+// the position of one number kSelBlock s: adds the distances to ones kSelBlock s + kSelSub k, k = 1,
+// 2, 3 (kSelRelNone from 1023 on, 0 past the last one).  Reads at most 17 words of the stream.
+__device__ __forceinline__ void sel_fill_entry(const uint64_t* __restrict__ un, uint64_t* __restrict__ sel,
+                                               uint64_t s, uint64_t nvals) {
+  const uint64_t a0 = sel[s] & 0xFFFFFFFFULL;
+  uint64_t out = a0, word = a0 >> 6;
+  const uint64_t last = (a0 + kSelRelNone) >> 6;  // words past it cannot hold a distance below 1023
+  uint64_t x = un[word] & (~0ULL << (a0 & 63));
+  uint32_t seen = 0;  // ones from a0 on before the bits of x
+  for (uint32_t k = 1; k < kSelBlock / kSelSub; k++) {
+    if (s * kSelBlock + k * kSelSub >= nvals) break;
+    const uint32_t want = k * kSelSub;  // one a0 is the 0th
+    uint64_t f = kSelRelNone;
+    for (;;) {
+      const uint32_t c = __popcll(x);
+      if (seen + c > want) {
+        const uint64_t rel = word * 64 + select_in_word(x, want - seen) - a0;
+        f = rel < kSelRelNone ? rel : kSelRelNone;
+        break;
+      }
+      if (word == last) break;
+      seen += c;
+      x = un[++word];
+    }
+    out |= f << (32 + 10 * (k - 1));
+  }
+  sel[s] = out;
 }
 
 // Bucket of a key: linear interpolation of the tabulated bucket function, scaled to B buckets.

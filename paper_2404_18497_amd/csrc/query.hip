@@ -20,32 +20,24 @@ namespace {
 
 constexpr int kQBlock = 256;
 
-// Position of the r-th set bit (r from 0) of a 64-bit word that has more than r set bits.
-__device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t r) {
-  uint32_t pos = 0;
-  uint32_t c = __popc((uint32_t)x);
-  if (r >= c) { r -= c; x >>= 32; pos += 32; }
-  c = __popc((uint32_t)x & 0xFFFFu);
-  if (r >= c) { r -= c; x >>= 16; pos += 16; }
-  c = __popc((uint32_t)x & 0xFFu);
-  if (r >= c) { r -= c; x >>= 8; pos += 8; }
-  c = __popc((uint32_t)x & 0xFu);
-  if (r >= c) { r -= c; x >>= 4; pos += 4; }
-  c = __popc((uint32_t)x & 0x3u);
-  if (r >= c) { r -= c; x >>= 2; pos += 2; }
-  c = (uint32_t)(x & 1u);
-  if (r >= c) { pos += 1; }
-  return pos;
+// From the select entry e of the block holding one ta: the position of a one at or before one ta
+// (the block's sample, or its sub-sample when ta lies past one and the distance was stored), and in
+// r how many ones separate the two.
+__device__ __forceinline__ uint64_t sel_start(uint64_t e, uint64_t ta, uint32_t& r) {
+  const uint32_t left = (uint32_t)(ta % kSelBlock), k = left / kSelSub;
+  const uint32_t rel = k ? (uint32_t)(e >> (32 + 10 * (k - 1))) & 1023u : kSelRelNone;
+  const bool sub = rel != kSelRelNone;
+  r = sub ? left % kSelSub : left;
+  return (e & 0xFFFFFFFFULL) + (sub ? rel : 0u);
 }
 
 // High part q of value t of the unary stream: q = (position of one t) - (position of one t-1) - 1,
-// with one -1 at position -1.  The select sample of one number 256 floor((t-1)/256) is read without
-// a preceding branch, so its load can issue as soon as t is known.
-__device__ __forceinline__ uint64_t unary_high(const uint64_t* __restrict__ un, const uint32_t* __restrict__ sel,
+// with one -1 at position -1.  The select entry of one t-1 is read without a preceding branch, so
+// its load can issue as soon as t is known.
+__device__ __forceinline__ uint64_t unary_high(const uint64_t* __restrict__ un, const uint64_t* __restrict__ sel,
                                                uint64_t t) {
   const uint64_t ta = t ? t - 1 : 0;
-  const uint64_t s = ta / kSelEvery;
-  const uint64_t sample = sel[s];
+  const uint64_t e = sel[ta / kSelBlock];
   uint64_t prev;  // position of one t-1, or UINT64_MAX for t = 0
   uint64_t word;
   uint64_t bits;
@@ -54,9 +46,10 @@ __device__ __forceinline__ uint64_t unary_high(const uint64_t* __restrict__ un, 
     word = 0;
     bits = un[0];
   } else {
-    uint32_t r = (uint32_t)(ta - s * kSelEvery);
-    word = sample >> 6;
-    bits = un[word] & (~0ULL << (sample & 63));
+    uint32_t r;
+    const uint64_t start = sel_start(e, ta, r);
+    word = start >> 6;
+    bits = un[word] & (~0ULL << (start & 63));
     for (;;) {
       uint32_t c = __popcll(bits);
       if (r < c) break;
@@ -108,7 +101,7 @@ __device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, 
   offset_pair(offs, j, a.woff, r0, r1);
   uint64_t p = get_bits(a.img + a.sec_data, (e >> 8) + j * w, w);
   if (a.coding == PHOBIC_IC_RICE) {
-    const uint64_t q = unary_high(a.img + a.sec_unary, (const uint32_t*)(a.img + a.sec_sel), (uint64_t)i * a.K + j);
+    const uint64_t q = unary_high(a.img + a.sec_unary, a.img + a.sec_sel, (uint64_t)i * a.K + j);
     p |= q << w;
   }
   const uint64_t o0 = expected_offset(j, a.R) + (uint64_t)a.dmin + r0;
@@ -135,7 +128,7 @@ __device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (
                                             uint64_t (&res)[kN]) {
   const uint64_t* __restrict__ offs = a.img + a.sec_off;
   const uint64_t* __restrict__ un = a.img + a.sec_unary;
-  const uint32_t* __restrict__ sel = (const uint32_t*)(a.img + a.sec_sel);
+  const uint64_t* __restrict__ sel = a.img + a.sec_sel;
   const bool rice = a.coding == PHOBIC_IC_RICE;
   uint64_t j[kN], e[kN], p[kN], r0[kN], r1[kN];
   uint32_t i[kN];
@@ -155,7 +148,7 @@ __device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (
     p[q] = get_bits(a.img + a.sec_data, (e[q] >> 8) + j[q] * w, w);
     t[q] = (uint64_t)i[q] * a.K + j[q];
     ta[q] = t[q] ? t[q] - 1 : 0;
-    sample[q] = rice ? sel[ta[q] / kSelEvery] : 0;
+    sample[q] = rice ? sel[ta[q] / kSelBlock] : 0;
   }
   if (rice) {
     uint64_t word[kN], bits[kN], prev[kN];
@@ -163,10 +156,10 @@ __device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (
     bool found[kN];
 #pragma unroll
     for (int q = 0; q < kN; q++) {
-      r[q] = (uint32_t)(ta[q] % kSelEvery);
-      word[q] = t[q] ? sample[q] >> 6 : 0;
+      const uint64_t start = sel_start(sample[q], ta[q], r[q]);
+      word[q] = t[q] ? start >> 6 : 0;
       bits[q] = un[word[q]];
-      if (t[q]) bits[q] &= ~0ULL << (sample[q] & 63);
+      if (t[q]) bits[q] &= ~0ULL << (start & 63);
       found[q] = t[q] == 0;
     }
     // the one of value t - 1: skip r ones from the sample

@@ -333,7 +333,7 @@ def test_encoder_parameters(ref, coding):
             assert widths[i] == int(col.max()).bit_length()
         else:
             assert widths[i] == ref.rice_param(int(col.sum()), K)
-    assert H["words"] == img.size and H["magic"] == int.from_bytes(b"PHOBIC02", "little")
+    assert H["words"] == img.size and H["magic"] == int.from_bytes(b"PHOBIC03", "little")
 
 
 # --------------------------------------------------------------------------------------------------
