@@ -93,6 +93,22 @@ def test_lambda_sweep_parity(torch, lam):
     _check_same(torch, g, r, keys)
 
 
+def _sel_overflows(img):
+    ss, sr = int(img[16]), int(img[17])
+    sel = img[ss:sr - 1]
+    return sum(int((((sel >> np.uint64(32 + 10 * k)) & np.uint64(1023)) == 1023).sum()) for k in range(3))
+
+
+def test_select_distance_overflow_parity(torch):
+    # 100-key partitions leave a few pilots far above their encoder's Rice width: long unary runs
+    # whose select distances do not fit 10 bits, so lookups there scan from the 256-one sample
+    keys = synth.u64_keys(200_000, 3)
+    _say("select overflow")
+    g, r = _both(torch, keys, lam=7.0, P=100)
+    assert _sel_overflows(r.image()) > 0
+    _check_same(torch, g, r, keys)
+
+
 EDGE = [(0, 2500), (1, 2500), (2, 2500), (63, 2500), (64, 2500), (65, 2500), (2499, 2500), (2500, 2500),
         (2501, 2500), (10_007, 2500), (7, 1), (40, 3), (1000, 17), (300, 64)]
 

@@ -336,6 +336,49 @@ def test_encoder_parameters(ref, coding):
     assert H["words"] == img.size and H["magic"] == int.from_bytes(b"PHOBIC03", "little")
 
 
+def test_select_entries_and_unary_stream_match_pilots(ref):
+    # Rice image read back with numpy: the ones of the unary stream give every high part, which with
+    # the low bits must rebuild the pilot array; every select entry must hold the position of one
+    # 256 s and the distances to ones 256 s + 64 k (1023 when they do not fit, 0 past the end).
+    # 100-key partitions leave some pilots far above their encoder's Rice width, so a few distances
+    # overflow and the lookups that start there scan from the sample.
+    keys = synth.u64_keys(200_000, 3)
+    h = ref.build_u64(keys, ref.params(lam=7.0, partition_size=100), threads=8)
+    img = h.image()
+    H = _header(img)
+    K, B = H["K"], H["B"]
+    words = img[H["sec_unary"]: H["sec_sel"] - 1]
+    bits = np.unpackbits(words.view(np.uint8), bitorder="little")[: H["ubits"]]
+    ones = np.flatnonzero(bits).astype(np.int64)
+    assert ones.size == K * B
+    high = np.diff(np.concatenate([[-1], ones])) - 1
+    enc = img[H["sec_enc"]: H["sec_enc"] + B]
+    widths, bases = (enc & np.uint64(0xFF)).astype(np.int64), (enc >> np.uint64(8)).astype(np.int64)
+    data = np.unpackbits(img[H["sec_data"]: H["sec_unary"]].view(np.uint8), bitorder="little")
+    pil = h.pilots().astype(np.int64).reshape(K, B)
+    for i in range(B):
+        w = int(widths[i])
+        low = np.zeros(K, dtype=np.int64)
+        for b in range(w):
+            low |= data[bases[i] + np.arange(K) * w + b].astype(np.int64) << b
+        assert np.array_equal(low | (high[i * K:(i + 1) * K] << w), pil[:, i]), i
+    sel = img[H["sec_sel"]: H["sec_remap"] - 1]
+    assert sel.size == (K * B + 255) // 256
+    overflow = 0
+    for s_ in range(sel.size):
+        e = int(sel[s_])
+        a0 = int(ones[256 * s_])
+        assert e & 0xFFFFFFFF == a0
+        for k in (1, 2, 3):
+            t = 256 * s_ + 64 * k
+            want = min(int(ones[t]) - a0, 1023) if t < ones.size else 0
+            assert (e >> (32 + 10 * (k - 1))) & 1023 == want, (s_, k)
+            overflow += want == 1023
+    assert overflow > 0
+    pos = ref.query_image_u64(img, keys)
+    assert np.array_equal(np.sort(pos), np.arange(keys.size, dtype=np.uint64))
+
+
 # --------------------------------------------------------------------------------------------------
 # space and work versus the paper
 # --------------------------------------------------------------------------------------------------
