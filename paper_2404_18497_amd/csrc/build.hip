@@ -286,6 +286,7 @@ constexpr uint32_t kCoarseGroups = 256;  // half the number of rows
 constexpr uint32_t kMaxCoarse = 14336;   // bins held by the LDS histogram (56 KB)
 constexpr uint32_t kMaxDigits = 256;     // destinations of one split (a byte each in LDS)
 constexpr uint32_t kMaxSliceBins = 16384; // (slice, bin) starts of one digit (64 KB of LDS)
+constexpr int kSplitThreads = 1024;      // workgroup of the splits
 constexpr int kSegThreads = 512;
 constexpr uint32_t kMaxG = 8;
 constexpr size_t kSegLdsBytes = 61440;   // dynamic LDS of k_segment_sort
@@ -406,7 +407,7 @@ template <> struct SplitElem<ulonglong2> {
   }
 };
 template <typename E>
-constexpr uint32_t split_tile() { return (uint32_t)kCoarseThreads * SplitElem<E>::kPer; }
+constexpr uint32_t split_tile() { return (uint32_t)kSplitThreads * SplitElem<E>::kPer; }
 template <typename E>
 constexpr size_t split_lds_bytes() {
   return split_tile<E>() * (sizeof(E) + 1) + 4 * kMaxDigits * sizeof(uint32_t);
@@ -414,6 +415,7 @@ constexpr size_t split_lds_bytes() {
 
 static_assert(split_lds_bytes<uint64_t>() <= 65536 && split_lds_bytes<ulonglong2>() <= 65536, "split LDS");
 static_assert(kMaxDigits == 4 * 64, "the tile scan takes four counts per lane of one wavefront");
+static_assert(kSplitThreads >= (int)kMaxDigits, "thread q passes the start of destination q");
 
 // LDS of a split: tile | dest byte per tile slot | count | tile base | write offset | cursor.
 template <typename E>
@@ -458,7 +460,7 @@ __device__ __forceinline__ void split_load(const E* __restrict__ in, uint64_t t0
   const uint32_t last = (uint32_t)min<uint64_t>(T, b - t0) - 1;
   const uint32_t tid = opaque_tid();
 #pragma unroll
-  for (int r = 0; r < SplitElem<E>::kPer; r++) v[r] = in[t0 + min((uint32_t)r * kCoarseThreads + tid, last)];
+  for (int r = 0; r < SplitElem<E>::kPer; r++) v[r] = in[t0 + min((uint32_t)r * kSplitThreads + tid, last)];
 }
 
 // One tile of tn elements held in v: grouped by destination in LDS, then written out in runs.
@@ -473,7 +475,7 @@ __device__ __forceinline__ void split_tile_step(const E (&v)[SplitElem<E>::kPer]
   for (int r = 0; r < kPer; r++) {
     const uint32_t q = dest(v[r]);
     qr[r] = q;
-    if (kFull || (uint32_t)r * kCoarseThreads + tid < tn) qr[r] |= atomicAdd(&L.cnt[q], 1u) << 8;
+    if (kFull || (uint32_t)r * kSplitThreads + tid < tn) qr[r] |= atomicAdd(&L.cnt[q], 1u) << 8;
   }
   lds_barrier();
   if (tid < 64) {  // exclusive scan of the tile's counts by one wavefront, four per lane
@@ -506,7 +508,7 @@ __device__ __forceinline__ void split_tile_step(const E (&v)[SplitElem<E>::kPer]
   lds_barrier();
 #pragma unroll
   for (int r = 0; r < kPer; r++) {
-    if (kFull || (uint32_t)r * kCoarseThreads + tid < tn) {
+    if (kFull || (uint32_t)r * kSplitThreads + tid < tn) {
       const uint32_t s = L.tb[qr[r] & 0xFF] + (qr[r] >> 8);
       L.tile[s] = v[r];
       L.dst[s] = (uint8_t)qr[r];
@@ -516,7 +518,7 @@ __device__ __forceinline__ void split_tile_step(const E (&v)[SplitElem<E>::kPer]
   lds_barrier();
 #pragma unroll
   for (int r = 0; r < kPer; r++) {
-    const uint32_t s = (uint32_t)r * kCoarseThreads + tid;
+    const uint32_t s = (uint32_t)r * kSplitThreads + tid;
     if (kFull || s < tn) out[L.wofs[L.dst[s]] + s] = L.tile[s];
   }
   lds_barrier();
@@ -557,7 +559,7 @@ __device__ __forceinline__ void split_range(const E* __restrict__ in, uint64_t a
 
 // Row r (the count's workgroup r, keys [r per, (r + 1) per)) to its share of every digit.
 template <typename E>
-__global__ __launch_bounds__(kCoarseThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_split_digits(
+__global__ __launch_bounds__(kSplitThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_split_digits(
     const E* __restrict__ in, uint64_t n, uint64_t per, uint64_t seed, uint64_t K, uint32_t gshift, uint32_t dshift,
     uint32_t D, uint32_t R, const uint32_t* __restrict__ doff, E* __restrict__ out) {
   extern __shared__ __align__(16) uint32_t lds[];
@@ -598,7 +600,7 @@ __global__ __launch_bounds__(1024) void k_slice_offsets(const uint32_t* __restri
 
 // Workgroup d Q + s: slice s of digit d to its 2^dshift bins.
 template <typename E>
-__global__ __launch_bounds__(kCoarseThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_split_bins(
+__global__ __launch_bounds__(kSplitThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_split_bins(
     const E* __restrict__ in, uint64_t seed, uint64_t K, uint32_t gshift, uint32_t dshift, uint32_t R, uint32_t g,
     uint32_t Q, const uint32_t* __restrict__ doff, const uint32_t* __restrict__ spos, E* __restrict__ out) {
   extern __shared__ __align__(16) uint32_t lds[];
@@ -1475,11 +1477,11 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
                          cbase, (uint32_t)C, R, g, Q, dshift, spos);
     tm.mark();  // 2
     if (str) {
-      hipLaunchKernelGGL(k_split_digits<ulonglong2>, dim3(R), dim3(kCoarseThreads), split_lds_bytes<ulonglong2>(),
+      hipLaunchKernelGGL(k_split_digits<ulonglong2>, dim3(R), dim3(kSplitThreads), split_lds_bytes<ulonglong2>(),
                          st, (const ulonglong2*)stage, n, per, prm.hash_seed, K, (uint32_t)gshift, dshift, D, R,
                          doff, codes);
       if (two) {
-        hipLaunchKernelGGL(k_split_bins<ulonglong2>, dim3(D * Q), dim3(kCoarseThreads),
+        hipLaunchKernelGGL(k_split_bins<ulonglong2>, dim3(D * Q), dim3(kSplitThreads),
                            split_lds_bytes<ulonglong2>(), st, (const ulonglong2*)codes, prm.hash_seed, K,
                            (uint32_t)gshift, dshift, R, g, Q, doff, spos, stage);
         std::swap(codes, stage);  // the bins are in `codes` from here on
@@ -1487,10 +1489,10 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     } else {
       // the fingerprint array is free until the bucket sort and holds the digits in between
       uint64_t* mid = two ? sortedf : kcodes;
-      hipLaunchKernelGGL(k_split_digits<uint64_t>, dim3(R), dim3(kCoarseThreads), split_lds_bytes<uint64_t>(), st,
+      hipLaunchKernelGGL(k_split_digits<uint64_t>, dim3(R), dim3(kSplitThreads), split_lds_bytes<uint64_t>(), st,
                          in.keys, n, per, prm.hash_seed, K, (uint32_t)gshift, dshift, D, R, doff, mid);
       if (two)
-        hipLaunchKernelGGL(k_split_bins<uint64_t>, dim3(D * Q), dim3(kCoarseThreads), split_lds_bytes<uint64_t>(),
+        hipLaunchKernelGGL(k_split_bins<uint64_t>, dim3(D * Q), dim3(kSplitThreads), split_lds_bytes<uint64_t>(),
                            st, (const uint64_t*)mid, prm.hash_seed, K, (uint32_t)gshift, dshift, R, g, Q, doff, spos,
                            kcodes);
     }
