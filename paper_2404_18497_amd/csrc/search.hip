@@ -111,21 +111,22 @@ __device__ bool equal_fingerprints(const uint64_t* keys, const uint32_t* rbuf, u
 // four with the last entry.  Returns lane k's position for k < 64 (the keys a small bucket marks).
 __device__ __forceinline__ uint32_t bucket_positions(uint32_t* rbuf, const uint64_t* keys, uint64_t f0, uint32_t sz,
                                                      uint64_t w, uint32_t m, uint32_t lane) {
-  const uint32_t ng = (sz + 63) >> 6, szp = (sz + 3) & ~3u;
-  uint32_t r0 = 0;
-  for (uint32_t g = 0; g < ng; g++) {
-    const uint32_t k = g * 64 + lane;
-    uint32_t r = 0;
+  const uint32_t szp = (sz + 3) & ~3u;
+  // keys 0..63 (every bucket of at most 64 keys: no loop)
+  const uint32_t r0 = lane < sz ? pos_hash(f0, w, m) : 0u;
+  if (lane < sz) rbuf[lane] = enc_pos(r0);
+  uint32_t r = r0, k = lane;
+  for (uint32_t g = 1; g * 64 < sz; g++) {  // keys 64 and on
+    k = g * 64 + lane;
+    r = 0;
     if (k < sz) {
-      r = pos_hash(g == 0 ? f0 : keys[k], w, m);
+      r = pos_hash(keys[k], w, m);
       rbuf[k] = enc_pos(r);
     }
-    if (g == 0) r0 = r;
-    if (g == ng - 1) {
-      const uint32_t last = __builtin_amdgcn_readlane(r, (sz - 1) & 63);
-      if (k >= sz && k < szp) rbuf[k] = enc_pos(last);
-    }
   }
+  // the padding of the last group repeats its last entry
+  const uint32_t last = __builtin_amdgcn_readlane(r, (sz - 1) & 63);
+  if (k >= sz && k < szp) rbuf[k] = enc_pos(last);
   wave_sync();
   return r0;
 }
@@ -217,17 +218,11 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         continue;
       }
 
-      // displacement scan: the lowest d such that every key's slot (r + d) mod m is free
+      // displacement scan: the lowest d such that every key's slot (r + d) mod m is free.  A pass
+      // covers 4096 displacements from d0 (acc: this lane's window bits below m, loff: its byte
+      // offset); the first pass covers every m up to 4096, the loop after it the larger ones.
       uint32_t d_found = 0xFFFFFFFFu;
-      for (uint32_t d0 = 0; d0 < m; d0 += 4096) {
-        uint64_t acc = acc_first;
-        uint32_t loff = loff_first;  // byte offset of this lane's window start
-        if (d0) {
-          const uint32_t dl = d0 + dl0;
-          const bool act = dl < m;
-          acc = act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL;
-          loff = act ? (dl >> 3) : 0u;
-        }
+      auto scan_pass = [&](uint32_t d0, uint64_t acc, uint32_t loff) {
         for (uint32_t k = 0; k < szp; k += 4) {
           const uint4 e4 = *(const uint4*)(rbuf + k);
           const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
@@ -245,8 +240,13 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
           const uint32_t L = (uint32_t)(__ffsll((long long)bal) - 1);
           const uint64_t accL = lane_value64(acc, L);
           d_found = d0 + L * 64 + (uint32_t)(__ffsll((long long)accL) - 1);
-          break;
         }
+      };
+      scan_pass(0, acc_first, loff_first);
+      for (uint32_t d0 = 4096; d_found == 0xFFFFFFFFu && d0 < m; d0 += 4096) {
+        const uint32_t dl = d0 + dl0;
+        const bool act = dl < m;
+        scan_pass(d0, act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL, act ? (dl >> 3) : 0u);
       }
       if (d_found == 0xFFFFFFFFu) continue;
       const uint64_t p = s * m + d_found;
