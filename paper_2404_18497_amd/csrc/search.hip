@@ -112,21 +112,26 @@ __device__ bool equal_fingerprints(const uint64_t* keys, const uint32_t* rbuf, u
 __device__ __forceinline__ uint32_t bucket_positions(uint32_t* rbuf, const uint64_t* keys, uint64_t f0, uint32_t sz,
                                                      uint64_t w, uint32_t m, uint32_t lane) {
   const uint32_t szp = (sz + 3) & ~3u;
-  // keys 0..63 (every bucket of at most 64 keys: no loop)
-  const uint32_t r0 = lane < sz ? pos_hash(f0, w, m) : 0u;
-  if (lane < sz) rbuf[lane] = enc_pos(r0);
-  uint32_t r = r0, k = lane;
-  for (uint32_t g = 1; g * 64 < sz; g++) {  // keys 64 and on
-    k = g * 64 + lane;
-    r = 0;
-    if (k < sz) {
-      r = pos_hash(keys[k], w, m);
-      rbuf[k] = enc_pos(r);
+  // keys 0..63: every lane hashes (those past the bucket a neighbour's fingerprint, unused), so no
+  // lane mask is set up; the padding lanes store the last key's position
+  const uint32_t r0 = pos_hash(f0, w, m);
+  if (sz <= 64) {
+    const uint32_t last = __builtin_amdgcn_readlane(r0, sz - 1);
+    if (lane < szp) rbuf[lane] = enc_pos(lane < sz ? r0 : last);
+  } else {
+    rbuf[lane] = enc_pos(r0);
+    uint32_t r = 0, k = lane;
+    for (uint32_t g = 1; g * 64 < sz; g++) {  // keys 64 and on
+      k = g * 64 + lane;
+      r = 0;
+      if (k < sz) {
+        r = pos_hash(keys[k], w, m);
+        rbuf[k] = enc_pos(r);
+      }
     }
+    const uint32_t last = __builtin_amdgcn_readlane(r, (sz - 1) & 63);
+    if (k >= sz && k < szp) rbuf[k] = enc_pos(last);
   }
-  // the padding of the last group repeats its last entry
-  const uint32_t last = __builtin_amdgcn_readlane(r, (sz - 1) & 63);
-  if (k >= sz && k < szp) rbuf[k] = enc_pos(last);
   wave_sync();
   return r0;
 }
@@ -167,7 +172,10 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   // (processing order), win1 the next 64.  The keys of consecutive buckets are consecutive, so one
   // load serves many small buckets, and the next window is in flight while the current one is used.
   const uint32_t nj = uniform((uint32_t)(a.off[j + 1] - kb));
-  const uint64_t smax = m ? a.limit / m : 0;  // s m > limit exactly when s > floor(limit / m)
+  // s m > limit exactly when s > floor(limit / m); limit < 2^32, so every seed tried fits 32 bits.
+  // The cap at 2^32 - 2 (which only m = 1 reaches, where the one key takes seed 0) keeps s + 1 from
+  // wrapping.
+  const uint32_t smax = m ? (uint32_t)min<uint64_t>(a.limit / m, 0xFFFFFFFEULL) : 0u;
   const uint32_t dlast = m ? (uint32_t)(a.limit - smax * m) : 0;  // largest d allowed with s = smax
   uint32_t wbase = 0, o = 0;  // o: first key of the current bucket
   uint64_t win0 = lane < nj ? a.fp[kb + lane] : 0;
@@ -204,12 +212,13 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       continue;
     }
 
-    for (uint64_t s = 0;; s++) {
+    uint64_t wseed = kPhi64;  // the seed's Weyl value (s + 1) phi, kept as a running sum
+    for (uint32_t s = 0;; s++, wseed += kPhi64) {
       if (s > smax) {  // every pilot s m + d of this seed exceeds the limit
         overflow = true;
         break;
       }
-      const uint32_t rmine = bucket_positions(rbuf, keys, f0, sz, (s + 1) * kPhi64, m, lane);
+      const uint32_t rmine = bucket_positions(rbuf, keys, f0, sz, wseed, m, lane);
       if (big && positions_repeat(scr, rbuf, sz, cm, lane)) {
         if (s == 0 && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
           if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
@@ -249,7 +258,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         scan_pass(d0, act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL, act ? (dl >> 3) : 0u);
       }
       if (d_found == 0xFFFFFFFFu) continue;
-      const uint64_t p = s * m + d_found;
+      const uint64_t p = (uint64_t)s * m + d_found;
       if (s == smax && d_found > dlast) {  // p > limit, with s <= smax
         overflow = true;
         break;
