@@ -715,10 +715,8 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(4, 
   constexpr int kBat = kIn == kInRecords ? kSegBatch - 1 : kSegBatch;
   uint64_t fp[kItems];
   const uint32_t nit = (ns + kSegThreads - 1) / kSegThreads;
-#pragma unroll
-  for (int t0 = 0; t0 < kItems; t0 += kBat) {
-    if ((uint32_t)t0 >= nit) break;
-    ulonglong2 cd[kBat];
+  // the raw items of batch t0 (u64 keys: the key in .x), loaded unconditionally
+  auto load_batch = [&](int t0, ulonglong2 (&cd)[kBat]) {
 #pragma unroll
     for (int u = 0; u < kBat; u++) {
       const uint32_t i = min(tid + (uint32_t)(t0 + u) * kSegThreads, ns - 1);
@@ -728,6 +726,18 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(4, 
         cd[u] = ((const ulonglong2*)src)[base + i];
       }
     }
+  };
+  // u64 keys and codes: the next batch is in flight while this one is hashed and ranked (records
+  // load batch by batch: their registers would spill)
+  constexpr bool kPre = kIn != kInRecords;
+  ulonglong2 cd[kBat];
+  if (kPre && nit) load_batch(0, cd);
+#pragma unroll
+  for (int t0 = 0; t0 < kItems; t0 += kBat) {
+    if ((uint32_t)t0 >= nit) break;
+    ulonglong2 nx[kBat];
+    if (!kPre) load_batch(t0, cd);
+    if (kPre && (uint32_t)(t0 + kBat) < nit) load_batch(t0 + kBat, nx);
     uint32_t pb[kBat];  // partition << 16 | bucket
 #pragma unroll
     for (int u = 0; u < kBat; u++) {
@@ -749,6 +759,9 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(4, 
         fp[t0 + u] = kIn == kInRecords ? (uint64_t)cd[u].x : fingerprint(cd[u].x, cd[u].y);
       }
     }
+    if (kPre)
+#pragma unroll
+      for (int u = 0; u < kBat; u++) cd[u] = nx[u];
   }
   __syncthreads();
   for (uint32_t x = tid; x < span; x += kSegThreads) {
