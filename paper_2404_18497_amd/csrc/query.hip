@@ -66,8 +66,9 @@ __device__ __forceinline__ uint64_t unary_high(const uint64_t* __restrict__ un, 
   return cur - prev - 1;
 }
 
-// The residues of offsets j and j + 1: adjacent fields of woff <= 32 bits lie in two consecutive
-// words (the section's trailing pad word keeps idx + 1 inside it).
+// The residues of offsets j and j + 1: adjacent fields of woff <= 32 bits lie in one word or in two
+// consecutive ones (the section's trailing pad word keeps idx + 1 inside it); the lookup is bound by
+// its memory requests, so the second word is read only when the pair straddles.
 __device__ __forceinline__ void offset_pair(const uint64_t* __restrict__ offs, uint64_t j, uint32_t woff,
                                             uint64_t& r0, uint64_t& r1) {
   if (woff == 0) {
@@ -75,7 +76,8 @@ __device__ __forceinline__ void offset_pair(const uint64_t* __restrict__ offs, u
   } else if (woff <= 32) {
     const uint64_t pos = j * woff, idx = pos >> 6;
     const uint32_t sh = (uint32_t)(pos & 63);
-    const uint64_t w0 = offs[idx], w1 = offs[idx + 1];
+    const uint64_t w0 = offs[idx];
+    const uint64_t w1 = sh + 2 * woff > 64 ? offs[idx + 1] : 0;  // only a straddling pair reads it
     const uint64_t lo64 = sh ? ((w0 >> sh) | (w1 << (64 - sh))) : w0;  // bits [pos, pos + 64)
     const uint64_t mask = (1ULL << woff) - 1;
     r0 = lo64 & mask;
