@@ -28,9 +28,9 @@ __global__ void k_queue_reset(unsigned long long* q) {
 // holds the smallest d, and seeds are tried in increasing order, so the first hit is the smallest
 // pilot p = s m + d (Sec. 4; the same minimum as the sequential nested loop, Sec. 4.2).
 //
-// The key loop is pure vector/LDS work: positions are kept encoded as e = (r >> 5) << 7 | (r & 31),
-// so (e >> 5) is the byte offset of the word holding bit r and the low five bits are the funnel
-// shift; the list is padded to a multiple of four with copies of its last entry (AND is
+// The key loop is pure vector/LDS work: positions are kept encoded as e = (r >> 5) << 18 | (r & 31),
+// so the high half of e is the byte offset of the word holding bit r (added to the lane's offset
+// straight from the high half, one instruction) and the low five bits are the funnel shift; the list is padded to a multiple of four with copies of its last entry (AND is
 // idempotent), and lanes whose window lies beyond m read in-bounds words into an accumulator that
 // is already zero.
 //
@@ -59,8 +59,8 @@ __device__ __forceinline__ uint64_t lane_value64(uint64_t v, uint32_t lane) {
          __builtin_amdgcn_readlane((uint32_t)v, lane);
 }
 
-__device__ __forceinline__ uint32_t enc_pos(uint32_t r) { return ((r >> 5) << 7) | (r & 31); }
-__device__ __forceinline__ uint32_t dec_pos(uint32_t e) { return ((e >> 7) << 5) | (e & 31); }
+__device__ __forceinline__ uint32_t enc_pos(uint32_t r) { return ((r >> 5) << 18) | (r & 31); }
+__device__ __forceinline__ uint32_t dec_pos(uint32_t e) { return ((e >> 18) << 5) | (e & 31); }
 
 // Marks the positions of rbuf[0..sz) in the scratch bitmap; cm[g] gets the lanes of group g whose
 // position was already marked.  Leaves the scratch clear.  Returns whether a position repeats.
@@ -237,7 +237,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
           const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
 #pragma unroll
           for (int t = 0; t < 4; t++) {
-            const uint32_t* wp = (const uint32_t*)(F2b + (ev[t] >> 5) + loff);
+            const uint32_t* wp = (const uint32_t*)(F2b + (ev[t] >> 16) + loff);
             const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
             acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, ev[t]) << 32) |
                    __builtin_amdgcn_alignbit(w1, w0, ev[t]);
