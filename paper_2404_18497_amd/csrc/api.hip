@@ -93,6 +93,38 @@ std::mutex g_table_mu;
 std::map<TableKey, uint64_t*> g_tables;
 }  // namespace
 
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  static std::mutex mu;
+  static std::vector<hipMemPool_t> pools;
+  hipMemPool_t pool = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if ((size_t)dev >= pools.size()) pools.resize((size_t)dev + 1, nullptr);
+    if (!pools[dev]) {
+      hipMemPoolProps props{};
+      props.allocType = hipMemAllocationTypePinned;
+      props.handleTypes = hipMemHandleTypeNone;
+      props.location.type = hipMemLocationTypeDevice;
+      props.location.id = dev;
+      hipMemPool_t created = nullptr;
+      e = hipMemPoolCreate(&created, &props);
+      if (e != hipSuccess) return e;
+      uint64_t keep = kPoolKeepBytes;
+      e = hipMemPoolSetAttribute(created, hipMemPoolAttrReleaseThreshold, &keep);
+      if (e != hipSuccess) {
+        (void)hipMemPoolDestroy(created);
+        return e;
+      }
+      pools[dev] = created;
+    }
+    pool = pools[dev];
+  }
+  return hipMallocFromPoolAsync(p, bytes, pool, st);
+}
+
 phobic_status upload_table(phobic_mphf* h, hipStream_t st) {
   TableKey key{h->device, 0, h->prm.partition_size, h->prm.alpha_num, h->prm.alpha_den};
   std::memcpy(&key.lambda_bits, &h->prm.lambda, 8);
@@ -355,7 +387,7 @@ extern "C" phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, v
     phobic_free(h);
     return r;
   }
-  hipError_t e = hipMallocAsync((void**)&h->d_image, bytes, st);
+  hipError_t e = pool_alloc((void**)&h->d_image, bytes, st);
   if (e == hipSuccess) e = hipMemcpyAsync(h->d_image, w.data(), bytes, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) {
@@ -369,8 +401,8 @@ extern "C" phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, v
 
 extern "C" void phobic_free(phobic_mphf* h) {
   if (!h) return;
-  // the image comes from the stream-ordered pool; the null stream orders the release after all
-  // work already enqueued on blocking streams.  Batch members share one allocation.
+  // the image comes from the library's stream-ordered pool; the null stream orders the release after
+  // all work already enqueued on blocking streams.  Batch members share one allocation.
   if (h->shared)
     h->shared.reset();
   else if (h->d_image)

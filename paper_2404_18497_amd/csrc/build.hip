@@ -46,6 +46,20 @@ __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
     p[i] = v;
 }
 
+// A fresh image of nw words: the header words hw[0..nh), the encoder words hw[nh..nh + ne) at word
+// enc_at, zero elsewhere (the packing kernels OR their fields in afterwards).
+__global__ void k_image_init(uint64_t* __restrict__ img, uint64_t nw, const uint64_t* __restrict__ hw, uint32_t nh,
+                             uint64_t enc_at, uint32_t ne) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < nw; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t v = 0;
+    if (i < nh)
+      v = hw[i];
+    else if (i - enc_at < ne)  // i >= enc_at >= nh here
+      v = hw[nh + (i - enc_at)];
+    img[i] = v;
+  }
+}
+
 // out[c][r] = in[r][c] for an R x Cn array of u32, in 64 x 64 tiles staged through LDS so that both
 // the reads (along a row of `in`) and the writes (along a row of `out`) are contiguous.
 constexpr uint32_t kTile = 64;
@@ -919,38 +933,72 @@ __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
   return v;
 }
 
-// One workgroup per encoder i: shsum[i * 33 + b] = sum_j (v_ij >> b), vmax[i] = max_j v_ij.
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// At most this many values per thread in k_encoder_stats, so that its byte counters cannot overflow.
+constexpr uint32_t kStatsPerThread = 64;
+static_assert(kBlock * kStatsPerThread < 65536, "16-bit count fields of k_encoder_stats");
+
+// Workgroups (g, i), g < gridDim.x, share encoder i: shsum[i * 33 + b] += sum_j (v_ij >> b) and
+// vmax[i] = max(vmax[i], max_j v_ij) over the slice j = g kBlock + tid (mod gridDim.x kBlock); both
+// arrays start at zero (k_stats_init), and the launch gives every thread at most kStatsPerThread
+// values.  Since v >> b = sum_{k >= b} bit_k(v) 2^(k - b), the slice only needs the bit counts
+// c_k = #{j : bit k of v_ij is set}, and sum_j (v_ij >> b) = sum_{k >= b} c_k 2^(k - b) exactly.
+// A thread counts eight bits per add: byte t of cnt8[s] counts bit 8 t + s of its values.
 __global__ __launch_bounds__(kBlock) void k_encoder_stats(const uint32_t* __restrict__ pilots, uint64_t K,
                                                           uint64_t* __restrict__ shsum, uint32_t* __restrict__ vmax) {
-  __shared__ uint64_t part[kBlock / 64][33];
+  __shared__ uint32_t wsum[kBlock / 64][16];
+  __shared__ uint64_t cnt[32];
   __shared__ uint32_t mx;
-  const uint32_t tid = threadIdx.x, i = blockIdx.x;
+  const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, i = blockIdx.y;
   if (tid == 0) mx = 0;
-  uint64_t acc[33];
+  uint32_t cnt8[8];
 #pragma unroll
-  for (int b = 0; b < 33; b++) acc[b] = 0;
+  for (int t = 0; t < 8; t++) cnt8[t] = 0;
   uint32_t lmx = 0;
   const uint32_t* col = pilots + (uint64_t)i * K;
-  for (uint64_t jj = tid; jj < K; jj += kBlock) {
-    uint64_t v = col[jj];
-    lmx = max(lmx, (uint32_t)v);
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t jj = (uint64_t)blockIdx.x * kBlock + tid; jj < K; jj += stride) {
+    const uint32_t v = col[jj];
+    lmx = max(lmx, v);
 #pragma unroll
-    for (int b = 0; b < 33; b++) acc[b] += v >> b;
+    for (int t = 0; t < 8; t++) cnt8[t] += (v >> t) & 0x01010101u;
+  }
+  // 16-bit fields: the counts of bits s and 16 + s (even bytes) and 8 + s and 24 + s (odd bytes); a
+  // field sums at most kBlock x kStatsPerThread < 2^16 values over the workgroup
+#pragma unroll
+  for (int t = 0; t < 8; t++) {
+    const uint32_t ev = wave_sum_u32(cnt8[t] & 0x00FF00FFu), od = wave_sum_u32((cnt8[t] >> 8) & 0x00FF00FFu);
+    if (lane == 0) {
+      wsum[wave][2 * t] = ev;
+      wsum[wave][2 * t + 1] = od;
+    }
   }
   __syncthreads();
   atomicMax(&mx, lmx);
-#pragma unroll
-  for (int b = 0; b < 33; b++) {
-    uint64_t v = wave_sum_u64(acc[b]);
-    if ((tid & 63) == 0) part[tid >> 6][b] = v;
+  if (tid < 32) {  // c_k for k = tid: byte k >> 3 of the counters of bit k & 7
+    const uint32_t t = tid & 7, byte = tid >> 3;
+    uint32_t f = 0;
+    for (int w = 0; w < kBlock / 64; w++) f += wsum[w][2 * t + (byte & 1)];
+    cnt[tid] = (f >> (16 * (byte >> 1))) & 0xFFFFu;
   }
   __syncthreads();
   if (tid < 33) {
-    uint64_t v = 0;
-    for (int w = 0; w < kBlock / 64; w++) v += part[w][tid];
-    shsum[(uint64_t)i * 33 + tid] = v;
+    uint64_t sb = 0;  // sum_{k >= b} c_k 2^(k - b) by Horner's rule from the top bit
+    for (int k = 31; k >= (int)tid; k--) sb = 2 * sb + cnt[k];
+    if (sb) atomicAdd((unsigned long long*)&shsum[(uint64_t)i * 33 + tid], (unsigned long long)sb);
   }
-  if (tid == 0) vmax[i] = mx;
+  if (tid == 0 && mx) atomicMax(&vmax[i], mx);
+}
+
+// Clears the statistics block of n words and sets the offset residue range at word mm_at to
+// (LLONG_MAX, LLONG_MIN), the identities of the minimum and maximum taken by k_offset_stats.
+__global__ void k_stats_init(uint64_t* __restrict__ st, uint64_t n, uint64_t mm_at) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    st[i] = i == mm_at ? (uint64_t)LLONG_MAX : (i == mm_at + 1 ? (uint64_t)LLONG_MIN : 0);
 }
 
 // Offset residues delta_j = toff[j] - E_j: minimum and maximum over j in [0, K].
@@ -976,7 +1024,8 @@ __global__ __launch_bounds__(kBlock) void k_pack_offsets(const uint64_t* __restr
 
 // One workgroup of 1024 threads per encoder i: low bits (or Compact values) at base_i + j w_i; for
 // Rice the unary stream of q = v >> w_i (q zeros then a one), whose one for value t = i K + j sits at
-// ubase_i + sum_{j' < j} (q_j' + 1) + q_j, and a select sample for every 128th one.
+// ubase_i + sum_{j' < j} (q_j' + 1) + q_j, and the position of every 256th one in the select entries
+// (their sub-sample distances are filled in afterwards, from the finished stream).
 //
 // Values go through in chunks of 4096.  A chunk's low bits (at most 4096 x 32 bits) and, when they
 // fit, its unary bits are assembled in LDS and written out as whole words: plain stores for the
@@ -1639,31 +1688,34 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     hipLaunchKernelGGL(k_transpose_u32, dim3((uint32_t)std::min<uint64_t>(tiles, 65536)), dim3(kTile, kTile / 16),
                        0, st, pilots_pm, K, (uint64_t)B, pilots);
   }
-  // statistics -> host parameters
-  uint64_t* shsum;
-  uint32_t* vmax;
-  long long* dmm;
-  PHOBIC_HIP(S.get(&shsum, (uint64_t)B * 33));
-  PHOBIC_HIP(S.get(&vmax, B));
-  PHOBIC_HIP(S.get(&dmm, 2));
+  // statistics -> host parameters, in one block so that one copy brings them back: the shifted sums
+  // (B x 33), the offset residue range (2), the maxima (B u32)
+  const uint64_t nstat = (uint64_t)B * 33 + 2 + (B + 1) / 2;
+  uint64_t* stats;
+  PHOBIC_HIP(S.get(&stats, nstat));
+  uint64_t* shsum = stats;
+  long long* dmm = (long long*)(stats + (uint64_t)B * 33);
+  uint32_t* vmax = (uint32_t*)(stats + (uint64_t)B * 33 + 2);
   const uint64_t R = (uint64_t)(((unsigned __int128)total << 32) / K);
-  const long long init_mm[2] = {LLONG_MAX, LLONG_MIN};
-  PHOBIC_HIP(S.upload(dmm, init_mm, 2));
-  hipLaunchKernelGGL(k_encoder_stats, dim3(B), dim3(kBlock), 0, st, pilots, K, shsum, vmax);
+  hipLaunchKernelGGL(k_stats_init, dim3(grid_for(nstat)), dim3(kBlock), 0, st, stats, nstat, (uint64_t)B * 33);
+  {  // at most kStatsPerThread values per thread (about 16 when K allows: enough workgroups to fill
+     // the device); a grid row may hold 2^31 - 1 workgroups
+    const uint64_t G = std::max<uint64_t>((K + (uint64_t)kStatsPerThread * kBlock - 1) / ((uint64_t)kStatsPerThread * kBlock),
+                                          std::max<uint64_t>(1, K / (16 * kBlock)));
+    hipLaunchKernelGGL(k_encoder_stats, dim3((uint32_t)G, B), dim3(kBlock), 0, st, pilots, K, shsum, vmax);
+  }
   hipLaunchKernelGGL(k_offset_stats, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, toff, K, R, dmm);
   PHOBIC_HIP(hipGetLastError());
-  uint64_t* hsh;  // pinned
-  uint32_t *hmax, *herrp;
-  long long* hmm;
-  PHOBIC_HIP(S.host(&hsh, (uint64_t)B * 33));
-  PHOBIC_HIP(S.host(&hmax, B));
-  PHOBIC_HIP(S.host(&hmm, 2));
+  uint64_t* hstats;  // pinned
+  uint32_t* herrp;
+  PHOBIC_HIP(S.host(&hstats, nstat));
   PHOBIC_HIP(S.host(&herrp, 1));
-  PHOBIC_HIP(hipMemcpyAsync(hsh, shsum, (size_t)B * 33 * 8, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(hmax, vmax, (size_t)B * 4, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(hmm, dmm, 2 * sizeof(long long), hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(hstats, stats, nstat * 8, hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipMemcpyAsync(herrp, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipStreamSynchronize(st));
+  const uint64_t* hsh = hstats;
+  const long long* hmm = (const long long*)(hstats + (uint64_t)B * 33);
+  const uint32_t* hmax = (const uint32_t*)(hstats + (uint64_t)B * 33 + 2);
   const uint32_t herr = *herrp;
   if (herr & (1u << PHOBIC_E_DUPLICATE)) return fail(PHOBIC_E_DUPLICATE, "two keys share their 128-bit hash code");
   if (herr & (1u << PHOBIC_E_PILOT_OVERFLOW))
@@ -1690,18 +1742,21 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   const std::vector<uint64_t> hdr = make_header(n, K, B, prm, total, dmin, woff, data_bits, unary_bits, R);
   const uint64_t nwords = hdr[kHWords];
 
-  PHOBIC_HIP(hipMallocAsync((void**)&h->d_image, nwords * sizeof(uint64_t), st));
+  PHOBIC_HIP(pool_alloc((void**)&h->d_image, nwords * sizeof(uint64_t), st));
   h->nwords = nwords;
   h->header = hdr;
   uint64_t* img = h->d_image;
-  hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(nwords)), dim3(kBlock), 0, st, img, nwords, (uint64_t)0);
-  PHOBIC_HIP(S.upload(img, hdr.data(), (uint64_t)kHeaderWords));
-  PHOBIC_HIP(S.upload(img + hdr[kHSecEnc], enc.data(), (uint64_t)B));
-  uint64_t* d_ubase = nullptr;
-  if (rice) {
-    PHOBIC_HIP(S.get(&d_ubase, B));
-    PHOBIC_HIP(S.upload(d_ubase, ubase.data(), (uint64_t)B));
-  }
+  // header, encoder words and unary bases go over in one copy; the image is zeroed and its header
+  // and encoder words set by one kernel
+  std::vector<uint64_t> hw(hdr.begin(), hdr.begin() + kHeaderWords);
+  hw.insert(hw.end(), enc.begin(), enc.end());
+  if (rice) hw.insert(hw.end(), ubase.begin(), ubase.end());
+  uint64_t* dhw;
+  PHOBIC_HIP(S.get(&dhw, hw.size()));
+  PHOBIC_HIP(S.upload(dhw, hw.data(), hw.size()));
+  hipLaunchKernelGGL(k_image_init, dim3(grid_for(nwords)), dim3(kBlock), 0, st, img, nwords, dhw,
+                     (uint32_t)kHeaderWords, hdr[kHSecEnc], B);
+  uint64_t* d_ubase = rice ? dhw + kHeaderWords + B : nullptr;
   if (woff)
     hipLaunchKernelGGL(k_pack_offsets, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, toff, K, R, dmin, woff,
                        img + hdr[kHSecOff]);
@@ -2266,7 +2321,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
     total_words += h[kHWords];
   }
   void* big = nullptr;
-  PHOBIC_HIP(hipMallocAsync(&big, total_words * 8, st));
+  PHOBIC_HIP(pool_alloc(&big, total_words * 8, st));
   std::shared_ptr<void> shared(big, [](void* p) { (void)hipFreeAsync(p, nullptr); });
   uint64_t *dh, *de, *du, *dib;
   PHOBIC_HIP(S.get(&dh, (uint64_t)count * kHeaderWords));

@@ -92,6 +92,12 @@ std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phob
                                   int64_t dmin, uint32_t woff, uint64_t data_bits, uint64_t unary_bits, uint64_t R);
 void fill_query_args(phobic_mphf* h);
 
+// Stream-ordered device memory for images (and short-lived launch buffers) from a per-device pool of
+// this library, which keeps up to kPoolKeepBytes of freed memory mapped for the next allocation:
+// repeated builds then reuse pages instead of mapping fresh ones.  Released with hipFreeAsync.
+constexpr uint64_t kPoolKeepBytes = 1ULL << 30;
+hipError_t pool_alloc(void** p, size_t bytes, hipStream_t st);
+
 // ---------------------------------------------------------------------------------------------
 // Device helpers.
 // ---------------------------------------------------------------------------------------------

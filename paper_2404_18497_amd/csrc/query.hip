@@ -372,7 +372,7 @@ extern "C" phobic_status phobic_query_multi_u64(const phobic_mphf* const* h_hand
   std::memcpy(stg.p, jobs.data(), jbytes);
   std::memcpy((char*)stg.p + jbytes, bstart.data(), bbytes);
   void* dbuf = nullptr;
-  PHOBIC_HIP(hipMallocAsync(&dbuf, jbytes + bbytes, st));
+  PHOBIC_HIP(pool_alloc(&dbuf, jbytes + bbytes, st));
   hipError_t e = hipMemcpyAsync(dbuf, stg.p, jbytes + bbytes, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipEventRecord(stg.ev, st);
   if (e == hipSuccess) {
