@@ -938,18 +938,24 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
   return v;
 }
 
-// At most this many values per thread in k_encoder_stats, so that its byte counters cannot overflow.
-constexpr uint32_t kStatsPerThread = 64;
-static_assert(kBlock * kStatsPerThread < 65536, "16-bit count fields of k_encoder_stats");
+// The encoders' values go through the statistics and the packing in chunks of kPackChunk.
+constexpr int kPackThreads = 1024;
+constexpr int kPackItems = 4;
+constexpr uint32_t kPackChunk = kPackThreads * kPackItems;
+// k_encoder_stats: one chunk per workgroup, so that its byte counters (at most kPackChunk / kBlock
+// per thread) and its 16-bit count fields (at most kPackChunk) cannot overflow.
+static_assert(kPackChunk / kBlock <= 255 && kPackChunk < 65536, "count fields of k_encoder_stats");
 
-// Workgroups (g, i), g < gridDim.x, share encoder i: shsum[i * 33 + b] += sum_j (v_ij >> b) and
-// vmax[i] = max(vmax[i], max_j v_ij) over the slice j = g kBlock + tid (mod gridDim.x kBlock); both
-// arrays start at zero (k_stats_init), and the launch gives every thread at most kStatsPerThread
-// values.  Since v >> b = sum_{k >= b} bit_k(v) 2^(k - b), the slice only needs the bit counts
-// c_k = #{j : bit k of v_ij is set}, and sum_j (v_ij >> b) = sum_{k >= b} c_k 2^(k - b) exactly.
-// A thread counts eight bits per add: byte t of cnt8[s] counts bit 8 t + s of its values.
+// Workgroup (c, i) reads chunk c of encoder i (j in [c kPackChunk, (c + 1) kPackChunk), gridDim.x
+// chunks): shsum[i * 33 + b] += sum_j (v_ij >> b), vmax[i] = max(vmax[i], max_j v_ij) (both start
+// at zero, k_stats_init), and the chunk's bit counts c_k = #{j : bit k of v_ij is set} go to
+// ccnt[(i gridDim.x + c) 32 + k].  Since v >> b = sum_{k >= b} bit_k(v) 2^(k - b), the counts give
+// sum_j (v_ij >> b) = sum_{k >= b} c_k 2^(k - b) exactly, for any b, here and once the Rice
+// parameters are known (k_chunk_carry).  A thread counts eight bits per add: byte t of cnt8[s]
+// counts bit 8 t + s of its values.
 __global__ __launch_bounds__(kBlock) void k_encoder_stats(const uint32_t* __restrict__ pilots, uint64_t K,
-                                                          uint64_t* __restrict__ shsum, uint32_t* __restrict__ vmax) {
+                                                          uint64_t* __restrict__ shsum, uint32_t* __restrict__ vmax,
+                                                          uint32_t* __restrict__ ccnt) {
   __shared__ uint32_t wsum[kBlock / 64][16];
   __shared__ uint64_t cnt[32];
   __shared__ uint32_t mx;
@@ -960,15 +966,15 @@ __global__ __launch_bounds__(kBlock) void k_encoder_stats(const uint32_t* __rest
   for (int t = 0; t < 8; t++) cnt8[t] = 0;
   uint32_t lmx = 0;
   const uint32_t* col = pilots + (uint64_t)i * K;
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t jj = (uint64_t)blockIdx.x * kBlock + tid; jj < K; jj += stride) {
+  const uint64_t j1 = min(K, (uint64_t)(blockIdx.x + 1) * kPackChunk);
+  for (uint64_t jj = (uint64_t)blockIdx.x * kPackChunk + tid; jj < j1; jj += kBlock) {
     const uint32_t v = col[jj];
     lmx = max(lmx, v);
 #pragma unroll
     for (int t = 0; t < 8; t++) cnt8[t] += (v >> t) & 0x01010101u;
   }
   // 16-bit fields: the counts of bits s and 16 + s (even bytes) and 8 + s and 24 + s (odd bytes); a
-  // field sums at most kBlock x kStatsPerThread < 2^16 values over the workgroup
+  // field sums at most kPackChunk < 2^16 values over the workgroup
 #pragma unroll
   for (int t = 0; t < 8; t++) {
     const uint32_t ev = wave_sum_u32(cnt8[t] & 0x00FF00FFu), od = wave_sum_u32((cnt8[t] >> 8) & 0x00FF00FFu);
@@ -983,7 +989,9 @@ __global__ __launch_bounds__(kBlock) void k_encoder_stats(const uint32_t* __rest
     const uint32_t t = tid & 7, byte = tid >> 3;
     uint32_t f = 0;
     for (int w = 0; w < kBlock / 64; w++) f += wsum[w][2 * t + (byte & 1)];
-    cnt[tid] = (f >> (16 * (byte >> 1))) & 0xFFFFu;
+    const uint32_t ck = (f >> (16 * (byte >> 1))) & 0xFFFFu;
+    cnt[tid] = ck;
+    ccnt[((uint64_t)i * gridDim.x + blockIdx.x) * 32 + tid] = ck;
   }
   __syncthreads();
   if (tid < 33) {
@@ -1022,19 +1030,53 @@ __global__ __launch_bounds__(kBlock) void k_pack_offsets(const uint64_t* __restr
   }
 }
 
-// One workgroup of 1024 threads per encoder i: low bits (or Compact values) at base_i + j w_i; for
+// Rice: the unary start of every chunk, carry[i nch + c] = ubase_i + the unary length of chunks
+// c' < c of encoder i, where a chunk's length is sum_j ((v_ij >> w_i) + 1), from its bit counts.
+// One workgroup per encoder, nch chunks of kPackChunk values.
+__global__ __launch_bounds__(kBlock) void k_chunk_carry(const uint32_t* __restrict__ ccnt, uint64_t K, uint64_t nch,
+                                                        const uint64_t* __restrict__ enc,
+                                                        const uint64_t* __restrict__ ubase,
+                                                        uint64_t* __restrict__ carry) {
+  __shared__ uint64_t part[kBlock / 64];
+  const uint32_t tid = threadIdx.x, ln = tid & 63, i = blockIdx.x;
+  const int w = (int)(enc[i] & 0xFF);
+  uint64_t run = ubase[i];
+  for (uint64_t c0 = 0; c0 < nch; c0 += kBlock) {
+    const uint64_t c = c0 + tid;
+    uint64_t u = 0;
+    if (c < nch) {
+      const uint32_t* cc = ccnt + ((uint64_t)i * nch + c) * 32;
+      for (int k = 31; k >= w; k--) u = 2 * u + cc[k];  // sum_j (v_ij >> w)
+      u += min(K, (c + 1) * kPackChunk) - c * kPackChunk;
+    }
+    uint64_t incl = u;  // block inclusive scan
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t y = __shfl_up(incl, o);
+      if (ln >= (uint32_t)o) incl += y;
+    }
+    if (ln == 63) part[tid >> 6] = incl;
+    __syncthreads();
+    uint64_t before = 0, total = 0;
+    for (uint32_t x = 0; x < kBlock / 64; x++) {
+      if (x < (tid >> 6)) before += part[x];
+      total += part[x];
+    }
+    if (c < nch) carry[(uint64_t)i * nch + c] = run + before + incl - u;
+    run += total;
+    __syncthreads();
+  }
+}
+
+// One workgroup of 1024 threads per chunk c and encoder i: low bits (or Compact values) at base_i + j w_i; for
 // Rice the unary stream of q = v >> w_i (q zeros then a one), whose one for value t = i K + j sits at
 // ubase_i + sum_{j' < j} (q_j' + 1) + q_j, and the position of every 256th one in the select entries
 // (their sub-sample distances are filled in afterwards, from the finished stream).
 //
-// Values go through in chunks of 4096.  A chunk's low bits (at most 4096 x 32 bits) and, when they
-// fit, its unary bits are assembled in LDS and written out as whole words: plain stores for the
+// A chunk's low bits (at most 4096 x 32 bits) and, when they fit, its unary bits (from the chunk's
+// unary start, k_chunk_carry) are assembled in LDS and written out as whole words: plain stores for the
 // words only this chunk touches, an atomic OR for its first and last word, which a neighbouring
 // chunk or encoder may share.  A chunk whose unary run is too long for the buffer (a few huge
 // pilots) sets its ones in global memory directly.
-constexpr int kPackThreads = 1024;
-constexpr int kPackItems = 4;
-constexpr uint32_t kPackChunk = kPackThreads * kPackItems;
 constexpr uint32_t kPackWords = kPackChunk / 2 + 2;  // 4096 fields of <= 32 bits, plus two partial words
 
 __device__ __forceinline__ void lds_put_bits(uint64_t* buf, uint64_t rel, uint64_t v, uint32_t w) {
@@ -1066,84 +1108,81 @@ __device__ __forceinline__ void flush_words(const uint64_t* buf, uint64_t* __res
 
 __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __restrict__ pilots, uint64_t K,
                                                               const uint64_t* __restrict__ enc,
-                                                              const uint64_t* __restrict__ ubase, uint32_t rice,
+                                                              const uint64_t* __restrict__ carries, uint32_t rice,
                                                               uint64_t* __restrict__ data, uint64_t* __restrict__ unary,
                                                               uint64_t* __restrict__ sel) {
   __shared__ uint64_t part[kPackThreads / 64];
   __shared__ uint64_t chunk_total;
   __shared__ uint64_t dbuf[kPackWords];
   __shared__ uint64_t ubuf[kPackWords];
-  const uint32_t tid = threadIdx.x, i = blockIdx.x;
+  const uint32_t tid = threadIdx.x, i = blockIdx.y;
   const uint64_t e = enc[i];
   const uint32_t w = (uint32_t)(e & 0xFF);
   const uint64_t base = e >> 8;
   const uint32_t* col = pilots + (uint64_t)i * K;
-  uint64_t carry = rice ? ubase[i] : 0;
-  for (uint64_t j0 = 0; j0 < K; j0 += kPackChunk) {
-    for (uint32_t x = tid; x < kPackWords; x += kPackThreads) {
-      dbuf[x] = 0;
-      ubuf[x] = 0;
-    }
-    const uint64_t jb = j0 + (uint64_t)tid * kPackItems;
-    uint64_t v[kPackItems];
-    uint64_t local = 0;
-#pragma unroll
-    for (int t = 0; t < kPackItems; t++) {
-      v[t] = jb + t < K ? col[jb + t] : 0;
-      if (jb + t < K) local += (v[t] >> w) + 1;
-    }
-    uint64_t incl = local;  // inclusive prefix of the unary lengths inside the wavefront
-    if (rice) {
-      // block exclusive scan of local
-      const uint32_t ln = tid & 63;
-      for (int o = 1; o < 64; o <<= 1) {
-        uint64_t y = __shfl_up(incl, o);
-        if (ln >= (uint32_t)o) incl += y;
-      }
-      if (ln == 63) part[tid >> 6] = incl;
-      __syncthreads();
-      if (tid < 64) {
-        uint64_t pv = tid < kPackThreads / 64 ? part[tid] : 0;
-        uint64_t pi = pv;
-        for (int o = 1; o < 64; o <<= 1) {
-          uint64_t y = __shfl_up(pi, o);
-          if (tid >= (uint32_t)o) pi += y;
-        }
-        if (tid < kPackThreads / 64) part[tid] = pi - pv;
-        if (tid == kPackThreads / 64 - 1) chunk_total = pi;
-      }
-    }
-    __syncthreads();  // buffers cleared; scan results visible
-    const uint64_t ctot = rice ? chunk_total : 0;
-    uint64_t excl = rice ? carry + part[tid >> 6] + (incl - local) : 0;
-    const uint64_t jend = min(K, j0 + kPackChunk);
-    const uint64_t d_first = (base + j0 * w) >> 6;
-    const uint64_t u_first = carry >> 6;
-    const bool u_lds = ctot == 0 || ((carry + ctot - 1) >> 6) - u_first < kPackWords;
-#pragma unroll
-    for (int t = 0; t < kPackItems; t++) {
-      const uint64_t jj = jb + t;
-      if (jj < K) {
-        const uint64_t q = v[t] >> w;
-        if (w) lds_put_bits(dbuf, base + jj * w - d_first * 64, v[t] & ((1ULL << w) - 1), w);
-        if (rice) {
-          const uint64_t pos = excl + q;
-          if (u_lds)
-            atomicOr((unsigned long long*)&ubuf[(pos >> 6) - u_first], 1ULL << (pos & 63));
-          else
-            atomicOr((unsigned long long*)&unary[pos >> 6], 1ULL << (pos & 63));
-          const uint64_t t_glob = (uint64_t)i * K + jj;
-          if ((t_glob & (kSelBlock - 1)) == 0) sel[t_glob / kSelBlock] = pos;
-          excl = pos + 1;
-        }
-      }
-    }
-    __syncthreads();
-    if (w) flush_words(dbuf, data, d_first, (uint32_t)(((base + jend * w - 1) >> 6) - d_first), tid);
-    if (rice && u_lds && ctot) flush_words(ubuf, unary, u_first, (uint32_t)(((carry + ctot - 1) >> 6) - u_first), tid);
-    carry += ctot;
-    __syncthreads();
+  const uint64_t j0 = (uint64_t)blockIdx.x * kPackChunk;
+  const uint64_t carry = rice ? carries[(uint64_t)i * gridDim.x + blockIdx.x] : 0;
+  for (uint32_t x = tid; x < kPackWords; x += kPackThreads) {
+    dbuf[x] = 0;
+    ubuf[x] = 0;
   }
+  const uint64_t jb = j0 + (uint64_t)tid * kPackItems;
+  uint64_t v[kPackItems];
+  uint64_t local = 0;
+#pragma unroll
+  for (int t = 0; t < kPackItems; t++) {
+    v[t] = jb + t < K ? col[jb + t] : 0;
+    if (jb + t < K) local += (v[t] >> w) + 1;
+  }
+  uint64_t incl = local;  // inclusive prefix of the unary lengths inside the wavefront
+  if (rice) {
+    // block exclusive scan of local
+    const uint32_t ln = tid & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+      uint64_t y = __shfl_up(incl, o);
+      if (ln >= (uint32_t)o) incl += y;
+    }
+    if (ln == 63) part[tid >> 6] = incl;
+    __syncthreads();
+    if (tid < 64) {
+      uint64_t pv = tid < kPackThreads / 64 ? part[tid] : 0;
+      uint64_t pi = pv;
+      for (int o = 1; o < 64; o <<= 1) {
+        uint64_t y = __shfl_up(pi, o);
+        if (tid >= (uint32_t)o) pi += y;
+      }
+      if (tid < kPackThreads / 64) part[tid] = pi - pv;
+      if (tid == kPackThreads / 64 - 1) chunk_total = pi;
+    }
+  }
+  __syncthreads();  // buffers cleared; scan results visible
+  const uint64_t ctot = rice ? chunk_total : 0;
+  uint64_t excl = rice ? carry + part[tid >> 6] + (incl - local) : 0;
+  const uint64_t jend = min(K, j0 + kPackChunk);
+  const uint64_t d_first = (base + j0 * w) >> 6;
+  const uint64_t u_first = carry >> 6;
+  const bool u_lds = ctot == 0 || ((carry + ctot - 1) >> 6) - u_first < kPackWords;
+#pragma unroll
+  for (int t = 0; t < kPackItems; t++) {
+    const uint64_t jj = jb + t;
+    if (jj < K) {
+      const uint64_t q = v[t] >> w;
+      if (w) lds_put_bits(dbuf, base + jj * w - d_first * 64, v[t] & ((1ULL << w) - 1), w);
+      if (rice) {
+        const uint64_t pos = excl + q;
+        if (u_lds)
+          atomicOr((unsigned long long*)&ubuf[(pos >> 6) - u_first], 1ULL << (pos & 63));
+        else
+          atomicOr((unsigned long long*)&unary[pos >> 6], 1ULL << (pos & 63));
+        const uint64_t t_glob = (uint64_t)i * K + jj;
+        if ((t_glob & (kSelBlock - 1)) == 0) sel[t_glob / kSelBlock] = pos;
+        excl = pos + 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (w) flush_words(dbuf, data, d_first, (uint32_t)(((base + jend * w - 1) >> 6) - d_first), tid);
+  if (rice && u_lds && ctot) flush_words(ubuf, unary, u_first, (uint32_t)(((carry + ctot - 1) >> 6) - u_first), tid);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1698,12 +1737,12 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   uint32_t* vmax = (uint32_t*)(stats + (uint64_t)B * 33 + 2);
   const uint64_t R = (uint64_t)(((unsigned __int128)total << 32) / K);
   hipLaunchKernelGGL(k_stats_init, dim3(grid_for(nstat)), dim3(kBlock), 0, st, stats, nstat, (uint64_t)B * 33);
-  {  // at most kStatsPerThread values per thread (about 16 when K allows: enough workgroups to fill
-     // the device); a grid row may hold 2^31 - 1 workgroups
-    const uint64_t G = std::max<uint64_t>((K + (uint64_t)kStatsPerThread * kBlock - 1) / ((uint64_t)kStatsPerThread * kBlock),
-                                          std::max<uint64_t>(1, K / (16 * kBlock)));
-    hipLaunchKernelGGL(k_encoder_stats, dim3((uint32_t)G, B), dim3(kBlock), 0, st, pilots, K, shsum, vmax);
-  }
+  // one workgroup per (chunk, encoder) in the statistics and the packing
+  const uint64_t nch = (K + kPackChunk - 1) / kPackChunk;
+  uint32_t* ccnt;
+  PHOBIC_HIP(S.get(&ccnt, (uint64_t)B * nch * 32));
+  if (nch)
+    hipLaunchKernelGGL(k_encoder_stats, dim3((uint32_t)nch, B), dim3(kBlock), 0, st, pilots, K, shsum, vmax, ccnt);
   hipLaunchKernelGGL(k_offset_stats, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, toff, K, R, dmm);
   PHOBIC_HIP(hipGetLastError());
   uint64_t* hstats;  // pinned
@@ -1756,12 +1795,19 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   PHOBIC_HIP(S.upload(dhw, hw.data(), hw.size()));
   hipLaunchKernelGGL(k_image_init, dim3(grid_for(nwords)), dim3(kBlock), 0, st, img, nwords, dhw,
                      (uint32_t)kHeaderWords, hdr[kHSecEnc], B);
-  uint64_t* d_ubase = rice ? dhw + kHeaderWords + B : nullptr;
+  uint64_t* carries = nullptr;
+  if (rice && nch) {
+    PHOBIC_HIP(S.get(&carries, (uint64_t)B * nch));
+    hipLaunchKernelGGL(k_chunk_carry, dim3(B), dim3(kBlock), 0, st, ccnt, K, nch, dhw + kHeaderWords,
+                       dhw + kHeaderWords + B, carries);
+  }
   if (woff)
     hipLaunchKernelGGL(k_pack_offsets, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, toff, K, R, dmin, woff,
                        img + hdr[kHSecOff]);
-  hipLaunchKernelGGL(k_pack_values, dim3(B), dim3(kPackThreads), 0, st, pilots, K, img + hdr[kHSecEnc], d_ubase,
-                     (uint32_t)rice, img + hdr[kHSecData], img + hdr[kHSecUnary], img + hdr[kHSecSel]);
+  if (nch)
+    hipLaunchKernelGGL(k_pack_values, dim3((uint32_t)nch, B), dim3(kPackThreads), 0, st, pilots, K,
+                       img + hdr[kHSecEnc], carries, (uint32_t)rice, img + hdr[kHSecData], img + hdr[kHSecUnary],
+                       img + hdr[kHSecSel]);
   if (rice && K * B)
     hipLaunchKernelGGL(k_sel_fill, dim3(grid_for((K * B + kSelBlock - 1) / kSelBlock)), dim3(kBlock), 0, st,
                        img + hdr[kHSecUnary], img + hdr[kHSecSel], (K * B + kSelBlock - 1) / kSelBlock, K * B);
