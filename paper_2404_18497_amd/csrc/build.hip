@@ -966,12 +966,23 @@ __global__ __launch_bounds__(kBlock) void k_encoder_stats(const uint32_t* __rest
   for (int t = 0; t < 8; t++) cnt8[t] = 0;
   uint32_t lmx = 0;
   const uint32_t* col = pilots + (uint64_t)i * K;
-  const uint64_t j1 = min(K, (uint64_t)(blockIdx.x + 1) * kPackChunk);
-  for (uint64_t jj = (uint64_t)blockIdx.x * kPackChunk + tid; jj < j1; jj += kBlock) {
-    const uint32_t v = col[jj];
-    lmx = max(lmx, v);
+  {  // the thread's kPackChunk / kBlock values, all loads issued before the counting (clamped
+     // index; a value past K counts as zero)
+    constexpr int kPer = kPackChunk / kBlock;
+    const uint64_t j0 = (uint64_t)blockIdx.x * kPackChunk + tid;
+    uint32_t v[kPer];
 #pragma unroll
-    for (int t = 0; t < 8; t++) cnt8[t] += (v >> t) & 0x01010101u;
+    for (int u = 0; u < kPer; u++) {
+      const uint64_t jj = j0 + (uint64_t)u * kBlock;
+      v[u] = col[jj < K ? jj : K - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; u++) {
+      const uint32_t x = j0 + (uint64_t)u * kBlock < K ? v[u] : 0u;
+      lmx = max(lmx, x);
+#pragma unroll
+      for (int t = 0; t < 8; t++) cnt8[t] += (x >> t) & 0x01010101u;
+    }
   }
   // 16-bit fields: the counts of bits s and 16 + s (even bytes) and 8 + s and 24 + s (odd bytes); a
   // field sums at most kPackChunk < 2^16 values over the workgroup
@@ -1018,8 +1029,14 @@ __global__ __launch_bounds__(kBlock) void k_offset_stats(const uint64_t* __restr
     lmin = min(lmin, d);
     lmax = max(lmax, d);
   }
-  atomicMin(&mm[0], lmin);
-  atomicMax(&mm[1], lmax);
+  for (int o = 32; o > 0; o >>= 1) {  // one pair of atomics per wavefront
+    lmin = min(lmin, (long long)__shfl_xor(lmin, o));
+    lmax = max(lmax, (long long)__shfl_xor(lmax, o));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&mm[0], lmin);
+    atomicMax(&mm[1], lmax);
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_offsets(const uint64_t* __restrict__ toff, uint64_t K, uint64_t R,
