@@ -1029,11 +1029,21 @@ __global__ __launch_bounds__(kBlock) void k_offset_stats(const uint64_t* __restr
     lmin = min(lmin, d);
     lmax = max(lmax, d);
   }
-  for (int o = 32; o > 0; o >>= 1) {  // one pair of atomics per wavefront
+  __shared__ long long wmin[kBlock / 64], wmax[kBlock / 64];
+  for (int o = 32; o > 0; o >>= 1) {
     lmin = min(lmin, (long long)__shfl_xor(lmin, o));
     lmax = max(lmax, (long long)__shfl_xor(lmax, o));
   }
   if ((threadIdx.x & 63) == 0) {
+    wmin[threadIdx.x >> 6] = lmin;
+    wmax[threadIdx.x >> 6] = lmax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {  // one pair of atomics per workgroup
+    for (int w = 1; w < kBlock / 64; w++) {
+      lmin = min(lmin, wmin[w]);
+      lmax = max(lmax, wmax[w]);
+    }
     atomicMin(&mm[0], lmin);
     atomicMax(&mm[1], lmax);
   }
@@ -1760,7 +1770,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   PHOBIC_HIP(S.get(&ccnt, (uint64_t)B * nch * 32));
   if (nch)
     hipLaunchKernelGGL(k_encoder_stats, dim3((uint32_t)nch, B), dim3(kBlock), 0, st, pilots, K, shsum, vmax, ccnt);
-  hipLaunchKernelGGL(k_offset_stats, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, toff, K, R, dmm);
+  hipLaunchKernelGGL(k_offset_stats, dim3(grid_for(K + 1, kBlock, 64)), dim3(kBlock), 0, st, toff, K, R, dmm);
   PHOBIC_HIP(hipGetLastError());
   uint64_t* hstats;  // pinned
   uint32_t* herrp;
