@@ -384,3 +384,20 @@ def test_search_shapes_do_not_change_results(torch):
                 assert np.array_equal(binding.build_u64(dk, prm).serialize(), ref), (w, g, grab)
     finally:
         binding.set_search_config(**before)
+
+
+def test_query_batches_on_two_streams(torch):
+    """Independent query batches issued round-robin on two streams (the bulk-query pattern of the
+    benchmark) give the oracle's positions."""
+    keys = synth.u64_keys(300_000, 23)
+    g, r = _both(torch, keys)
+    q = keys[synth.query_indices(keys.size, 1_000_000, 29)]
+    dq = _dev(torch, q)
+    out = torch.empty(q.size, dtype=torch.int64, device="cuda")
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    batch = 65_536
+    for i, b in enumerate(range(0, q.size, batch)):
+        g.query_u64(dq[b:b + batch], out=out[b:b + batch], stream=streams[i % 2])
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint64), r.query_u64(q))
+    g.close()
