@@ -64,8 +64,10 @@ def cmd_kernels(a):
     rows = list(csv.DictReader(open(a.stats)))
     total = sum(float(r["TotalDurationNs"]) for r in rows)
     lines = [f"# {a.title}", "", "Command (from the repository root on the GPU host, `$R` = repository root):", "",
-             "```", a.command, "```", "", f"Per step = total / {a.steps} timed+warm-up steps profiled.", "",
-             "| Kernel | Calls | Total ms | Avg us | % of GPU time |", "|---|---|---|---|---|"]
+             "```", a.command, "```", "", f"Per step = total / {a.steps} timed+warm-up steps profiled.", ""]
+    if a.note:
+        lines += [a.note, ""]
+    lines += ["| Kernel | Calls | Total ms | Avg us | % of summed kernel time |", "|---|---|---|---|---|"]
     for r in rows:
         lines.append(f"| {short_name(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {100 * float(r['TotalDurationNs']) / total:.2f} |")
@@ -126,6 +128,7 @@ def main():
     k.add_argument("--title", required=True)
     k.add_argument("--command", required=True)
     k.add_argument("--out", required=True)
+    k.add_argument("--note", default="", help="a paragraph printed above the table")
     t = sub.add_parser("traffic")
     for x in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--title", "--out", "--json"):
         t.add_argument(x, required=True)
