@@ -1778,6 +1778,15 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   PHOBIC_HIP(S.host(&herrp, 1));
   PHOBIC_HIP(hipMemcpyAsync(hstats, stats, nstat * 8, hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipMemcpyAsync(herrp, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  {  // while the device searches: take and give back a block of the likely image size (3 bits/key
+     // and 40 per partition), so that the image allocation after the round trip finds mapped memory
+     // in the pool instead of mapping pages on the critical path
+    void* warm = nullptr;
+    if (pool_alloc(&warm, (size_t)((3 * n + 40 * K) / 8) + ((size_t)B << 7) + 4096, st) == hipSuccess)
+      (void)hipFreeAsync(warm, st);
+    else
+      (void)hipGetLastError();  // only a hint: a failure here must not surface later
+  }
   PHOBIC_HIP(hipStreamSynchronize(st));
   const uint64_t* hsh = hstats;
   const long long* hmm = (const long long*)(hstats + (uint64_t)B * 33);
