@@ -224,6 +224,9 @@ double phobic_server_now(phobic_server* s); /* the server's clock, seconds */
 /* Waits for every queued request, then frees the resident MPHFs and the server. */
 void phobic_server_destroy(phobic_server* s);
 
+/* Releases a handle.  The image goes back to the library's pool in the order of the default (NULL)
+ * stream, which follows the work already queued on blocking streams; queries still queued on a
+ * non-blocking stream must have completed, or been joined into the default stream, before the call. */
 void phobic_free(phobic_mphf* h);
 const char* phobic_status_str(phobic_status s);
 const char* phobic_last_error(void);
