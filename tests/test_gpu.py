@@ -227,9 +227,11 @@ def _golden_100m(lam):
 def test_full_size_100m(torch, keys_100m, lam, coding):
     """The benchmark workload (100M keys, P 2500) at lambda 5, 7 and 9: the whole device image
     (Rice) and the whole pilot array hash to the values the oracle's own 100M-key build produced
-    (tests/golden, written by a script that calls only the oracle); bijection over all keys; at
-    lambda 7 also pilots of sampled partitions against the oracle's search on the same codes,
-    sampled queries against the oracle reading the device image, and the encoder parameters."""
+    (tests/golden, written by a script that calls only the oracle); bijection over all keys; sampled
+    queries against the oracle reading the device image; at lambda 7 also the benchmark's 100M
+    lookups in its launch configuration (batches of 1M on two streams) against the positions above,
+    pilots of sampled partitions against the oracle's search on the same codes, and the encoder
+    parameters."""
     import hashlib
 
     keys, dk = keys_100m
@@ -257,6 +259,16 @@ def test_full_size_100m(torch, keys_100m, lam, coding):
     assert np.array_equal(oracle.query_image_u64(img, keys[sample]), got)
     if lam != 7.0 or coding != "rice":
         return
+    _say("100M keys: the benchmark's lookups in batches of 1M on two streams")
+    qidx = torch.from_numpy(synth.query_indices(n, n, 2)).cuda()
+    dq = dk[qidx]
+    out = torch.empty(n, dtype=torch.int64, device=dk.device)
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    for i, b in enumerate(range(0, n, 1_000_000)):
+        g.query_u64(dq[b:b + 1_000_000], out=out[b:b + 1_000_000], stream=streams[i % 2])
+    torch.cuda.synchronize()
+    assert torch.equal(out, pos[qidx]), "batched lookups differ from the single launch"
+    del dq, out, qidx
     _say("100M keys: sampled partitions")
     offs, codes = binding.partition_u64(dk, prm)
     offs = offs.cpu().numpy().view(np.uint64)
