@@ -16,7 +16,7 @@
  *   4. bucket ordering: size descending, then expected size
  *      ascending                                                   (Sec. 3 intro; Sec. 5.1 "Further remarks")
  *   5. seed (pilot) search with the additive displacement hash     (Sec. 4, "Hash Function")
- *   6. interleaved coding, Compact or Golomb-Rice                  (Sec. 4.1)
+ *   6. interleaved coding, Compact, Golomb-Rice or a mix of both   (Sec. 4.1)
  *   7. partition offsets stored relative to their expectation       (Sec. 4, "Encoding the offsets")
  *   8. query                                                       (Sec. 4, "Hash Function", last sentences)
  *   9. non-minimal variant with remapping                          (App. B; Sec. 5.1 "Further remarks")
@@ -57,7 +57,7 @@ typedef struct {
   uint32_t alpha_den;
   uint64_t hash_seed;
   uint64_t pilot_limit;    /* largest admissible pilot; 0 means 2^32 - 1 */
-  uint32_t n_compact;      /* reserved, 0 or B */
+  uint32_t n_compact;      /* interleaved Rice: encoders 0 .. n_compact-1 use Compact instead (0..B) */
   uint32_t reserved;
 } ref_params;
 
@@ -204,7 +204,10 @@ static int validate(const ref_params *p, uint32_t *B) {
   double b = ceil((double)p->partition_size / p->lambda);
   if (b < 1.0 || b > 65535.0) return REF_E_INVALID;
   *B = num_buckets(p->partition_size, p->lambda);
-  if (p->n_compact != 0 && p->n_compact != *B) return REF_E_INVALID;
+  /* mixed coding (Sec. 4.1: Compact for the large buckets, Rice for the rest) is a variant of the
+   * interleaved Rice image; an all-Compact image has no Rice encoders to replace */
+  if (p->coding == 0 && p->n_compact > *B) return REF_E_INVALID;
+  if (p->coding == 1 && p->n_compact != 0 && p->n_compact != *B) return REF_E_INVALID;
   return REF_OK;
 }
 
@@ -262,7 +265,7 @@ uint32_t phobic_ref_rice_param(uint64_t sum, uint64_t count) {
 enum {
   H_MAGIC = 0, H_N, H_K, H_B, H_P, H_LAMBDA, H_ALPHA, H_CODING, H_SEED, H_TOTAL, H_DMIN, H_WOFF,
   H_SEC_OFF, H_SEC_ENC, H_SEC_DATA, H_SEC_UNARY, H_SEC_SEL, H_SEC_REMAP, H_WREMAP, H_NREMAP,
-  H_UBITS, H_WORDS, H_RPART, H_SPARE
+  H_UBITS, H_WORDS, H_RPART, H_NCOMPACT
 };
 
 struct ref_mphf {
@@ -461,6 +464,9 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
   const uint32_t B = h->B;
   const uint64_t Ttot = h->offsets[K];
   const int rice = h->prm.coding == 0;
+  /* mixed interleaved coding: encoder i is Compact for i < c and Golomb-Rice for i >= c (the first
+   * buckets are the largest, hence queried most often; Sec. 4.1) */
+  const uint32_t c = rice ? h->prm.n_compact : 0;
 
   /* partition offsets as differences to their expectation, shifted by the minimum (Sec. 4) */
   uint64_t R = (uint64_t)(((unsigned __int128)Ttot << 32) / K);
@@ -476,7 +482,8 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
   }
   unsigned woff = bit_length(umax);
 
-  /* per-encoder parameter: encoder i holds the pilots of bucket i of all K partitions (Sec. 4.1) */
+  /* per-encoder parameter: encoder i holds the pilots of bucket i of all K partitions (Sec. 4.1);
+   * Compact takes the bit length of the largest value, Rice Kiely's parameter */
   uint32_t *width = calloc(B, sizeof(uint32_t));
   uint64_t *base = calloc(B, sizeof(uint64_t));
   if (!width || !base) { free(width); free(base); return REF_E_OOM; }
@@ -488,10 +495,11 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
       sum += v;
       if (v > mx) mx = v;
     }
-    width[i] = rice ? phobic_ref_rice_param(sum, K) : bit_length(mx);
+    const int enc_rice = rice && i >= c;
+    width[i] = enc_rice ? phobic_ref_rice_param(sum, K) : bit_length(mx);
     base[i] = data_bits;
     data_bits += (uint64_t)width[i] * K;
-    if (rice)
+    if (enc_rice)
       for (uint64_t j = 0; j < K; j++) unary_bits += ((uint64_t)h->pilots[j * B + i] >> width[i]) + 1;
   }
   if (rice && unary_bits > 0xFFFFFFFFULL) { free(width); free(base); return REF_E_CAPACITY; }
@@ -505,7 +513,7 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
   uint64_t sec_enc = sec_off + ((K + 1) * woff + 63) / 64 + 1;
   uint64_t sec_data = sec_enc + B + 1;
   uint64_t sec_unary = sec_data + (data_bits + 63) / 64 + 1;
-  uint64_t nvals = K * B;
+  uint64_t nvals = K * (B - c); /* values of the Rice encoders, each one a one of the unary stream */
   uint64_t nsel = rice ? (nvals + SEL_BLOCK - 1) / SEL_BLOCK : 0;
   uint64_t sec_sel = sec_unary + (rice ? (unary_bits + 63) / 64 + 1 : 0);
   uint64_t sec_remap = sec_sel + (rice ? nsel + 1 : 0);
@@ -536,6 +544,7 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
   w[H_UBITS] = rice ? unary_bits : 0;
   w[H_WORDS] = total;
   w[H_RPART] = R;
+  w[H_NCOMPACT] = c;
 
   for (uint64_t j = 0; j <= K; j++) {
     uint64_t u = (uint64_t)((int64_t)(h->offsets[j] - expected_offset(j, R)) - dmin);
@@ -544,7 +553,8 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
   for (uint32_t i = 0; i < B; i++) w[sec_enc + i] = (base[i] << 8) | width[i];
 
   /* Compact: fixed width per encoder.  Golomb-Rice: the low width[i] bits compact, the rest as
-   * q = v >> width[i] in unary (q zeros then a one) in one stream ordered encoder by encoder. */
+   * q = v >> width[i] in unary (q zeros then a one) in one stream ordered encoder by encoder; the
+   * stream holds the Rice encoders only, so value j of encoder i >= c is its one number (i - c) K + j. */
   uint64_t upos = 0, ones = 0;
   for (uint32_t i = 0; i < B; i++)
     for (uint64_t j = 0; j < K; j++) {
@@ -552,7 +562,7 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
       unsigned wd = width[i];
       uint64_t low = wd >= 64 ? v : (v & (((uint64_t)1 << wd) - 1));
       put_bits(w + sec_data, base[i] + j * wd, low, wd);
-      if (rice) {
+      if (rice && i >= c) {
         upos += v >> wd;
         w[sec_unary + (upos >> 6)] |= (uint64_t)1 << (upos & 63);
         if (ones % SEL_SUB == 0) {
@@ -735,8 +745,9 @@ static uint64_t query_hash(const uint64_t *w, const uint64_t *T, uint64_t hi, ui
   uint64_t e = w[w[H_SEC_ENC] + i];
   unsigned wd = (unsigned)(e & 0xFF);
   uint64_t p = get_bits(w + w[H_SEC_DATA], (e >> 8) + j * wd, wd);
-  if (w[H_CODING] == 0) {
-    uint64_t t = (uint64_t)i * K + j;
+  const uint64_t c = w[H_NCOMPACT]; /* encoders below c are Compact */
+  if (w[H_CODING] == 0 && i >= c) {
+    uint64_t t = (uint64_t)(i - c) * K + j;
     const uint64_t *un = w + w[H_SEC_UNARY], *sel = w + w[H_SEC_SEL];
     uint64_t pt = select_one(un, sel, t);
     uint64_t prev = t ? select_one(un, sel, t - 1) : (uint64_t)-1;

@@ -87,6 +87,57 @@ def test_string_hash_distinguishes_length_and_content(ref):
     assert len(pairs) == len(strs)
 
 
+def _strings(items):
+    buf = np.frombuffer(b"".join(items), dtype=np.uint8)
+    offs = np.zeros(len(items) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(s) for s in items])
+    return buf, offs
+
+
+def _chi2_ok(counts):
+    exp = counts.sum() / counts.size
+    dof = counts.size - 1
+    return ((counts - exp) ** 2 / exp).sum() < dof + 6 * math.sqrt(2 * dof)
+
+
+@pytest.mark.parametrize("family", ["counter", "long_prefix", "one_char", "random"])
+def test_string_hash_partition_and_bucket_bits_uniform(ref, family):
+    # Structured key sets (a shared prefix and a decimal counter, a 30-byte prefix so that only the
+    # last 8-byte word differs, strings that differ in a single character at every position, and the
+    # benchmark's random strings): the partition index mulhi(hi, K) and the bucket bits (the top bits
+    # of lo, which pick the table interval) must be uniform, and no two codes may be equal.  A chain
+    # that dropped the zero-padded last word, the length or one of the two mixers fails here.
+    if family == "counter":
+        items = [b"user:%07d" % i for i in range(40_000)]
+    elif family == "long_prefix":
+        items = [b"k" * 30 + b"%d" % i for i in range(40_000)]
+    elif family == "one_char":
+        base = bytearray(b"abcdefghijklmnopqrstuvwxyz0123456789abcdefghijklm")  # 49 bytes
+        items = []
+        for pos in range(len(base)):
+            for c in b"abcdefghijklmnopqrstuvwxyz0123456789":
+                if c != base[pos]:
+                    v = bytearray(base)
+                    v[pos] = c
+                    items.append(bytes(v))
+        items += [bytes(base[:L]) for L in range(len(base) + 1)]  # every prefix, the empty string too
+    else:
+        buf, offs = synth.ascii_strings(40_000, 3)
+        items = [bytes(buf[offs[i]:offs[i + 1]]) for i in range(offs.size - 1)]
+    buf, offs = _strings(items)
+    hi, lo = ref.hash_str(buf, offs, 0x5EED)
+    assert len(set(zip(hi.tolist(), lo.tolist()))) == len(items)
+    K = 64
+    part = ((hi >> np.uint64(32)) * np.uint64(K)
+            + (((hi & np.uint64(0xFFFFFFFF)) * np.uint64(K)) >> np.uint64(32))) >> np.uint64(32)
+    assert all(ref.partition_of(int(h), K) == int(p) for h, p in zip(hi[:500], part[:500]))
+    assert _chi2_ok(np.bincount(part.astype(np.int64), minlength=K))
+    assert _chi2_ok(np.bincount((lo >> np.uint64(56)).astype(np.int64), minlength=256))
+    # the fingerprint's position under seed 0 must be uniform as well (it decides the slots)
+    pos = np.array([ref.pos_hash(int(h), int(l), 0, 97) for h, l in zip(hi[:20_000], lo[:20_000])])
+    assert _chi2_ok(np.bincount(pos, minlength=97))
+
+
 # --------------------------------------------------------------------------------------------------
 # bucket assignment function
 # --------------------------------------------------------------------------------------------------
@@ -377,6 +428,81 @@ def test_select_entries_and_unary_stream_match_pilots(ref):
     assert overflow > 0
     pos = ref.query_image_u64(img, keys)
     assert np.array_equal(np.sort(pos), np.arange(keys.size, dtype=np.uint64))
+
+
+def _unpack_values(img, H, K, B, c):
+    """Every encoder's values read back from the image with numpy: encoder i < c from its fixed-width
+    fields (Compact), encoder i >= c from its low bits and the unary stream's ones (Rice)."""
+    enc = img[H["sec_enc"]: H["sec_enc"] + B]
+    widths, bases = (enc & np.uint64(0xFF)).astype(np.int64), (enc >> np.uint64(8)).astype(np.int64)
+    data = np.unpackbits(img[H["sec_data"]: H["sec_unary"]].view(np.uint8), bitorder="little")
+    words = img[H["sec_unary"]: H["sec_sel"] - 1]
+    bits = np.unpackbits(words.view(np.uint8), bitorder="little")[: H["ubits"]]
+    ones = np.flatnonzero(bits).astype(np.int64)
+    high = np.diff(np.concatenate([[-1], ones])) - 1
+    out = np.zeros((K, B), dtype=np.int64)
+    for i in range(B):
+        w = int(widths[i])
+        low = np.zeros(K, dtype=np.int64)
+        for b in range(w):
+            low |= data[bases[i] + np.arange(K) * w + b].astype(np.int64) << b
+        out[:, i] = low if i < c else low | (high[(i - c) * K:(i - c + 1) * K] << w)
+    return out, widths, ones
+
+
+@pytest.mark.parametrize("c", [0, 1, 16, "half", "all_but_one", "all"])
+def test_mixed_coding_image(ref, c):
+    # Sec. 4.1: interleaved coding may mix encoders, Compact for the first buckets (the largest, so
+    # the most often queried) and Golomb-Rice for the rest.  Encoders i < c take the bit length of
+    # their largest value, encoders i >= c Kiely's parameter; the unary stream holds the Rice encoders
+    # only (K (B - c) ones); read back with numpy, the fields rebuild the pilot array; the select
+    # entries cover the Rice values; every key maps to its own position; c = 0 is the plain Rice
+    # image.  The search does not depend on the coding.
+    keys = synth.u64_keys(60_000, 41)
+    B = ref.num_buckets(2500, 7.0)
+    cc = {"half": B // 2, "all_but_one": B - 1, "all": B}.get(c, c)
+    h = ref.build_u64(keys, ref.params(lam=7.0, n_compact=cc), threads=4)
+    plain = ref.build_u64(keys, ref.params(lam=7.0), threads=4)
+    assert np.array_equal(h.pilots(), plain.pilots())
+    img = h.image()
+    H = _header(img)
+    K = H["K"]
+    assert int(img[23]) == cc and H["coding"] == 0 and H["words"] == img.size
+    pil = h.pilots().astype(np.int64)
+    vals, widths, ones = _unpack_values(img, H, K, B, cc)
+    assert np.array_equal(vals, pil)
+    assert ones.size == K * (B - cc)
+    for i in range(B):
+        col = pil[:, i]
+        want = int(col.max()).bit_length() if i < cc else ref.rice_param(int(col.sum()), K)
+        assert widths[i] == want, i
+    sel = img[H["sec_sel"]: H["sec_remap"] - 1]
+    assert sel.size == (K * (B - cc) + 255) // 256
+    for s_ in range(sel.size):
+        assert int(sel[s_]) & 0xFFFFFFFF == int(ones[256 * s_])
+    pos = h.query_u64(keys)
+    assert _is_perm(pos, keys.size)
+    assert np.array_equal(ref.query_image_u64(img, keys), pos)
+    if cc == 0:
+        assert np.array_equal(img, plain.image())
+    # the positions do not depend on the coding either
+    assert np.array_equal(pos, plain.query_u64(keys))
+
+
+def test_mixed_coding_bijection_tiny_and_invalid(ref):
+    for n in [0, 1, 2, 7, 64, 65, 300]:
+        keys = synth.u64_keys(n, 900 + n)
+        for lam, P in [(3.0, 4), (5.0, 100), (2.5, 1)]:
+            B = ref.num_buckets(P, lam)
+            for cc in sorted({0, 1, B // 2, B}):
+                h = ref.build_u64(keys, ref.params(partition_size=P, lam=lam, n_compact=cc))
+                assert _is_perm(h.query_u64(keys), n), (n, lam, P, cc)
+    keys = synth.u64_keys(100, 5)
+    B = ref.num_buckets(2500, 7.0)
+    for bad in [ref.params(lam=7.0, n_compact=B + 1), ref.params(lam=7.0, coding="compact", n_compact=3)]:
+        with pytest.raises(ref.OracleError) as e:
+            ref.build_u64(keys, bad)
+        assert e.value.code == 1
 
 
 # --------------------------------------------------------------------------------------------------
