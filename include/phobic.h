@@ -30,7 +30,7 @@ extern "C" {
 typedef enum {
   PHOBIC_OK = 0,
   PHOBIC_E_INVALID = 1,        /* bad argument or parameter */
-  PHOBIC_E_DUPLICATE = 2,      /* two keys share their 128-bit master hash code (equal keys) */
+  PHOBIC_E_DUPLICATE = 2,      /* two keys of one bucket share their 64-bit fingerprint (equal keys) */
   PHOBIC_E_OOM = 3,            /* device or host allocation failed */
   PHOBIC_E_PILOT_OVERFLOW = 4, /* a bucket needs a pilot above params.pilot_limit */
   PHOBIC_E_DEVICE = 5,         /* a HIP runtime call failed */
@@ -50,7 +50,9 @@ typedef struct {
   uint32_t alpha_den;      /*   alpha < 1 builds a table of ceil(n_j / alpha) slots and remaps */
   uint64_t hash_seed;      /* seed of the 128-bit key hash */
   uint64_t pilot_limit;    /* largest admissible pilot; 0 = 2^32 - 1 */
-  uint32_t n_compact;      /* reserved: must be 0 or B */
+  uint32_t n_compact;      /* mixed interleaved coding (Sec. 4.1): with PHOBIC_IC_RICE, encoders
+                              0 .. n_compact-1 (the largest, most queried buckets) use Compact and the
+                              rest Golomb-Rice; 0 .. B.  With PHOBIC_IC_COMPACT it must be 0 or B. */
   uint32_t flags;          /* PHOBIC_FLAG_* */
 } phobic_params;
 
@@ -67,7 +69,9 @@ typedef struct {
   double total_ms;       /* first kernel to last, host round trips included */
   uint64_t max_partition_keys;
   uint32_t max_bucket_keys;
-  uint32_t reserved;
+  uint32_t partition_path; /* 0: coarse bins of a few partitions, two splits and a per-bin sort;
+                              1: the general path (per-key global atomics), taken when the coarse
+                              bins would not fit one histogram or n >= 2^32 */
 } phobic_build_info;
 
 /* Fills *p with the defaults: P = 2500, lambda = 7, alpha = 1, interleaved Rice, seed 0x5EED. */
@@ -105,25 +109,32 @@ phobic_status phobic_query_multi_u64(const phobic_mphf* const* h_handles, const 
                                      const uint64_t* h_counts, uint64_t* const* h_outs, uint32_t count,
                                      void* hip_stream);
 
-/* Size of the structure in bits = 8 x serialized bytes (header and tables included). */
+/* Size of the structure in bits = 8 x serialized bytes, header and tables included; divided by n it
+ * is the space measure (bits per key) of Sec. 5 and Table 1. */
 uint64_t phobic_size_bits(const phobic_mphf* h);
 uint64_t phobic_num_keys(const phobic_mphf* h);
 uint64_t phobic_num_partitions(const phobic_mphf* h);
 uint32_t phobic_num_buckets(const phobic_mphf* h);
 
-/* Copies the pilots, partition-major (h_out[j * B + i] = pilot of bucket i of partition j), into
- * h_out (host, cap entries).  Needs PHOBIC_FLAG_KEEP_PILOTS at build time. */
+/* Copies the pilots (the per-bucket seeds of Sec. 4, "Hash Function", before interleaved coding),
+ * partition-major (h_out[j * B + i] = pilot of bucket i of partition j), into h_out (host, cap
+ * entries).  Needs PHOBIC_FLAG_KEEP_PILOTS at build time; PHOBIC_E_INVALID without it or when cap
+ * is below K * B. */
 phobic_status phobic_get_pilots(const phobic_mphf* h, uint32_t* h_out, uint64_t cap);
 
 /* Per-phase times of the build that produced h (zeros for deserialized handles; for members of a
  * batch, the times of the whole batch, with hashing, partitioning and bucketing in bucket_sort_ms). */
 phobic_status phobic_get_build_info(const phobic_mphf* h, phobic_build_info* out);
 
-/* Serializes h into h_buf (host).  *inout_bytes holds the capacity on entry and the image size on
- * return; with h_buf = NULL only the size is returned. */
+/* Serializes h into h_buf (host): the partition offsets as differences to their expectation
+ * (Sec. 4, "Encoding the offsets") and the interleaved pilot encoders (Sec. 4.1), little-endian
+ * 64-bit words.  *inout_bytes holds the capacity on entry and the image size on return; with
+ * h_buf = NULL only the size is returned; a smaller capacity gives PHOBIC_E_INVALID. */
 phobic_status phobic_serialize(const phobic_mphf* h, void* h_buf, uint64_t* inout_bytes);
 
-/* Rebuilds a handle on the current device from an image made by phobic_serialize. */
+/* Rebuilds a handle on the current device from an image made by phobic_serialize (the layout of
+ * Sec. 4 and Sec. 4.1 written there).  Every field, section extent, unary stream and select entry is
+ * checked on the host first; an inconsistent image gives PHOBIC_E_FORMAT and no handle. */
 phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, void* hip_stream, phobic_mphf** out);
 
 /* Hashing and partitioning alone, for parity checks: hashes and partitions the keys.  d_offsets gets K + 1
@@ -150,7 +161,9 @@ phobic_status phobic_get_search_config(phobic_search_config* out);
 
 /* Builds `count` independent MPHFs together: MPHF t is built from the h_counts[t] distinct keys at
  * the device pointer h_key_ptrs[t] (both arrays are host arrays of `count` entries), all with the
- * same params (alpha must be 1).  Every handle outs[t] is identical -- pilots, image, positions --
+ * same params (alpha must be 1).  Each member follows the construction of Sec. 3, Sec. 4 and
+ * Sec. 4.1 exactly as phobic_build_u64 does; the partition independence that makes this possible is
+ * the one Sec. 4.2 relies on for its parallel search.  Every handle outs[t] is identical -- pilots, image, positions --
  * to what phobic_build_u64 returns for the same keys.  Hashing, partitioning and bucketing run over
  * the concatenated key sets; the pilot search is one persistent launch over all (MPHF, partition)
  * items; encoding runs for all MPHFs in a handful of launches.  The handles share one device

@@ -68,7 +68,7 @@ class BuildInfo(C.Structure):
     _fields_ = [("hash_count_ms", C.c_double), ("scan_ms", C.c_double), ("scatter_ms", C.c_double),
                 ("bucket_sort_ms", C.c_double), ("search_ms", C.c_double), ("encode_ms", C.c_double),
                 ("total_ms", C.c_double), ("max_partition_keys", C.c_uint64), ("max_bucket_keys", C.c_uint32),
-                ("reserved", C.c_uint32)]
+                ("partition_path", C.c_uint32)]
 
 
 _lib = None
@@ -136,7 +136,7 @@ def _check(code: int):
 
 
 def params(partition_size=2500, lam=7.0, alpha=(1, 1), coding="rice", hash_seed=0x5EED, pilot_limit=0,
-           keep_pilots=False) -> Params:
+           keep_pilots=False, n_compact=0) -> Params:
     p = Params()
     lib().phobic_params_default(C.byref(p))
     p.partition_size = partition_size
@@ -145,6 +145,7 @@ def params(partition_size=2500, lam=7.0, alpha=(1, 1), coding="rice", hash_seed=
     p.coding = RICE if coding == "rice" else COMPACT
     p.hash_seed = hash_seed
     p.pilot_limit = pilot_limit
+    p.n_compact = n_compact
     p.flags = FLAG_KEEP_PILOTS if keep_pilots else 0
     return p
 
@@ -218,7 +219,7 @@ class MPHF:
     def build_info(self) -> dict:
         bi = BuildInfo()
         _check(lib().phobic_get_build_info(self.h, C.byref(bi)))
-        return {f: getattr(bi, f) for f, _ in BuildInfo._fields_ if f != "reserved"}
+        return {f: getattr(bi, f) for f, _ in BuildInfo._fields_}
 
     def serialize(self) -> np.ndarray:
         size = C.c_uint64(0)

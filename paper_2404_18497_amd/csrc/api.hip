@@ -43,7 +43,12 @@ phobic_status validate_params(const phobic_params* p, uint32_t* B) {
   double b = std::ceil((double)p->partition_size / p->lambda);  // B = P / lambda (Sec. 4.1)
   if (b < 1.0 || b > 65535.0) return fail(PHOBIC_E_INVALID, "B = ceil(P / lambda) must be in [1, 65535]");
   *B = (uint32_t)b;
-  if (p->n_compact != 0 && p->n_compact != *B) return fail(PHOBIC_E_INVALID, "n_compact must be 0 or B");
+  // mixed interleaved coding (Sec. 4.1: Compact for the first, largest buckets, Golomb-Rice for the
+  // rest) is a variant of the Rice image; an all-Compact image has no Rice encoders to replace
+  if (p->coding == PHOBIC_IC_RICE && p->n_compact > *B)
+    return fail(PHOBIC_E_INVALID, "n_compact must be at most B");
+  if (p->coding == PHOBIC_IC_COMPACT && p->n_compact != 0 && p->n_compact != *B)
+    return fail(PHOBIC_E_INVALID, "n_compact must be 0 or B with Compact coding");
   return PHOBIC_OK;
 }
 
@@ -153,9 +158,10 @@ phobic_status upload_table(phobic_mphf* h, hipStream_t st) {
 std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phobic_params& prm, uint64_t total,
                                   int64_t dmin, uint32_t woff, uint64_t data_bits, uint64_t unary_bits, uint64_t R) {
   const bool rice = prm.coding == PHOBIC_IC_RICE;
+  const uint32_t c = rice ? prm.n_compact : 0;  // leading Compact encoders of a mixed image
   const uint64_t nremap = total - n;
   const uint32_t wremap = n > 1 ? host_bit_length_pub(n - 1) : 0;
-  const uint64_t nsel = rice ? (K * B + kSelBlock - 1) / kSelBlock : 0;
+  const uint64_t nsel = rice ? (K * (B - c) + kSelBlock - 1) / kSelBlock : 0;
   std::vector<uint64_t> hdr(kHeaderWords, 0);
   hdr[kHMagic] = kMagic;
   hdr[kHN] = n;
@@ -180,6 +186,7 @@ std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phob
   hdr[kHUbits] = rice ? unary_bits : 0;
   hdr[kHWords] = hdr[kHSecRemap] + (nremap ? (nremap * wremap + 63) / 64 + 1 : 0);
   hdr[kHR] = R;
+  hdr[kHNcompact] = c;
   return hdr;
 }
 
@@ -204,6 +211,7 @@ void fill_query_args(phobic_mphf* h) {
   a.woff = (uint32_t)H[kHWoff];
   a.coding = (uint32_t)H[kHCoding];
   a.wremap = (uint32_t)H[kHWremap];
+  a.ncompact = (uint32_t)H[kHNcompact];
 }
 
 static uint64_t host_bits(const uint64_t* w, uint64_t pos, uint32_t width) {
@@ -224,6 +232,8 @@ static phobic_status check_image(const uint64_t* w, uint64_t nwords) {
   if (w[kHWords] != nwords) return bad("length");
   const uint64_t n = w[kHN], K = w[kHK], B = w[kHB], total = w[kHTotal];
   if (K == 0 || B == 0 || B > 65535 || w[kHCoding] > 1 || total < n) return bad("sizes");
+  const uint64_t c = w[kHNcompact];  // Compact encoders before the Rice ones (Rice images only)
+  if (c > B || (w[kHCoding] != PHOBIC_IC_RICE && c != 0)) return bad("mixed coding");
   const uint32_t an = (uint32_t)w[kHAlpha], ad = (uint32_t)(w[kHAlpha] >> 32);
   if (an == 0 || ad == 0 || an > ad || w[kHP] == 0 || w[kHP] > 0xFFFFFFFFULL) return bad("parameters");
   double lambda;
@@ -252,7 +262,7 @@ static phobic_status check_image(const uint64_t* w, uint64_t nwords) {
     const uint32_t wd = (uint32_t)(e & 0xFF);
     if (wd > 32 || (e >> 8) + (uint64_t)wd * K > data_bits) return bad("encoder table");
   }
-  const uint64_t nvals = K * B;
+  const uint64_t nvals = K * (B - c);  // values of the Rice encoders: one one each in the unary stream
   if (w[kHCoding] == PHOBIC_IC_RICE) {
     const uint64_t ubits = w[kHUbits];
     if (su + (ubits + 63) / 64 + 1 != ss) return bad("unary length");
@@ -380,6 +390,7 @@ extern "C" phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, v
   h->prm.alpha_num = (uint32_t)w[kHAlpha];
   h->prm.alpha_den = (uint32_t)(w[kHAlpha] >> 32);
   h->prm.coding = (uint32_t)w[kHCoding];
+  h->prm.n_compact = (uint32_t)w[kHNcompact];
   h->prm.hash_seed = w[kHSeed];
   h->nwords = nwords;
   phobic_status r = upload_table(h, st);

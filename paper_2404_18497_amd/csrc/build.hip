@@ -1059,13 +1059,14 @@ __global__ __launch_bounds__(kBlock) void k_pack_offsets(const uint64_t* __restr
 
 // Rice: the unary start of every chunk, carry[i nch + c] = ubase_i + the unary length of chunks
 // c' < c of encoder i, where a chunk's length is sum_j ((v_ij >> w_i) + 1), from its bit counts.
-// One workgroup per encoder, nch chunks of kPackChunk values.
+// One workgroup per Rice encoder (i0 + blockIdx.x; the encoders below i0 are Compact), nch chunks of
+// kPackChunk values.
 __global__ __launch_bounds__(kBlock) void k_chunk_carry(const uint32_t* __restrict__ ccnt, uint64_t K, uint64_t nch,
                                                         const uint64_t* __restrict__ enc,
                                                         const uint64_t* __restrict__ ubase,
-                                                        uint64_t* __restrict__ carry) {
+                                                        uint64_t* __restrict__ carry, uint32_t i0) {
   __shared__ uint64_t part[kBlock / 64];
-  const uint32_t tid = threadIdx.x, ln = tid & 63, i = blockIdx.x;
+  const uint32_t tid = threadIdx.x, ln = tid & 63, i = i0 + blockIdx.x;  // Rice encoders i >= i0
   const int w = (int)(enc[i] & 0xFF);
   uint64_t run = ubase[i];
   for (uint64_t c0 = 0; c0 < nch; c0 += kBlock) {
@@ -1095,9 +1096,10 @@ __global__ __launch_bounds__(kBlock) void k_chunk_carry(const uint32_t* __restri
 }
 
 // One workgroup of 1024 threads per chunk c and encoder i: low bits (or Compact values) at base_i + j w_i; for
-// Rice the unary stream of q = v >> w_i (q zeros then a one), whose one for value t = i K + j sits at
-// ubase_i + sum_{j' < j} (q_j' + 1) + q_j, and the position of every 256th one in the select entries
-// (their sub-sample distances are filled in afterwards, from the finished stream).
+// a Rice encoder (i >= ncompact when rice is set) the unary stream of q = v >> w_i (q zeros then a
+// one), whose one for value t = (i - ncompact) K + j sits at ubase_i + sum_{j' < j} (q_j' + 1) + q_j,
+// and the position of every 256th one in the select entries (their sub-sample distances are filled
+// in afterwards, from the finished stream).
 //
 // A chunk's low bits (at most 4096 x 32 bits) and, when they fit, its unary bits (from the chunk's
 // unary start, k_chunk_carry) are assembled in LDS and written out as whole words: plain stores for the
@@ -1135,14 +1137,15 @@ __device__ __forceinline__ void flush_words(const uint64_t* buf, uint64_t* __res
 
 __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __restrict__ pilots, uint64_t K,
                                                               const uint64_t* __restrict__ enc,
-                                                              const uint64_t* __restrict__ carries, uint32_t rice,
-                                                              uint64_t* __restrict__ data, uint64_t* __restrict__ unary,
-                                                              uint64_t* __restrict__ sel) {
+                                                              const uint64_t* __restrict__ carries, uint32_t rice_any,
+                                                              uint32_t ncompact, uint64_t* __restrict__ data,
+                                                              uint64_t* __restrict__ unary, uint64_t* __restrict__ sel) {
   __shared__ uint64_t part[kPackThreads / 64];
   __shared__ uint64_t chunk_total;
   __shared__ uint64_t dbuf[kPackWords];
   __shared__ uint64_t ubuf[kPackWords];
   const uint32_t tid = threadIdx.x, i = blockIdx.y;
+  const bool rice = rice_any && i >= ncompact;
   const uint64_t e = enc[i];
   const uint32_t w = (uint32_t)(e & 0xFF);
   const uint64_t base = e >> 8;
@@ -1201,7 +1204,7 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_values(const uint32_t* __
           atomicOr((unsigned long long*)&ubuf[(pos >> 6) - u_first], 1ULL << (pos & 63));
         else
           atomicOr((unsigned long long*)&unary[pos >> 6], 1ULL << (pos & 63));
-        const uint64_t t_glob = (uint64_t)i * K + jj;
+        const uint64_t t_glob = (uint64_t)(i - ncompact) * K + jj;
         if ((t_glob & (kSelBlock - 1)) == 0) sel[t_glob / kSelBlock] = pos;
         excl = pos + 1;
       }
@@ -1705,6 +1708,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   const uint32_t hmaxb = hinfo[1];
   h->info.max_partition_keys = max_nj;
   h->info.max_bucket_keys = hmaxb;
+  h->info.partition_path = coarse_path ? 0u : 1u;
   if (max_m > kMaxTableSlots)
     return fail(PHOBIC_E_CAPACITY, "a partition needs " + std::to_string(max_m) + " slots; the device path holds " +
                                        std::to_string(kMaxTableSlots));
@@ -1737,6 +1741,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   sa.rb_cap = up4(mb) + 4;
   sa.bl_cap = up4(B);
   sa.cm_cap = (mb + 63) / 64 + 1;
+  sa.max_m = mm;
   sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
   sa.owner = nullptr;
   sa.Kbase = nullptr;
@@ -1792,18 +1797,20 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   const long long* hmm = (const long long*)(hstats + (uint64_t)B * 33);
   const uint32_t* hmax = (const uint32_t*)(hstats + (uint64_t)B * 33 + 2);
   const uint32_t herr = *herrp;
-  if (herr & (1u << PHOBIC_E_DUPLICATE)) return fail(PHOBIC_E_DUPLICATE, "two keys share their 128-bit hash code");
+  if (herr & (1u << PHOBIC_E_DUPLICATE)) return fail(PHOBIC_E_DUPLICATE, "two keys of one bucket share their 64-bit fingerprint");
   if (herr & (1u << PHOBIC_E_PILOT_OVERFLOW))
     return fail(PHOBIC_E_PILOT_OVERFLOW, "a bucket needs a pilot above " + std::to_string(limit));
 
   const bool rice = prm.coding == PHOBIC_IC_RICE;
+  const uint32_t nc = rice ? prm.n_compact : 0;  // mixed coding: encoders below nc are Compact
   std::vector<uint64_t> enc(B), ubase(B);
   uint64_t data_bits = 0, unary_bits = 0;
   for (uint32_t i = 0; i < B; i++) {
-    uint32_t w = rice ? rice_parameter(hsh[(size_t)i * 33], K) : bit_length(hmax[i]);
+    const bool enc_rice = rice && i >= nc;
+    uint32_t w = enc_rice ? rice_parameter(hsh[(size_t)i * 33], K) : bit_length(hmax[i]);
     enc[i] = (data_bits << 8) | w;
     data_bits += (uint64_t)w * K;
-    if (rice) {
+    if (enc_rice) {
       ubase[i] = unary_bits;
       unary_bits += hsh[(size_t)i * 33 + w] + K;
     }
@@ -1834,19 +1841,21 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   uint64_t* carries = nullptr;
   if (rice && nch) {
     PHOBIC_HIP(S.get(&carries, (uint64_t)B * nch));
-    hipLaunchKernelGGL(k_chunk_carry, dim3(B), dim3(kBlock), 0, st, ccnt, K, nch, dhw + kHeaderWords,
-                       dhw + kHeaderWords + B, carries);
+    if (B > nc)
+      hipLaunchKernelGGL(k_chunk_carry, dim3(B - nc), dim3(kBlock), 0, st, ccnt, K, nch, dhw + kHeaderWords,
+                         dhw + kHeaderWords + B, carries, nc);
   }
   if (woff)
     hipLaunchKernelGGL(k_pack_offsets, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, toff, K, R, dmin, woff,
                        img + hdr[kHSecOff]);
   if (nch)
     hipLaunchKernelGGL(k_pack_values, dim3((uint32_t)nch, B), dim3(kPackThreads), 0, st, pilots, K,
-                       img + hdr[kHSecEnc], carries, (uint32_t)rice, img + hdr[kHSecData], img + hdr[kHSecUnary],
-                       img + hdr[kHSecSel]);
-  if (rice && K * B)
-    hipLaunchKernelGGL(k_sel_fill, dim3(grid_for((K * B + kSelBlock - 1) / kSelBlock)), dim3(kBlock), 0, st,
-                       img + hdr[kHSecUnary], img + hdr[kHSecSel], (K * B + kSelBlock - 1) / kSelBlock, K * B);
+                       img + hdr[kHSecEnc], carries, (uint32_t)rice, nc, img + hdr[kHSecData],
+                       img + hdr[kHSecUnary], img + hdr[kHSecSel]);
+  const uint64_t nvals = K * (B - nc);  // ones of the unary stream: the values of the Rice encoders
+  if (rice && nvals)
+    hipLaunchKernelGGL(k_sel_fill, dim3(grid_for((nvals + kSelBlock - 1) / kSelBlock)), dim3(kBlock), 0, st,
+                       img + hdr[kHSecUnary], img + hdr[kHSecSel], (nvals + kSelBlock - 1) / kSelBlock, nvals);
   PHOBIC_HIP(hipGetLastError());
   if (nremap && wremap) {
     uint32_t *fc, *oc, *freeslot;
@@ -2097,7 +2106,8 @@ __global__ __launch_bounds__(256) void k_batch_pack_vals(const uint32_t* __restr
   uint64_t* img = buf + ibase[t];
   uint64_t* data = img + h[kHSecData];
   uint64_t* unary = img + h[kHSecUnary];
-  const bool rice = h[kHCoding] == PHOBIC_IC_RICE;
+  const uint32_t nc = (uint32_t)h[kHNcompact];  // mixed coding: encoders below nc are Compact
+  const bool rice = h[kHCoding] == PHOBIC_IC_RICE && i >= nc;
   const uint64_t e = encw[item];
   const uint32_t w = (uint32_t)(e & 0xFF);
   const uint64_t base = e >> 8;
@@ -2136,7 +2146,7 @@ __global__ __launch_bounds__(256) void k_batch_pack_vals(const uint32_t* __restr
         atomicOr((unsigned long long*)&ubuf[(pos >> 6) - u_first], 1ULL << (pos & 63));
       else
         atomicOr((unsigned long long*)&unary[pos >> 6], 1ULL << (pos & 63));
-      const uint64_t tg = (uint64_t)i * K + j;
+      const uint64_t tg = (uint64_t)(i - nc) * K + j;
       if ((tg & (kSelBlock - 1)) == 0) img[h[kHSecSel] + tg / kSelBlock] = pos;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -2156,7 +2166,7 @@ __global__ __launch_bounds__(256) void k_batch_sel_fill(const BatchDesc* __restr
   const uint32_t t = blockIdx.x;
   const uint64_t* h = hdrs + (uint64_t)t * kHeaderWords;
   uint64_t* img = buf + ibase[t];
-  const uint64_t nvals = d[t].K * B, nsel = (nvals + kSelBlock - 1) / kSelBlock;
+  const uint64_t nvals = d[t].K * (B - h[kHNcompact]), nsel = (nvals + kSelBlock - 1) / kSelBlock;
   for (uint64_t s = threadIdx.x; s < nsel; s += blockDim.x) sel_fill_entry(img + h[kHSecUnary], img + h[kHSecSel], s, nvals);
 }
 
@@ -2320,6 +2330,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   sa.rb_cap = up4(mb) + 4;
   sa.bl_cap = up4(B);
   sa.cm_cap = (mb + 63) / 64 + 1;
+  sa.max_m = mm;
   sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
   sa.owner = owner;
   sa.Kbase = d_Kbase;
@@ -2361,12 +2372,14 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
                 "MPHF " + std::to_string(t) + (dup ? ": two keys share their hash code" : ": pilot overflow"));
   }
   const bool rice = prm.coding == PHOBIC_IC_RICE;
+  const uint32_t ncomp = rice ? prm.n_compact : 0;  // mixed coding: encoders below it are Compact
   uint8_t* hw;  // pinned
   uint64_t* hub;
   PHOBIC_HIP(S.host(&hw, items));
   PHOBIC_HIP(S.host(&hub, items));
   parallel_for(items, [&](uint64_t it) {
-    hw[it] = (uint8_t)(rice ? rice_parameter(hsum[it], desc[it / B].K) : bit_length(hmx[it]));
+    const bool enc_rice = rice && it % B >= ncomp;
+    hw[it] = (uint8_t)(enc_rice ? rice_parameter(hsum[it], desc[it / B].K) : bit_length(hmx[it]));
     hub[it] = 0;
   });
   if (rice) {
@@ -2392,7 +2405,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
       encw[it] = (data_bits << 8) | hw[it];
       data_bits += (uint64_t)hw[it] * desc[t].K;
       ubase[it] = unary_bits;
-      unary_bits += hub[it];
+      if (i >= ncomp) unary_bits += hub[it];  // Compact encoders have no unary part
     }
     if (rice && unary_bits > 0xFFFFFFFFULL) return fail(PHOBIC_E_CAPACITY, "a unary stream exceeds 2^32 bits");
     const long long dmin = hmm[2 * t], dmax = hmm[2 * t + 1];

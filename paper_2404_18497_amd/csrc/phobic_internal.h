@@ -35,7 +35,7 @@ constexpr uint32_t kSelRelNone = 1023;
 enum : uint32_t {
   kHMagic = 0, kHN, kHK, kHB, kHP, kHLambda, kHAlpha, kHCoding, kHSeed, kHTotal, kHDmin, kHWoff,
   kHSecOff, kHSecEnc, kHSecData, kHSecUnary, kHSecSel, kHSecRemap, kHWremap, kHNremap, kHUbits,
-  kHWords, kHR, kHSpare, kHeaderWords
+  kHWords, kHR, kHNcompact, kHeaderWords
 };
 constexpr uint64_t kMagic = 0x33304349424F4850ULL;  // "PHOBIC03"
 
@@ -48,6 +48,7 @@ struct QueryArgs {
   uint64_t sec_off, sec_enc, sec_data, sec_unary, sec_sel, sec_remap;
   uint64_t seed;
   uint32_t B, woff, coding, wremap;
+  uint32_t ncompact;  // Rice images: encoders below it are Compact (mixed interleaved coding)
 };
 
 }  // namespace phobic

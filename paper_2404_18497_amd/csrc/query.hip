@@ -102,8 +102,8 @@ __device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, 
   uint64_t r0, r1;
   offset_pair(offs, j, a.woff, r0, r1);
   uint64_t p = get_bits(a.img + a.sec_data, (e >> 8) + j * w, w);
-  if (a.coding == PHOBIC_IC_RICE) {
-    const uint64_t q = unary_high(a.img + a.sec_unary, a.img + a.sec_sel, (uint64_t)i * a.K + j);
+  if (a.coding == PHOBIC_IC_RICE && i >= a.ncompact) {  // encoders below ncompact are Compact
+    const uint64_t q = unary_high(a.img + a.sec_unary, a.img + a.sec_sel, (uint64_t)(i - a.ncompact) * a.K + j);
     p |= q << w;
   }
   const uint64_t o0 = expected_offset(j, a.R) + (uint64_t)a.dmin + r0;
@@ -141,16 +141,20 @@ __device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (
   }
 #pragma unroll
   for (int q = 0; q < kN; q++) e[q] = a.img[a.sec_enc + i[q]];
-  // offsets, low bits and select samples: independent of each other
+  // offsets, low bits and select samples: independent of each other.  A lookup whose encoder is
+  // Rice (u) reads the unary stream at its value t = (i - ncompact) K + j; one of a Compact encoder
+  // (all of a Compact image, the first ncompact of a mixed one) is done with its field.
   uint64_t t[kN], ta[kN], sample[kN];
+  bool u[kN];
 #pragma unroll
   for (int q = 0; q < kN; q++) {
     offset_pair(offs, j[q], a.woff, r0[q], r1[q]);
     const uint32_t w = (uint32_t)(e[q] & 0xFF);
     p[q] = get_bits(a.img + a.sec_data, (e[q] >> 8) + j[q] * w, w);
-    t[q] = (uint64_t)i[q] * a.K + j[q];
+    u[q] = rice && i[q] >= a.ncompact;
+    t[q] = u[q] ? (uint64_t)(i[q] - a.ncompact) * a.K + j[q] : 0;
     ta[q] = t[q] ? t[q] - 1 : 0;
-    sample[q] = rice ? sel[ta[q] / kSelBlock] : 0;
+    sample[q] = u[q] ? sel[ta[q] / kSelBlock] : 0;
   }
   if (rice) {
     uint64_t word[kN], bits[kN], prev[kN];
@@ -160,7 +164,7 @@ __device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (
     for (int q = 0; q < kN; q++) {
       const uint64_t start = sel_start(sample[q], ta[q], r[q]);
       word[q] = t[q] ? start >> 6 : 0;
-      bits[q] = un[word[q]];
+      bits[q] = u[q] ? un[word[q]] : 1;  // a Compact lookup keeps a set bit: no reads below
       if (t[q]) bits[q] &= ~0ULL << (start & 63);
       found[q] = t[q] == 0;
     }
@@ -205,7 +209,7 @@ __device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (
 #pragma unroll
     for (int q = 0; q < kN; q++) {
       const uint64_t cur = word[q] * 64 + (uint32_t)(__ffsll((long long)bits[q]) - 1);
-      p[q] |= (cur - prev[q] - 1) << (uint32_t)(e[q] & 0xFF);
+      if (u[q]) p[q] |= (cur - prev[q] - 1) << (uint32_t)(e[q] & 0xFF);
     }
   }
 #pragma unroll

@@ -142,6 +142,14 @@ __device__ __forceinline__ void note_failure(const SearchArgs& a, uint64_t j, ui
 }
 
 // Places every bucket of partition j (global index).  Uniform across the wavefront.
+//
+// The buckets come in processing order, sizes non-increasing, so they fall into three runs that get
+// their own loops: big buckets (more than kSmallBucket keys; positions checked for repeats before
+// the scan), small ones (2 .. kSmallBucket keys; a repeat shows while marking) and single keys (no
+// repeat possible; seed 0 always finds a free slot).  Seed-0 positions come from the fingerprint
+// windows, hashed once per window instead of once per bucket.  kMulti: some table of the launch
+// has more than 4096 slots, so a displacement scan may need several passes.
+template <bool kMulti>
 __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, uint32_t lane) {
   uint32_t* scr = F2 + a.f2_words;
   uint32_t* rbuf = scr + a.scr_words;
@@ -168,103 +176,180 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   const uint64_t acc_first = dl0 < m ? (m - dl0 >= 64 ? ~0ULL : ((1ULL << (m - dl0)) - 1)) : 0ULL;
   const uint32_t loff_first = dl0 < m ? (dl0 >> 3) : 0u;
 
-  // Fingerprints arrive through a sliding window: lane l of win0 holds key wbase + l of the partition
-  // (processing order), win1 the next 64.  The keys of consecutive buckets are consecutive, so one
-  // load serves many small buckets, and the next window is in flight while the current one is used.
   const uint32_t nj = uniform((uint32_t)(a.off[j + 1] - kb));
   // s m > limit exactly when s > floor(limit / m); limit < 2^32, so every seed tried fits 32 bits.
   // The cap at 2^32 - 2 (which only m = 1 reaches, where the one key takes seed 0) keeps s + 1 from
   // wrapping.
   const uint32_t smax = m ? (uint32_t)min<uint64_t>(a.limit / m, 0xFFFFFFFEULL) : 0u;
   const uint32_t dlast = m ? (uint32_t)(a.limit - smax * m) : 0;  // largest d allowed with s = smax
+
+  // Fingerprints arrive through a sliding window: lane l of win0 holds key wbase + l of the partition
+  // (processing order), win1 the next 64.  The keys of consecutive buckets are consecutive, so one
+  // load serves many small buckets, and the next window is in flight while the current one is used.
+  // p0w0 holds win0's positions under seed 0; p0w1 win1's once a bucket has needed them (p1).
   uint32_t wbase = 0, o = 0;  // o: first key of the current bucket
   uint64_t win0 = lane < nj ? a.fp[kb + lane] : 0;
   uint64_t win1 = 64 + lane < nj ? a.fp[kb + 64 + lane] : 0;
-  bool overflow = false;
-  for (uint32_t r = 0; r < nb; r++) {
-    const uint32_t e = uniform(bl[r]);
-    const uint32_t bid = e & 0xFFFF, sz = e >> 16;
-    const uint64_t* keys = a.fp + kb + o;
+  uint32_t p0w0 = pos_hash(win0, kPhi64, m), p0w1 = 0;
+  bool p1 = false;
+  // Moves the windows so that the bucket starting at key o lies in them (its first 64 keys).
+  auto advance = [&]() {
     if (o >= wbase + 64) {
       if (o < wbase + 128) {
         win0 = win1;
+        p0w0 = p1 ? p0w1 : pos_hash(win0, kPhi64, m);
         wbase += 64;
       } else {  // past both windows (after a big bucket)
         wbase = o;
         win0 = wbase + lane < nj ? a.fp[kb + wbase + lane] : 0;
+        p0w0 = pos_hash(win0, kPhi64, m);
       }
       win1 = wbase + 64 + lane < nj ? a.fp[kb + wbase + 64 + lane] : 0;
+      p1 = false;
     }
-    // key k < 64 of the bucket is window entry o - wbase + k < 128
+  };
+  // key o + lane's fingerprint (lanes past the bucket get a neighbour's, unused)
+  auto key_fp = [&]() -> uint64_t {
     const uint32_t widx = o - wbase + lane;
     const uint64_t f0a = __shfl(win0, (int)(widx & 63)), f0b = __shfl(win1, (int)(widx & 63));
-    const uint64_t f0 = widx < 64 ? f0a : f0b;
-    o += sz;
-    const bool big = sz > kSmallBucket;
-    const uint32_t szp = (sz + 3) & ~3u;
-
-    if (overflow) {  // the partition has failed: only look for equal fingerprints
-      bucket_positions(rbuf, keys, f0, sz, kPhi64, m, lane);
-      if (positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
-        if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
-        return;
-      }
-      continue;
+    return widx < 64 ? f0a : f0b;
+  };
+  // key o + lane's position under seed 0, for a bucket of sz keys
+  auto key_p0 = [&](uint32_t sz) -> uint32_t {
+    if (o - wbase + sz > 64 && !p1) {  // the bucket reaches into win1
+      p0w1 = pos_hash(win1, kPhi64, m);
+      p1 = true;
     }
+    const uint32_t widx = o - wbase + lane;
+    const uint32_t pa = __shfl(p0w0, (int)(widx & 63)), pb = __shfl(p0w1, (int)(widx & 63));
+    return widx < 64 ? pa : pb;
+  };
 
+  // displacement scan: the lowest d such that every key's slot (r + d) mod m is free, for the szp
+  // encoded positions in rbuf.  A pass covers 4096 displacements from d0 (acc: this lane's window
+  // bits below m, loff: its byte offset); the first pass covers every m up to 4096, further passes
+  // (kMulti) the larger ones.  ~0 when no displacement works.
+  auto scan = [&](uint32_t szp) -> uint32_t {
+    uint32_t d_found = 0xFFFFFFFFu;
+    auto scan_pass = [&](uint32_t d0, uint64_t acc, uint32_t loff) {
+      for (uint32_t k = 0; k < szp; k += 4) {
+        const uint4 e4 = *(const uint4*)(rbuf + k);
+        const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const uint32_t* wp = (const uint32_t*)(F2b + (ev[t] >> 16) + loff);
+          const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
+          acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, ev[t]) << 32) |
+                 __builtin_amdgcn_alignbit(w1, w0, ev[t]);
+        }
+        if (__ballot(acc != 0) == 0) break;
+      }
+      const uint64_t bal = __ballot(acc != 0);
+      if (bal) {
+        const uint32_t L = (uint32_t)(__ffsll((long long)bal) - 1);
+        const uint64_t accL = lane_value64(acc, L);
+        d_found = d0 + L * 64 + (uint32_t)(__ffsll((long long)accL) - 1);
+      }
+    };
+    scan_pass(0, acc_first, loff_first);
+    if (kMulti) {
+      for (uint32_t d0 = 4096; d_found == 0xFFFFFFFFu && d0 < m; d0 += 4096) {
+        const uint32_t dl = d0 + dl0;
+        const bool act = dl < m;
+        scan_pass(d0, act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL, act ? (dl >> 3) : 0u);
+      }
+    }
+    return d_found;
+  };
+
+  bool overflow = false;
+  uint32_t r = 0;
+  const uint64_t* keys = a.fp + kb;  // the current bucket's keys
+
+  // ---- big buckets: every seed's positions are checked for repeats first --------------------
+  for (; r < nb; r++) {
+    const uint32_t e = uniform(bl[r]);
+    const uint32_t bid = e & 0xFFFF, sz = e >> 16;
+    if (sz <= kSmallBucket) break;
+    advance();
+    keys = a.fp + kb + o;
+    const uint64_t f0 = key_fp();
+    o += sz;
     uint64_t wseed = kPhi64;  // the seed's Weyl value (s + 1) phi, kept as a running sum
     for (uint32_t s = 0;; s++, wseed += kPhi64) {
       if (s > smax) {  // every pilot s m + d of this seed exceeds the limit
         overflow = true;
         break;
       }
-      const uint32_t rmine = bucket_positions(rbuf, keys, f0, sz, wseed, m, lane);
-      if (big && positions_repeat(scr, rbuf, sz, cm, lane)) {
+      bucket_positions(rbuf, keys, f0, sz, wseed, m, lane);
+      if (positions_repeat(scr, rbuf, sz, cm, lane)) {
         if (s == 0 && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
           if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
           return;
         }
         continue;
       }
-
-      // displacement scan: the lowest d such that every key's slot (r + d) mod m is free.  A pass
-      // covers 4096 displacements from d0 (acc: this lane's window bits below m, loff: its byte
-      // offset); the first pass covers every m up to 4096, the loop after it the larger ones.
-      uint32_t d_found = 0xFFFFFFFFu;
-      auto scan_pass = [&](uint32_t d0, uint64_t acc, uint32_t loff) {
-        for (uint32_t k = 0; k < szp; k += 4) {
-          const uint4 e4 = *(const uint4*)(rbuf + k);
-          const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
-#pragma unroll
-          for (int t = 0; t < 4; t++) {
-            const uint32_t* wp = (const uint32_t*)(F2b + (ev[t] >> 16) + loff);
-            const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
-            acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, ev[t]) << 32) |
-                   __builtin_amdgcn_alignbit(w1, w0, ev[t]);
-          }
-          if (__ballot(acc != 0) == 0) break;
-        }
-        const uint64_t bal = __ballot(acc != 0);
-        if (bal) {
-          const uint32_t L = (uint32_t)(__ffsll((long long)bal) - 1);
-          const uint64_t accL = lane_value64(acc, L);
-          d_found = d0 + L * 64 + (uint32_t)(__ffsll((long long)accL) - 1);
-        }
-      };
-      scan_pass(0, acc_first, loff_first);
-      for (uint32_t d0 = 4096; d_found == 0xFFFFFFFFu && d0 < m; d0 += 4096) {
-        const uint32_t dl = d0 + dl0;
-        const bool act = dl < m;
-        scan_pass(d0, act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL, act ? (dl >> 3) : 0u);
-      }
+      const uint32_t d_found = scan((sz + 3) & ~3u);
       if (d_found == 0xFFFFFFFFu) continue;
-      const uint64_t p = (uint64_t)s * m + d_found;
       if (s == smax && d_found > dlast) {  // p > limit, with s <= smax
         overflow = true;
         break;
       }
-      // mark the slots; a small bucket discovers here whether two of its keys share a slot
-      if (!big) {
+      for (uint32_t k = lane; k < sz; k += 64) {
+        uint32_t t = dec_pos(rbuf[k]) + d_found;
+        if (t >= m) t -= m;
+        atomicAnd(&F2[t >> 5], ~(1u << (t & 31)));
+        const uint32_t t2 = t + m;
+        atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
+      }
+      if (lane == 0) pil[bid] = s * m + d_found;
+      wave_sync();
+      break;
+    }
+    if (overflow) {
+      r++;
+      break;
+    }
+  }
+
+  // ---- small buckets (2 .. kSmallBucket keys): a repeat shows while marking ------------------
+  if (!overflow) {
+    for (; r < nb; r++) {
+      const uint32_t e = uniform(bl[r]);
+      const uint32_t bid = e & 0xFFFF, sz = e >> 16;
+      if (sz < 2) break;
+      advance();
+      keys = a.fp + kb + o;
+      const uint64_t f0 = key_fp();
+      const uint32_t p0 = key_p0(sz);
+      o += sz;
+      const uint32_t szp = (sz + 3) & ~3u;
+      uint64_t wseed = kPhi64;
+      for (uint32_t s = 0;; s++, wseed += kPhi64) {
+        if (s > smax) {
+          overflow = true;
+          break;
+        }
+        // positions: seed 0 from the window, later seeds hashed; padded with the last entry
+        const uint32_t rmine = s == 0 ? p0 : pos_hash(f0, wseed, m);
+        const uint32_t last = __builtin_amdgcn_readlane(rmine, sz - 1);
+        if (lane < szp) rbuf[lane] = enc_pos(lane < sz ? rmine : last);
+        wave_sync();
+        const uint32_t d_found = scan(szp);
+        // Without an admissible displacement at seed 0 the bucket is checked for equal keys here,
+        // so that they are reported as such and not as a pilot overflow.
+        const bool unplaced0 = d_found == 0xFFFFFFFFu || (s == smax && d_found > dlast);
+        if (unplaced0 && s == 0 && positions_repeat(scr, rbuf, sz, cm, lane) &&
+            equal_fingerprints(keys, rbuf, sz, cm, lane)) {
+          if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
+          return;
+        }
+        if (d_found == 0xFFFFFFFFu) continue;
+        if (s == smax && d_found > dlast) {
+          overflow = true;
+          break;
+        }
+        // mark the slots; two keys on one slot show as a slot this bucket has already cleared
         bool mine = false;
         uint32_t t = rmine + d_found;
         if (t >= m) t -= m;
@@ -283,21 +368,76 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
           const uint32_t t2 = t + m;
           atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
         }
-      } else {
-        for (uint32_t k = lane; k < sz; k += 64) {
-          uint32_t t = dec_pos(rbuf[k]) + d_found;
-          if (t >= m) t -= m;
-          atomicAnd(&F2[t >> 5], ~(1u << (t & 31)));
-          const uint32_t t2 = t + m;
-          atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
-        }
+        if (lane == 0) pil[bid] = s * m + d_found;
+        wave_sync();
+        break;
       }
-      if (lane == 0) pil[bid] = (uint32_t)p;
-      wave_sync();
-      break;
+      if (overflow) {
+        r++;
+        break;
+      }
     }
   }
-  if (overflow) {
+
+  // ---- single keys: seed 0, the first free slot at or after the key's position ---------------
+  if (!overflow) {
+    for (; r < nb; r++) {
+      const uint32_t bid = uniform(bl[r]) & 0xFFFF;
+      advance();
+      const uint32_t r0 = __builtin_amdgcn_readlane(p0w0, o - wbase);
+      o += 1;
+      const uint32_t ebase = ((r0 >> 5) << 2);  // byte offset of the word holding bit r0
+      uint32_t d_found = 0xFFFFFFFFu;
+      auto single_pass = [&](uint32_t d0, uint64_t acc, uint32_t loff) {
+        const uint32_t* wp = (const uint32_t*)(F2b + ebase + loff);
+        const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
+        acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, r0) << 32) | __builtin_amdgcn_alignbit(w1, w0, r0);
+        const uint64_t bal = __ballot(acc != 0);
+        if (bal) {
+          const uint32_t L = (uint32_t)(__ffsll((long long)bal) - 1);
+          const uint64_t accL = lane_value64(acc, L);
+          d_found = d0 + L * 64 + (uint32_t)(__ffsll((long long)accL) - 1);
+        }
+      };
+      single_pass(0, acc_first, loff_first);
+      if (kMulti) {
+        for (uint32_t d0 = 4096; d_found == 0xFFFFFFFFu && d0 < m; d0 += 4096) {
+          const uint32_t dl = d0 + dl0;
+          const bool act = dl < m;
+          single_pass(d0, act ? (m - dl >= 64 ? ~0ULL : ((1ULL << (m - dl)) - 1)) : 0ULL, act ? (dl >> 3) : 0u);
+        }
+      }
+      // a free slot always exists (fewer keys placed than slots), so d_found < m
+      if (smax == 0 && d_found > dlast) {  // the pilot d exceeds the limit
+        overflow = true;
+        r++;
+        break;
+      }
+      uint32_t t = r0 + d_found;
+      if (t >= m) t -= m;
+      if (lane < 2) {  // lane 0 the slot's bit, lane 1 its copy m bits further
+        const uint32_t tt = t + lane * m;
+        atomicAnd(&F2[tt >> 5], ~(1u << (tt & 31)));
+        if (lane == 0) pil[bid] = d_found;
+      }
+      wave_sync();
+    }
+  }
+
+  if (overflow) {  // the partition has failed: only look for equal fingerprints in the rest
+    for (; r < nb; r++) {
+      const uint32_t sz = uniform(bl[r]) >> 16;
+      advance();
+      keys = a.fp + kb + o;
+      const uint64_t f0 = key_fp();
+      o += sz;
+      if (sz < 2) continue;
+      bucket_positions(rbuf, keys, f0, sz, kPhi64, m, lane);
+      if (positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
+        if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
+        return;
+      }
+    }
     if (lane == 0) note_failure(a, j, PHOBIC_E_PILOT_OVERFLOW);
     return;
   }
@@ -323,17 +463,17 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
 }
 
 // One wavefront per partition.
-template <int kWaves>
+template <int kWaves, bool kMulti>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search(SearchArgs a) {
   extern __shared__ __align__(16) uint32_t lds32[];
   const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const uint64_t j = (uint64_t)blockIdx.x * kWaves + wave;
   if (j >= a.K) return;
-  search_partition(a, j, lds32 + (size_t)wave * (a.wave_lds / 4), lane);
+  search_partition<kMulti>(a, j, lds32 + (size_t)wave * (a.wave_lds / 4), lane);
 }
 
 // Persistent: every wavefront takes `grab` partitions at a time from the queue until none is left.
-template <int kWaves>
+template <int kWaves, bool kMulti>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search_persistent(SearchArgs a) {
   extern __shared__ __align__(16) uint32_t lds32[];
   const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -345,7 +485,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(8, 
     if (item >= a.K) break;
     const uint64_t end = min((uint64_t)item + a.grab, a.K);
     for (uint64_t j = item; j < end; j++) {
-      search_partition(a, j, F2, lane);
+      search_partition<kMulti>(a, j, F2, lane);
       wave_sync();
     }
   }
@@ -362,14 +502,14 @@ phobic_search_config search_config() {
   return g_cfg;
 }
 
-template <int W>
+template <int W, bool kMulti>
 hipError_t launch_search_w(SearchArgs& sa, uint64_t items, const phobic_search_config& cfg, hipStream_t st,
                            unsigned long long* queue) {
   const size_t lds = (size_t)sa.wave_lds * W;
   if (lds > 160 * 1024) return hipErrorInvalidConfiguration;
   if (cfg.groups_per_cu == 0) {
     sa.queue = nullptr;
-    hipLaunchKernelGGL(k_search<W>, dim3((uint32_t)((items + W - 1) / W)), dim3(64 * W), lds, st, sa);
+    hipLaunchKernelGGL((k_search<W, kMulti>), dim3((uint32_t)((items + W - 1) / W)), dim3(64 * W), lds, st, sa);
     return hipGetLastError();
   }
   int dev = 0, cus = 0;
@@ -380,22 +520,30 @@ hipError_t launch_search_w(SearchArgs& sa, uint64_t items, const phobic_search_c
   sa.grab = std::max<uint32_t>(1, cfg.items_per_grab);
   hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, queue);
   const uint64_t groups = std::min<uint64_t>((uint64_t)cus * cfg.groups_per_cu, (items + W - 1) / W);
-  hipLaunchKernelGGL(k_search_persistent<W>, dim3((uint32_t)std::max<uint64_t>(groups, 1)), dim3(64 * W), lds, st,
-                     sa);
+  hipLaunchKernelGGL((k_search_persistent<W, kMulti>), dim3((uint32_t)std::max<uint64_t>(groups, 1)), dim3(64 * W),
+                     lds, st, sa);
   return hipGetLastError();
 }
 
 // Launches the search over `items` partitions (sa.K) with the configured shape.
 }  // namespace
 
+template <bool kMulti>
+hipError_t launch_search_m(SearchArgs& sa, uint64_t items, const phobic_search_config& cfg, hipStream_t st,
+                           unsigned long long* queue) {
+  switch (cfg.waves_per_group) {
+    case 1: return launch_search_w<1, kMulti>(sa, items, cfg, st, queue);
+    case 2: return launch_search_w<2, kMulti>(sa, items, cfg, st, queue);
+    case 8: return launch_search_w<8, kMulti>(sa, items, cfg, st, queue);
+    default: return launch_search_w<4, kMulti>(sa, items, cfg, st, queue);
+  }
+}
+
 hipError_t launch_search(SearchArgs& sa, uint64_t items, hipStream_t st, unsigned long long* queue) {
   const phobic_search_config cfg = search_config();
-  switch (cfg.waves_per_group) {
-    case 1: return launch_search_w<1>(sa, items, cfg, st, queue);
-    case 2: return launch_search_w<2>(sa, items, cfg, st, queue);
-    case 8: return launch_search_w<8>(sa, items, cfg, st, queue);
-    default: return launch_search_w<4>(sa, items, cfg, st, queue);
-  }
+  // tables of more than 4096 slots need scans of several passes
+  return sa.max_m > 4096 ? launch_search_m<true>(sa, items, cfg, st, queue)
+                         : launch_search_m<false>(sa, items, cfg, st, queue);
 }
 
 }  // namespace phobic

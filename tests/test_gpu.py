@@ -33,10 +33,11 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
 
 
-def _both(torch, keys, lam=7.0, P=2500, alpha=(1, 1), coding="rice", seed=0x5EED, pilot_limit=0):
+def _both(torch, keys, lam=7.0, P=2500, alpha=(1, 1), coding="rice", seed=0x5EED, pilot_limit=0, n_compact=0):
     gp = binding.params(partition_size=P, lam=lam, alpha=alpha, coding=coding, hash_seed=seed, pilot_limit=pilot_limit,
-                        keep_pilots=True)
-    rp = oracle.params(partition_size=P, lam=lam, alpha=alpha, coding=coding, hash_seed=seed, pilot_limit=pilot_limit)
+                        keep_pilots=True, n_compact=n_compact)
+    rp = oracle.params(partition_size=P, lam=lam, alpha=alpha, coding=coding, hash_seed=seed, pilot_limit=pilot_limit,
+                       n_compact=n_compact)
     g = binding.build_u64(_dev(torch, keys), gp)
     r = oracle.build_u64(keys, rp, threads=8)
     return g, r
@@ -85,12 +86,60 @@ def test_config1_full_parity(torch, coding):
     _check_same(torch, g, r, keys[synth.permutation(keys.size, 11)])
 
 
-@pytest.mark.parametrize("lam", [1.5, 3.0, 5.0, 9.0])
+@pytest.mark.parametrize("lam", [1.5, 3.0, 5.0, 9.0, 11.0, 13.0])
 def test_lambda_sweep_parity(torch, lam):
     keys = synth.u64_keys(200_000, 3)
     _say("lambda", lam)
     g, r = _both(torch, keys, lam=lam)
     _check_same(torch, g, r, keys)
+
+
+def test_lambda14_parity(torch):
+    # the search-dominated end of Table 1's range: about 3e5 slot probes per key
+    keys = synth.u64_keys(100_000, 14)
+    _say("lambda", 14)
+    g, r = _both(torch, keys, lam=14.0)
+    _check_same(torch, g, r, keys)
+
+
+@pytest.mark.parametrize("c", [0, 1, 16, 179, 358])
+def test_mixed_coding_parity(torch, c):
+    """Mixed interleaved coding (Sec. 4.1): the first c of B = 358 encoders Compact, the rest Rice;
+    c = 0 is the Rice image, c = B an image with an empty unary stream."""
+    keys = synth.u64_keys(1_000_000, 1)
+    _say("mixed coding", c)
+    g, r = _both(torch, keys, n_compact=c)
+    assert int(g.serialize()[23]) == c
+    _check_same(torch, g, r, keys[synth.permutation(keys.size, 11)])
+
+
+@pytest.mark.parametrize("kind", ["u64", "str"])
+def test_general_partitioner_parity(torch, kind):
+    """More coarse bins than one histogram holds send a build through the general partitioner (per-key
+    global atomics): 1M keys (or strings) at P = 8, lambda 4 give K = 125000 partitions in 15625 bins
+    of eight. Offsets, pilots, image and queries against the oracle."""
+    _say("general partitioner", kind)
+    if kind == "u64":
+        keys = synth.u64_keys(1_000_000, 31)
+        g, r = _both(torch, keys, lam=4.0, P=8)
+        assert g.build_info()["partition_path"] == 1
+        _check_same(torch, g, r, keys)
+        offs, _ = binding.partition_u64(_dev(torch, keys), binding.params(partition_size=8, lam=4.0))
+        assert np.array_equal(offs.cpu().numpy().view(np.uint64), r.offsets())
+    else:
+        buf, offs = synth.ascii_strings(1_000_000, 32)
+        for alpha in [(1, 1), (9, 10)]:
+            gp = binding.params(partition_size=8, lam=4.0, alpha=alpha, keep_pilots=True)
+            g = binding.build_str(torch.from_numpy(buf).cuda(), _dev(torch, offs), gp)
+            r = oracle.build_str(buf, offs, oracle.params(partition_size=8, lam=4.0, alpha=alpha), threads=8)
+            assert g.build_info()["partition_path"] == 1
+            assert np.array_equal(g.pilots(), r.pilots())
+            assert np.array_equal(g.serialize(), r.image())
+            pos = g.query_str(torch.from_numpy(buf).cuda(), _dev(torch, offs)).cpu().numpy().view(np.uint64)
+            assert np.array_equal(pos, r.query_str(buf, offs))
+    # the default shape stays on the coarse-bin path
+    small = synth.u64_keys(10_000, 33)
+    assert binding.build_u64(_dev(torch, small), binding.params()).build_info()["partition_path"] == 0
 
 
 def _sel_overflows(img):
@@ -161,6 +210,14 @@ def test_errors(torch):
     with pytest.raises(binding.PhobicError) as e:
         binding.build_u64(_dev(torch, keys), binding.params(lam=9.0, pilot_limit=3))
     assert e.value.code == binding.E_PILOT_OVERFLOW
+    # equal keys stay a duplicate when no pilot fits the limit (seed 0 finds no admissible displacement)
+    for lim in (3, 1):
+        with pytest.raises(binding.PhobicError) as e:
+            binding.build_u64(_dev(torch, dup), binding.params(lam=9.0, pilot_limit=lim))
+        assert e.value.code == binding.E_DUPLICATE
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.build_u64(dup, oracle.params(lam=9.0, pilot_limit=lim))
+        assert e.value.code == binding.E_DUPLICATE
     with pytest.raises(binding.PhobicError) as e:
         binding.build_u64(_dev(torch, keys), binding.params(lam=0.5, partition_size=2500))
     assert e.value.code == binding.E_CAPACITY
@@ -223,29 +280,46 @@ def _golden_100m(lam):
     return json.load(open(path))["counters"][f"{lam:g}"]
 
 
-@pytest.mark.parametrize("lam,coding", [(7.0, "rice"), (5.0, "rice"), (9.0, "rice"), (7.0, "compact")])
-def test_full_size_100m(torch, keys_100m, lam, coding):
-    """The benchmark workload (100M keys, P 2500) at lambda 5, 7 and 9: the whole device image
-    (Rice) and the whole pilot array hash to the values the oracle's own 100M-key build produced
-    (tests/golden, written by a script that calls only the oracle); bijection over all keys; sampled
-    queries against the oracle reading the device image; at lambda 7 also the benchmark's 100M
-    lookups in its launch configuration (batches of 1M on two streams) against the positions above,
-    pilots of sampled partitions against the oracle's search on the same codes, and the encoder
-    parameters."""
+def _golden_full(name):
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "full_size_images.json")
+    return json.load(open(path))[name]
+
+
+def _sha(a):
     import hashlib
 
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("lam,coding,nc", [(7.0, "rice", 0), (5.0, "rice", 0), (9.0, "rice", 0), (7.0, "compact", 0),
+                                           (7.0, "rice", 64)])
+def test_full_size_100m(torch, keys_100m, lam, coding, nc):
+    """The benchmark workload (100M keys, P 2500) at lambda 5, 7 and 9 (Rice), Compact and mixed
+    coding (first 64 encoders Compact) at lambda 7: the whole device image and the whole pilot array
+    hash to the values the oracle's own 100M-key builds produced (tests/golden, written by scripts that
+    call only the oracle); bijection over all keys; sampled queries against the oracle reading the
+    device image; at lambda 7 (Rice) also the benchmark's 100M lookups in its launch configuration
+    (batches of 1M on two streams) against the positions above, pilots of sampled partitions against
+    the oracle's search on the same codes, and the encoder parameters."""
     keys, dk = keys_100m
     n = keys.size
     golden = _golden_100m(lam)
-    prm = binding.params(lam=lam, coding=coding, keep_pilots=True)
-    _say("100M keys: build", lam, coding)
+    prm = binding.params(lam=lam, coding=coding, keep_pilots=True, n_compact=nc)
+    _say("100M keys: build", lam, coding, nc)
     g = binding.build_u64(dk, prm)
     pil = g.pilots()
-    assert hashlib.sha256(np.ascontiguousarray(pil, dtype=np.uint32).tobytes()).hexdigest() == golden["pilots_sha256"]
+    assert _sha(np.asarray(pil, dtype=np.uint32)) == golden["pilots_sha256"]
     img = g.serialize()
-    if coding == "rice":
-        assert hashlib.sha256(img.tobytes()).hexdigest() == golden["image_sha256_rice"]
+    if coding == "rice" and nc == 0:
+        assert _sha(img) == golden["image_sha256_rice"]
         assert g.size_bits() / n == golden["bits_per_key_rice"]
+    else:
+        full = _golden_full("u64_100m_l7_compact" if coding == "compact" else f"u64_100m_l7_mixed{nc}")
+        assert _sha(img) == full["image_sha256"] and full["pilots_sha256"] == golden["pilots_sha256"]
+        assert g.size_bits() / n == full["bits_per_key"]
     _say("100M keys: query all")
     pos = g.query_u64(dk)
     cnt = torch.zeros(n, dtype=torch.int32, device=dk.device)
@@ -257,7 +331,7 @@ def test_full_size_100m(torch, keys_100m, lam, coding):
     sample = rng.integers(0, n, 200_000)
     got = pos[torch.from_numpy(sample).cuda()].cpu().numpy().view(np.uint64)
     assert np.array_equal(oracle.query_image_u64(img, keys[sample]), got)
-    if lam != 7.0 or coding != "rice":
+    if lam != 7.0 or coding != "rice" or nc:
         return
     _say("100M keys: the benchmark's lookups in batches of 1M on two streams")
     qidx = torch.from_numpy(synth.query_indices(n, n, 2)).cuda()
@@ -295,10 +369,11 @@ def strings_100m():
 
 
 @pytest.mark.parametrize("alpha", [(1, 1), (99, 100)])
-def test_full_size_strings_100m_sampled(torch, strings_100m, alpha):
+def test_full_size_strings_100m(torch, strings_100m, alpha):
     """The 100M-string workload (lengths 10-50, [a-z0-9], lambda 7) with alpha 1 and 0.99: bijection
     over all strings; pilots of sampled partitions against the oracle's search on the oracle's hashes
-    of their members; sampled queries against the oracle reading the GPU image."""
+    of their members; sampled queries against the oracle reading the GPU image; the whole image
+    (remap table included) and pilot array against the hashes of the oracle's own build."""
     buf, offs, hi, lo = strings_100m
     n = offs.size - 1
     db, do = torch.from_numpy(buf).cuda(), _dev(torch, offs)
@@ -332,22 +407,66 @@ def test_full_size_strings_100m_sampled(torch, strings_100m, alpha):
                                                             np.repeat(sub_offs[:-1].astype(np.int64), lens))
     got = pos[torch.from_numpy(sample).cuda()].cpu().numpy().view(np.uint64)
     assert np.array_equal(oracle.query_image_str(g.serialize(), buf[idx], sub_offs), got)
+    _say("100M strings: whole image and pilots against the oracle's build")
+    full = _golden_full("str_100m_l7_a1" if alpha == (1, 1) else "str_100m_l7_a099")
+    assert _sha(np.asarray(pil, dtype=np.uint32)) == full["pilots_sha256"]
+    assert _sha(g.serialize()) == full["image_sha256"]
     bits = g.size_bits() / n
+    assert bits == full["bits_per_key"]
     _say("100M strings: bits/key", bits)
     # the remap table (alpha < 1) adds (T - n) / n entries of bitlen(n - 1) bits per key
     remap = (-(-n * alpha[1] // alpha[0]) - n) / n * (n - 1).bit_length()
     assert 1.7 + remap < bits < 1.9 + remap
 
 
+def test_full_size_150m_general_partitioner(torch):
+    """150M keys at P 2500, lambda 7: 60000 partitions in 15000 coarse bins of four, more than one
+    histogram holds, so the build runs the general partitioner. Whole image and pilot array against
+    the oracle's build (tests/golden), bijection over all keys."""
+    full = _golden_full("u64_150m_l7_rice")
+    _say("150M keys: generate")
+    keys = synth.u64_keys(150_000_000, 1)
+    dk = _dev(torch, keys)
+    _say("150M keys: build")
+    g = binding.build_u64(dk, binding.params(lam=7.0, keep_pilots=True))
+    assert g.build_info()["partition_path"] == 1
+    assert _sha(np.asarray(g.pilots(), dtype=np.uint32)) == full["pilots_sha256"]
+    assert _sha(g.serialize()) == full["image_sha256"]
+    _say("150M keys: query all")
+    pos = g.query_u64(dk)
+    n = keys.size
+    cnt = torch.zeros(n, dtype=torch.int32, device=dk.device)
+    cnt.index_add_(0, pos, torch.ones(n, dtype=torch.int32, device=dk.device))
+    assert int(cnt.min()) == 1 and int(cnt.max()) == 1, "not a bijection onto [0, n)"
+
+
+def test_full_size_10m_lambda13(torch):
+    """10M keys at lambda 13 (Table 1's search-dominated regime): whole image and pilot array against
+    the oracle's build (tests/golden), bijection over all keys."""
+    full = _golden_full("u64_10m_l13_rice")
+    keys = synth.u64_keys(10_000_000, 1)
+    dk = _dev(torch, keys)
+    _say("10M keys, lambda 13: build")
+    g = binding.build_u64(dk, binding.params(lam=13.0, keep_pilots=True))
+    assert _sha(np.asarray(g.pilots(), dtype=np.uint32)) == full["pilots_sha256"]
+    assert _sha(g.serialize()) == full["image_sha256"]
+    pos = g.query_u64(dk).cpu().numpy().view(np.uint64)
+    assert np.array_equal(np.sort(pos), np.arange(keys.size, dtype=np.uint64))
+
+
 BATCH_SIZES = [0, 1, 2, 5, 63, 2500, 2501, 10_007, 50_000, 123_456, 7, 300_000, 1, 0, 40_000]
 
 
-@pytest.mark.parametrize("coding,lam", [("rice", 7.0), ("compact", 5.0)])
-def test_batch_matches_plain_builds(torch, monkeypatch, coding, lam):
+@pytest.mark.parametrize("coding,lam,nc", [("rice", 7.0, 0), ("compact", 5.0, 0), ("rice", 7.0, 40)])
+def test_batch_matches_plain_builds(torch, monkeypatch, coding, lam, nc):
     keysets = [synth.u64_keys(n, 900 + i) for i, n in enumerate(BATCH_SIZES)]
     dev = [_dev(torch, k) for k in keysets]
-    prm = binding.params(lam=lam, coding=coding)
+    prm = binding.params(lam=lam, coding=coding, n_compact=nc)
     plain = [binding.build_u64(d, prm).serialize() for d in dev]
+    # every member's plain build is the oracle's image
+    rp = oracle.params(lam=lam, coding=coding, n_compact=nc)
+    for t, k in enumerate(keysets):
+        assert np.array_equal(plain[t], oracle.build_u64(k, rp, threads=8).image()), f"member {t} (n={k.size})"
     before = binding.get_search_config()
     shapes = [dict(waves_per_group=4, groups_per_cu=0, items_per_grab=1),
               dict(waves_per_group=1, groups_per_cu=2, items_per_grab=4),
@@ -369,9 +488,6 @@ def test_batch_matches_plain_builds(torch, monkeypatch, coding, lam):
             del hs
     finally:
         binding.set_search_config(**before)
-    for t in (3, 8):
-        r = oracle.build_u64(keysets[t], oracle.params(lam=lam, coding=coding))
-        assert np.array_equal(plain[t], r.image())
 
 
 def test_batch_reports_the_failing_member(torch):

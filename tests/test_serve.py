@@ -3,12 +3,13 @@
 A request served alone (one worker, no batching, submitted only after the previous one completed)
 and the same request served in a mix (several workers, queries coalesced into one launch, builds
 coalesced into batched builds, everything submitted at once) must give identical MPHF images and
-identical positions, and both must equal the plain library calls.
+identical positions, and both must equal the oracle's image and positions word for word.
 """
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2404_18497_amd import binding, synth
 
 pytestmark = pytest.mark.gpu
@@ -45,6 +46,11 @@ def test_query_multi_matches_single_queries(torch):
     binding.query_multi_u64([hs[t] for t, _ in reqs], [q for _, q in reqs], outs)
     for (t, q), o in zip(reqs, outs):
         assert torch.equal(o, hs[t].query_u64(q))
+    # and against the oracle's positions for the same key sets
+    refs = [oracle.build_u64(k, oracle.params(lam=6.0), threads=8) for k in sets]
+    for (t, q), o in zip(reqs, outs):
+        qh = q.cpu().numpy().view(np.uint64)
+        assert np.array_equal(o.cpu().numpy().view(np.uint64), refs[t].query_u64(qh))
 
 
 def _trace(seed, nbuild=10, nquery=60):
@@ -102,12 +108,15 @@ def test_server_same_alone_and_in_the_mix(torch):
     img_m, pos_m, batch_m, stats = _run(torch, keysets, queries, workers=4, qb=16, bb=4, alone=False,
                                         query_workers=1)
     assert batch_a == 1 and batch_m > 1  # the mix really batched
-    prm = binding.params(lam=7.0)
-    for k, a, m in zip(keysets, img_a, img_m):
-        plain = binding.build_u64(_dev(torch, k), prm).serialize()
-        assert np.array_equal(a, plain) and np.array_equal(m, plain)
-    for a, m in zip(pos_a, pos_m):
-        assert np.array_equal(a, m) and a.min() >= 0
+    refs = [oracle.build_u64(k, oracle.params(lam=7.0), threads=8) for k in keysets]
+    for t, (r, a, m) in enumerate(zip(refs, img_a, img_m)):
+        want = r.image()
+        assert np.array_equal(a, want), f"build {t} alone differs from the oracle"
+        assert np.array_equal(m, want), f"build {t} in the mix differs from the oracle"
+    for x, ((b, q), a, m) in enumerate(zip(queries, pos_a, pos_m)):
+        want = refs[b].query_u64(q)
+        assert np.array_equal(a.view(np.uint64), want), f"query {x} alone differs from the oracle"
+        assert np.array_equal(m.view(np.uint64), want), f"query {x} in the mix differs from the oracle"
     assert stats["resident_mphfs"] == len(keysets)
 
 
