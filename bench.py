@@ -8,14 +8,20 @@
     launch's start). One step =
     one full build (hash, partition, bucket, order, search, encode) plus the 100 query batches. Keys
     and query keys are resident in HBM before timing starts. ``value`` = build ns/key + query
-    ns/query (lower is better).
+    ns/query (lower is better). The same line then carries the rest of the metric, each after the
+    timed region: lambda 5 and 9 on the same keys and lookups; the mixed-coding curve (query ns/key
+    and bits/key for several counts of leading Compact encoders); 100M random strings (lengths 10-50,
+    [a-z0-9]) at alpha 1 and 0.99 with 100M lookups; a short serving trace (p50/p99 per request kind,
+    plain vs served); and the oracle on the host cores (``cpu_baseline``). ``--no-extras`` skips all
+    but the last.
 --workload batch: 4096 MPHFs, key counts lognormal(median 50K, sigma 1.5) clipped to [1K, 10M]
     (seed 5), uniform uint64 keys (set t from seed 100 + t), P 2500, lambda 7; one batched build with
     an autotuned search shape versus 4096 sequential plain builds. ``value`` = batched ns/key.
 --workload serve: Poisson arrivals of build requests (10%, lognormal sizes median 5e5, sigma 1.5,
     clipped to [10K, 50M]) and query requests (90%, 1K-1M lookups, log-uniform, against resident
     MPHFs) under a 200 GB HBM budget; the library's server with continuous batching versus plain
-    per-request FIFO execution, at the same arrival trace. ``value`` = p99 query latency (ms).
+    per-request FIFO execution, at the same arrival trace, for each load in ``--loads`` (fractions of
+    the measured plain capacity). ``value`` = p99 query latency (ms) at the first load.
 
 --workload copy: a plain 1 GiB device-to-device copy, repeated; the reference kernel whose HBM counter
     readings (FETCH_SIZE, WRITE_SIZE) calibrate the traffic figures of the other kernels, and a
@@ -59,6 +65,11 @@ def parse():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--requests", type=int, default=1500)
     ap.add_argument("--load", type=float, default=0.8, help="arrival rate as a fraction of plain capacity")
+    ap.add_argument("--loads", default="", help="serve workload: comma-separated load fractions")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only: no lambda 5/9 lines, mixed-coding curve, strings or serving trace")
+    ap.add_argument("--mixed", default="16,64,128,-1",
+                    help="mixed-coding curve: leading Compact encoders per point (-1 = Compact coding)")
     return ap.parse_args()
 
 
@@ -66,27 +77,48 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(args):
-    """The oracle as it stands, on a bounded sample of the same workload (1M keys of the same
-    distribution, same parameters): build ns/key + query ns/query on the host cores."""
+    """The oracle as it stands, on a bounded sample of the same workload: the first args.cpu_sample
+    keys' worth of the same distribution (same seed, P, lambda, coding). Per-key build and query cost do
+    not depend on n at fixed P (every partition holds about P keys and is searched alone), so the
+    sample's ns/key stands for the 100M-key workload; its 100M-key equivalent is ns/key x 1e8.
+    The build is timed on one thread and on every host core; the query on one thread."""
     import oracle
     from paper_2404_18497_amd import synth
 
-    threads = max(1, min(16, os.cpu_count() or 1))
+    cores = os.cpu_count() or 1
     keys = synth.u64_keys(args.cpu_sample, 1)
     q = keys[synth.query_indices(keys.size, keys.size, 2)]
     prm = oracle.params(lam=args.lam, coding=args.coding)
     t0 = time.perf_counter()
-    h = oracle.build_u64(keys, prm, threads=threads)
+    oracle.build_u64(keys, prm, threads=1)
     t1 = time.perf_counter()
-    h.query_u64(q)
+    h = oracle.build_u64(keys, prm, threads=cores)
     t2 = time.perf_counter()
-    b = (t1 - t0) * 1e9 / keys.size
-    qn = (t2 - t1) * 1e9 / q.size
-    return {"value": round(b + qn, 2), "unit": "ns/key (build + query)", "cores": threads, "kind": "oracle",
-            "sample": f"{keys.size} keys of the same distribution (seed 1), lambda {args.lam:g}, {args.coding}; "
-                      f"build {b:.1f} ns/key on {threads} threads, query {qn:.1f} ns/query on 1 thread",
-            "build_ns_per_key": round(b, 2), "query_ns_per_query": round(qn, 2)}
+    h.query_u64(q)
+    t3 = time.perf_counter()
+    b1 = (t1 - t0) * 1e9 / keys.size
+    bn = (t2 - t1) * 1e9 / keys.size
+    qn = (t3 - t2) * 1e9 / q.size
+    return {"value": round(bn + qn, 2), "unit": "ns/key (build + query)", "cores": cores, "kind": "oracle",
+            "sample": f"{keys.size} keys of the same distribution (seed 1), lambda {args.lam:g}, {args.coding}, "
+                      f"{keys.size} lookups (seed 2); build {bn:.1f} ns/key on {cores} threads and {b1:.1f} ns/key "
+                      f"on 1 thread, query {qn:.1f} ns/query on 1 thread; per-key cost is independent of n at "
+                      f"fixed P, so x 1e8 gives the 100M-key equivalent",
+            "cpu_model": cpu_model(), "build_ns_per_key": round(bn, 2), "build_ns_per_key_1thread": round(b1, 2),
+            "query_ns_per_query": round(qn, 2),
+            "equivalent_100m_s": {"build_all_cores": round(bn * 0.1, 2), "build_1thread": round(b1 * 0.1, 2),
+                                  "query_1thread": round(qn * 0.1, 2)}}
 
 
 def search_work(n, lam):
@@ -114,6 +146,58 @@ def measured_traffic(kernel: str, n: int, lam: float):
     return rec["read_bytes"] + rec["write_bytes"]
 
 
+def _timed(torch, build, queries, steps, warmup):
+    """Runs `warmup` untimed and `steps` timed steps of build() followed by queries(handle); returns
+    (ms per step by the host clock around the synchronized timed region, mean build ms and mean query
+    ms from events on the build stream, build infos, bits per key source handle)."""
+    stream = torch.cuda.current_stream()
+
+    def step(record=None):
+        if record is not None:
+            record[0].record(stream)
+        h = build()  # returns once the image is complete
+        if record is not None:
+            record[1].record(stream)
+        queries(h)
+        if record is not None:
+            record[2].record(stream)
+        return h
+
+    for _ in range(warmup):
+        step().close()
+    torch.cuda.synchronize()
+    handles, events = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ev = tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
+        handles.append(step(ev))
+        events.append(ev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    infos = [h.build_info() for h in handles]
+    build_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
+    query_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
+    bits = handles[0].size_bits()
+    for h in handles:
+        h.close()
+    return (t1 - t0) * 1e3 / steps, build_ms, query_ms, infos, bits
+
+
+def _phases(infos):
+    return {k: float(np.mean([i[k] for i in infos])) for k in
+            ["hash_count_ms", "scan_ms", "scatter_ms", "bucket_sort_ms", "search_ms", "encode_ms"]}
+
+
+def _batched_queries(torch, n, batch, qstreams, launch):
+    """Issues the lookups in batches of `batch`, round-robin on qstreams, then joins them into the
+    current stream. launch(lo, hi, stream) queries lookups [lo, hi)."""
+    stream = torch.cuda.current_stream()
+    for i, b in enumerate(range(0, n, batch)):
+        launch(b, min(n, b + batch), qstreams[i % len(qstreams)])
+    for qs in qstreams[1:]:
+        stream.wait_stream(qs)
+
+
 def headline(args):
     import torch
 
@@ -130,56 +214,28 @@ def headline(args):
     dq = dk[torch.from_numpy(qidx).to(dev)]
     dp = torch.empty(n, dtype=torch.int64, device=dev)
     del qidx
-    prm = binding.params(lam=args.lam, coding=args.coding)
-    stream = torch.cuda.current_stream()
     # The query batches are independent: they go round-robin to two streams (default priority), so
     # the next batch's wavefronts fill the device while the previous launch drains.
-    qstreams = [stream, torch.cuda.Stream()]
+    qstreams = [torch.cuda.current_stream(), torch.cuda.Stream()]
 
-    def step(record=None):
-        # events on the build stream: [0] before the build, [1] after it, [2] after all queries (the
-        # second query stream joined first)
-        if record is not None:
-            record[0].record(stream)
-        h = binding.build_u64(dk, prm)  # returns once the image is complete
-        if record is not None:
-            record[1].record(stream)
-        for i, b in enumerate(range(0, n, batch)):
-            h.query_u64(dq[b:b + batch], out=dp[b:b + batch], stream=qstreams[i % len(qstreams)])
-        for qs in qstreams[1:]:
-            stream.wait_stream(qs)
-        if record is not None:
-            record[2].record(stream)
-        return h
+    def u64_run(prm, steps, warmup):
+        def queries(h):
+            _batched_queries(torch, n, batch, qstreams,
+                             lambda lo, hi, st: h.query_u64(dq[lo:hi], out=dp[lo:hi], stream=st))
+        return _timed(torch, lambda: binding.build_u64(dk, prm), queries, steps, warmup)
 
-    log("warmup")
-    for _ in range(args.warmup):
-        step().close()
-    torch.cuda.synchronize()
-    handles, events = [], []
     log(f"timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ev = tuple(torch.cuda.Event(enable_timing=True) for _ in range(3))
-        handles.append(step(ev))
-        events.append(ev)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-
-    infos = [h.build_info() for h in handles]
-    build_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
-    query_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
-    phase = {k: float(np.mean([i[k] for i in infos])) for k in
-             ["hash_count_ms", "scan_ms", "scatter_ms", "bucket_sort_ms", "search_ms", "encode_ms"]}
-    bits = handles[0].size_bits() / n
+    ms_per_step, build_ms, query_ms, infos, bits = u64_run(binding.params(lam=args.lam, coding=args.coding),
+                                                           args.steps, args.warmup)
+    phase = _phases(infos)
+    bits /= n
     nlaunch = (n + batch - 1) // batch
 
     # dominant kernel and its roofline (per launch; durations from HIP events on the launch stream)
     cfg = binding.get_search_config()
-    search_kernel = (f"k_search_persistent<{cfg['waves_per_group']}>" if cfg["groups_per_cu"]
-                     else f"k_search<{cfg['waves_per_group']}>")
+    # tables of P 2500 partitions stay below 4096 slots: the one-pass scan instance
+    search_kernel = (f"k_search_persistent<{cfg['waves_per_group']}, false>" if cfg["groups_per_cu"]
+                     else f"k_search<{cfg['waves_per_group']}, false>")
     per_step = {"k_search": phase["search_ms"], "k_query_u64": query_ms}
     dom = max(per_step, key=per_step.get)
     if dom == "k_search":
@@ -229,12 +285,83 @@ def headline(args):
         "query_kernel": {"ms_per_batch": round(q_per, 4), "streams": len(qstreams),
                          "hbm_GBps": round(16.0 * min(batch, n) / (q_per * 1e-3) / 1e9, 1)},
     }
-    for h in handles:
-        h.close()
+    if not args.no_extras:
+        # the rest of the metric, each on the same keys and lookups, one warm-up and two timed steps
+        lam_rows = {}
+        for lam in (5.0, 9.0):
+            log(f"lambda {lam:g}")
+            ms, b_ms, q_ms, inf, bt = u64_run(binding.params(lam=lam), 2, 1)
+            lam_rows[f"{lam:g}"] = {"ms_per_step": round(ms, 3), "build_ns_per_key": round(b_ms * 1e6 / n, 4),
+                                    "query_ns_per_key": round(q_ms * 1e6 / n, 4), "bits_per_key": round(bt / n, 4),
+                                    "search_ms": round(_phases(inf)["search_ms"], 4)}
+        out["lambda_sweep"] = lam_rows
+        curve = []
+        for c in args.mixed:
+            log(f"mixed coding, {c} Compact encoders")
+            coding = "compact" if c < 0 else "rice"
+            ms, b_ms, q_ms, inf, bt = u64_run(binding.params(lam=args.lam, coding=coding, n_compact=max(c, 0)), 2, 1)
+            curve.append({"n_compact": "all (Compact coding)" if c < 0 else c, "bits_per_key": round(bt / n, 4),
+                          "query_ns_per_key": round(q_ms * 1e6 / n, 4), "build_ns_per_key": round(b_ms * 1e6 / n, 4)})
+        out["mixed_coding_curve"] = curve
+    del dk, dq, dp
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        out["strings"] = strings_rows(args, qstreams)
+        log("serving (short trace)")
+        out["serving"] = serve_run(args.requests, [args.load])
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
+
+
+def strings_rows(args, qstreams):
+    """100M random strings (seed 3; lengths 10-50, [a-z0-9]) at lambda 7, alpha 1 and 0.99: build and
+    100M lookups drawn uniformly with replacement (seed 4), in batches of 1M on two streams."""
+    import torch
+
+    from paper_2404_18497_amd import binding, synth
+
+    dev = torch.device("cuda", 0)
+    n, batch = args.n, args.batch
+    log(f"generating {n} strings")
+    buf, offs = synth.ascii_strings(n, 3)
+    db = torch.from_numpy(buf).to(dev)
+    do = torch.from_numpy(offs.view(np.int64)).to(dev)
+    del buf, offs
+    # the lookups' strings gathered once into their own contiguous buffer (before timing)
+    qi = torch.from_numpy(synth.query_indices(n, n, 4)).to(dev)
+    ql = (do[1:] - do[:-1])[qi]
+    qo = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    torch.cumsum(ql, 0, out=qo[1:])
+    qb = torch.empty(int(qo[-1]), dtype=torch.uint8, device=dev)
+    for c0 in range(0, n, 1_000_000):
+        c1 = min(n, c0 + 1_000_000)
+        L = ql[c0:c1]
+        base = qo[c0]
+        rel = torch.arange(int(qo[c1] - base), device=dev) - torch.repeat_interleave(qo[c0:c1] - base, L)
+        qb[int(base):int(qo[c1])] = db[torch.repeat_interleave(do[qi[c0:c1]], L) + rel]
+    del qi, ql
+    dp = torch.empty(n, dtype=torch.int64, device=dev)
+    rows = {}
+    for alpha in [(1, 1), (99, 100)]:
+        log(f"strings, alpha {alpha[0]}/{alpha[1]}")
+        prm = binding.params(lam=7.0, alpha=alpha)
+
+        def queries(h):
+            # offsets are absolute positions in qb, so a slice of them is a batch
+            _batched_queries(torch, n, batch, qstreams,
+                             lambda lo, hi, st: h.query_str(qb, qo[lo:hi + 1], out=dp[lo:hi], stream=st))
+        ms, b_ms, q_ms, inf, bt = _timed(torch, lambda: binding.build_str(db, do, prm), queries, 2, 1)
+        rows[f"alpha_{alpha[0]}/{alpha[1]}"] = {
+            "ms_per_step": round(ms, 3), "build_ns_per_key": round(b_ms * 1e6 / n, 4),
+            "query_ns_per_key": round(q_ms * 1e6 / n, 4), "bits_per_key": round(bt / n, 4),
+            "phases_ms": {k: round(v, 4) for k, v in _phases(inf).items()}}
+    rows["workload"] = (f"{n} random strings (seed 3), lengths 10-50, [a-z0-9], P 2500, lambda 7, interleaved "
+                        f"Rice; {n} uniform lookups (seed 4) in batches of {batch} on {len(qstreams)} streams")
+    del db, do, qb, qo, dp
+    torch.cuda.empty_cache()
+    return rows
 
 
 def batch_mode(args):
@@ -290,7 +417,11 @@ def batch_mode(args):
     print(json.dumps(out), flush=True)
 
 
-def serve_mode(args):
+def serve_run(R, loads):
+    """C5: R requests, 10% builds (lognormal median 5e5, sigma 1.5, clipped to [10K, 50M]) and 90%
+    queries (1K-1M lookups, log-uniform) against 16 resident MPHFs, 200 GB HBM budget. The plain
+    capacity is measured with every request queued at once and run one at a time (FIFO); then for each
+    load factor the same Poisson trace at load x capacity runs plain and served (continuous batching)."""
     import torch
 
     from paper_2404_18497_amd import binding, synth
@@ -298,7 +429,6 @@ def serve_mode(args):
     torch.cuda.set_device(0)
     binding.lib()
     rng = np.random.default_rng(6)
-    R = args.requests
     kinds = rng.random(R) < 0.1  # True = build
     nb = int(kinds.sum())
     bsizes = synth.lognormal_sizes(nb + 16, 500_000, 1.5, 10_000, 50_000_000, 7)
@@ -310,6 +440,7 @@ def serve_mode(args):
     qkeys = [dkeys[t][torch.from_numpy(rng.integers(0, keysets[t].size, int(m))).cuda()]
              for t, m in zip(targets, qsizes)]
     outs = [torch.empty(int(m), dtype=torch.int64, device="cuda") for m in qsizes]
+    del keysets
     prm = binding.params(lam=7.0)
     budget = 200 << 30
 
@@ -343,39 +474,47 @@ def serve_mode(args):
         srv.close()
         lat = {k: np.array([r["done_s"] - r["submit_s"] for r in results.values() if r["kind"] == k]) * 1e3
                for k in ("build", "query")}
-        ok = all(r["status"] == 0 for r in results.values())
-        return {"ok": ok, "makespan_s": t_end - t_start, "throughput_rps": R / (t_end - t_start),
-                "p50_ms": {k: float(np.percentile(v, 50)) for k, v in lat.items() if v.size},
-                "p99_ms": {k: float(np.percentile(v, 99)) for k, v in lat.items() if v.size},
-                "mean_batch": float(np.mean([r["batch"] for r in results.values()])), "stats": st}
+        batches = {k: [r["batch"] for r in results.values() if r["kind"] == k] for k in ("build", "query")}
+        r3 = lambda v: round(float(v), 3)  # noqa: E731
+        return {"ok": all(r["status"] == 0 for r in results.values()),
+                "throughput_rps": round(R / (t_end - t_start), 2), "makespan_s": round(t_end - t_start, 3),
+                "p50_ms": {k: r3(np.percentile(v, 50)) for k, v in lat.items() if v.size},
+                "p99_ms": {k: r3(np.percentile(v, 99)) for k, v in lat.items() if v.size},
+                "mean_batch": {k: r3(np.mean(v)) for k, v in batches.items() if v},
+                "query_launches": st["query_launches"], "build_launches": st["build_launches"],
+                "peak_bytes": st["peak_bytes"]}
 
     plain_kw = dict(workers=1, max_query_batch=1, max_build_batch=1)
     served_kw = dict(workers=4, max_query_batch=64, max_build_batch=8, query_workers=1)
     log("plain capacity (all requests at once, FIFO, one at a time)")
     cap = run(plain_kw, None)
-    rate = args.load * cap["throughput_rps"]
-    arrivals = synth.poisson_arrivals(R, rate, 9)
-    log(f"open loop at {rate:.1f} requests/s: plain")
-    plain = run(plain_kw, arrivals)
-    log("open loop: served (continuous batching)")
-    served = run(served_kw, arrivals)
-    r2 = lambda d: {k: round(v, 3) for k, v in d.items()}  # noqa: E731
+    out = {"requests": R, "plain_capacity_rps": cap["throughput_rps"], "loads": {}}
+    for load in loads:
+        rate = load * cap["throughput_rps"]
+        arrivals = synth.poisson_arrivals(R, rate, 9)
+        log(f"open loop at {load:g} x capacity ({rate:.1f} requests/s): plain")
+        plain = run(plain_kw, arrivals)
+        log("open loop: served (continuous batching)")
+        served = run(served_kw, arrivals)
+        out["loads"][f"{load:g}"] = {"offered_rps": round(rate, 2), "plain": plain, "served": served}
+    out["workload"] = (f"{R} requests, 10% builds (lognormal median 5e5, sigma 1.5, [10K, 50M]), 90% queries "
+                       f"(log-uniform 1K-1M) on 16 resident MPHFs, Poisson arrivals (seed 9) at the given fractions "
+                       f"of plain capacity, 200 GB budget; served = 4 workers (1 query-only), up to 64 queries per "
+                       f"launch and 8 builds per batched build; plain = one at a time, FIFO")
+    return out
+
+
+def serve_mode(args):
+    loads = [float(x) for x in args.loads.split(",")] if args.loads else [args.load]
+    res = serve_run(args.requests, loads)
+    main_load = res["loads"][f"{loads[0]:g}"]
     out = {
         "metric": "serving p99 query latency (ms), Poisson arrivals, 200 GB HBM budget",
-        "value": round(served["p99_ms"]["query"], 3), "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
-        "ms_per_step": round(served["makespan_s"] * 1e3, 3), "higher_is_better": False, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"{R} requests, 10% builds (lognormal median 5e5, sigma 1.5, [10K, 50M]), 90% "
-                               f"queries (log-uniform 1K-1M) on 16 resident MPHFs, Poisson at {args.load:g} x "
-                               f"plain capacity ({rate:.1f}/s), 200 GB budget"},
-        "served": {"p50_ms": r2(served["p50_ms"]), "p99_ms": r2(served["p99_ms"]),
-                   "throughput_rps": round(served["throughput_rps"], 2), "mean_batch": round(served["mean_batch"], 2),
-                   "ok": served["ok"], "peak_bytes": served["stats"]["peak_bytes"],
-                   "query_launches": served["stats"]["query_launches"],
-                   "build_launches": served["stats"]["build_launches"]},
-        "plain": {"p50_ms": r2(plain["p50_ms"]), "p99_ms": r2(plain["p99_ms"]),
-                  "throughput_rps": round(plain["throughput_rps"], 2), "ok": plain["ok"]},
-        "plain_capacity_rps": round(cap["throughput_rps"], 2),
+        "value": main_load["served"]["p99_ms"]["query"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(main_load["served"]["makespan_s"] * 1e3, 3), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": res["workload"], "load": loads[0]},
+        "serving": res,
     }
     print(json.dumps(out), flush=True)
 
@@ -408,6 +547,7 @@ def copy_mode(args):
 
 def main():
     args = parse()
+    args.mixed = [int(x) for x in args.mixed.split(",") if x.strip()] if isinstance(args.mixed, str) else args.mixed
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py runs on one GPU: this library has no multi-GPU path; partitions are independent, so a "
