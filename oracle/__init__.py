@@ -30,7 +30,10 @@ class OracleError(RuntimeError):
 class RefParams(C.Structure):
     _fields_ = [("partition_size", C.c_uint32), ("coding", C.c_uint32), ("lambda_", C.c_double),
                 ("alpha_num", C.c_uint32), ("alpha_den", C.c_uint32), ("hash_seed", C.c_uint64),
-                ("pilot_limit", C.c_uint64), ("n_compact", C.c_uint32), ("reserved", C.c_uint32)]
+                ("pilot_limit", C.c_uint64), ("n_compact", C.c_uint32), ("bucket_fn", C.c_uint32)]
+
+
+BUCKET_FNS = {"optimized": 0, "beta_star": 1, "skew": 2, "uniform": 3}
 
 
 def build_library(force: bool = False) -> str:
@@ -88,6 +91,9 @@ def lib():
         L.phobic_ref_epsilon.argtypes = [C.c_double, C.c_uint32]
         L.phobic_ref_epsilon.restype = C.c_double
         L.phobic_ref_bucket_table.argtypes = [C.c_double, C.c_uint32, C.c_uint32, C.c_uint32, u64p]
+        L.phobic_ref_bucket_table_fn.argtypes = [C.c_double, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, u64p]
+        L.phobic_ref_gamma.argtypes = [C.c_double, C.c_uint32, C.c_double]
+        L.phobic_ref_gamma.restype = C.c_double
         L.phobic_ref_bucket_of.argtypes = [C.c_uint64, u64p, C.c_uint32]
         L.phobic_ref_bucket_of.restype = C.c_uint32
         L.phobic_ref_buckets.argtypes = [u64p, C.c_uint64, u64p, C.c_uint32, u32p]
@@ -108,9 +114,9 @@ def _p(a: np.ndarray, ct):
 
 
 def params(partition_size=2500, lam=7.0, alpha=(1, 1), coding="rice", hash_seed=0x5EED,
-           pilot_limit=0, n_compact=0) -> RefParams:
+           pilot_limit=0, n_compact=0, bucket_fn="optimized") -> RefParams:
     return RefParams(partition_size, 0 if coding == "rice" else 1, float(lam), alpha[0], alpha[1],
-                     hash_seed, pilot_limit, n_compact, 0)
+                     hash_seed, pilot_limit, n_compact, BUCKET_FNS[bucket_fn])
 
 
 class RefMPHF:
@@ -257,10 +263,15 @@ def hash_str(buf: np.ndarray, offs: np.ndarray, seed: int):
     return hi, lo
 
 
-def bucket_table(lam: float, P: int, alpha=(1, 1)) -> np.ndarray:
+def bucket_table(lam: float, P: int, alpha=(1, 1), bucket_fn="optimized") -> np.ndarray:
     T = np.zeros(2049, dtype=np.uint64)
-    lib().phobic_ref_bucket_table(float(lam), P, alpha[0], alpha[1], _p(T, C.c_uint64))
+    lib().phobic_ref_bucket_table_fn(float(lam), P, alpha[0], alpha[1], BUCKET_FNS[bucket_fn], _p(T, C.c_uint64))
     return T
+
+
+def gamma(x: float, bucket_fn="optimized", eps: float = 0.0) -> float:
+    """The bucket assignment function selected by bucket_fn at x (eps only for "optimized")."""
+    return lib().phobic_ref_gamma(float(x), BUCKET_FNS[bucket_fn], float(eps))
 
 
 def bucket_of(lo: int, T: np.ndarray, B: int) -> int:

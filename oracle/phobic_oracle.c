@@ -58,7 +58,7 @@ typedef struct {
   uint64_t hash_seed;
   uint64_t pilot_limit;    /* largest admissible pilot; 0 means 2^32 - 1 */
   uint32_t n_compact;      /* interleaved Rice: encoders 0 .. n_compact-1 use Compact instead (0..B) */
-  uint32_t reserved;
+  uint32_t bucket_fn;      /* bucket assignment function: 0 beta_eps, 1 beta_*, 2 skewed, 3 uniform */
 } ref_params;
 
 /* ----------------------------------------------------------------------------------------------
@@ -126,6 +126,10 @@ static uint64_t pos_hash(uint64_t hi, uint64_t lo, uint64_t s, uint64_t m) {
 /* ----------------------------------------------------------------------------------------------
  * 3. Bucket assignment.  beta_*(x) = x + (1 - x) ln(1 - x) (Sec. 3.2), perturbed to
  * beta_eps(x) = eps x + (1 - eps) beta_*(x) (Theorem 2) with eps = lambda / (5 sqrt(P)) (App. C.1).
+ * For comparison (Sec. 3.1, the figure of bucket assignment functions) the parameter bucket_fn also
+ * selects beta_* itself, the skewed function of PTHash and FCH (the first 60% of the normalized hash
+ * range go to the first 30% of the buckets, each part spread evenly: x / 2 below 0.6, then
+ * 0.3 + 1.75 (x - 0.6); Sec. 2) and the uniform one of CHD (gamma(x) = x).
  * For a load factor alpha < 1 the function is gamma_alpha(x) = gamma(alpha x) / gamma(alpha)
  * (App. B).  It is tabulated at 2048 equally spaced points and interpolated linearly (App. C.1);
  * the table holds round(2^32 gamma(k / 2048)) for k = 0..2048.
@@ -146,19 +150,36 @@ double phobic_ref_epsilon(double lambda, uint32_t P) {
   return eps > 1.0 ? 1.0 : eps;
 }
 
-void phobic_ref_bucket_table(double lambda, uint32_t P, uint32_t alpha_num, uint32_t alpha_den,
-                             uint64_t *T /* TABLE_SIZE + 1 */) {
+enum { BF_OPTIMIZED = 0, BF_BETA_STAR = 1, BF_SKEW = 2, BF_UNIFORM = 3, BF_COUNT = 4 };
+
+/* The bucket assignment function selected by fn, at x in [0, 1]. */
+double phobic_ref_gamma(double x, uint32_t fn, double eps) {
+  switch (fn) {
+    case BF_BETA_STAR: return phobic_ref_beta_star(x);
+    case BF_SKEW: return x <= 0.6 ? 0.5 * x : 0.3 + 1.75 * (x - 0.6);
+    case BF_UNIFORM: return x;
+    default: return phobic_ref_beta_eps(x, eps);
+  }
+}
+
+void phobic_ref_bucket_table_fn(double lambda, uint32_t P, uint32_t alpha_num, uint32_t alpha_den, uint32_t fn,
+                                uint64_t *T /* TABLE_SIZE + 1 */) {
   double eps = phobic_ref_epsilon(lambda, P);
   double alpha = (double)alpha_num / (double)alpha_den;
-  double norm = phobic_ref_beta_eps(alpha, eps);
+  double norm = phobic_ref_gamma(alpha, fn, eps);
   for (int k = 0; k <= TABLE_SIZE; k++) {
     double x = (double)k / TABLE_SIZE;
-    double g = (alpha_num == alpha_den) ? phobic_ref_beta_eps(x, eps)
-                                        : phobic_ref_beta_eps(alpha * x, eps) / norm;
+    double g = (alpha_num == alpha_den) ? phobic_ref_gamma(x, fn, eps)
+                                        : phobic_ref_gamma(alpha * x, fn, eps) / norm;
     T[k] = (uint64_t)llround(ldexp(g, 32));
   }
   T[0] = 0;
   T[TABLE_SIZE] = (uint64_t)1 << 32;
+}
+
+void phobic_ref_bucket_table(double lambda, uint32_t P, uint32_t alpha_num, uint32_t alpha_den,
+                             uint64_t *T /* TABLE_SIZE + 1 */) {
+  phobic_ref_bucket_table_fn(lambda, P, alpha_num, alpha_den, BF_OPTIMIZED, T);
 }
 
 /* Zero-based bucket of a key: floor(B * gamma~(x)) with x = lo / 2^64 and gamma~ the linear
@@ -200,7 +221,7 @@ static int validate(const ref_params *p, uint32_t *B) {
   if (!p) return REF_E_INVALID;
   if (p->partition_size < 1 || !(p->lambda > 0.0) || !isfinite(p->lambda)) return REF_E_INVALID;
   if (p->alpha_den == 0 || p->alpha_num == 0 || p->alpha_num > p->alpha_den) return REF_E_INVALID;
-  if (p->coding > 1) return REF_E_INVALID;
+  if (p->coding > 1 || p->bucket_fn >= BF_COUNT) return REF_E_INVALID;
   double b = ceil((double)p->partition_size / p->lambda);
   if (b < 1.0 || b > 65535.0) return REF_E_INVALID;
   *B = num_buckets(p->partition_size, p->lambda);
@@ -438,7 +459,7 @@ int phobic_ref_search_partition(const uint64_t *hi, const uint64_t *lo, uint64_t
   if (st) return st;
   if (m < nj) return REF_E_INVALID;
   uint64_t T[TABLE_SIZE + 1];
-  phobic_ref_bucket_table(prm->lambda, prm->partition_size, prm->alpha_num, prm->alpha_den, T);
+  phobic_ref_bucket_table_fn(prm->lambda, prm->partition_size, prm->alpha_num, prm->alpha_den, prm->bucket_fn, T);
   uint64_t kbeg[2] = {0, nj}, toff[2] = {0, m};
   part_job job;
   memset(&job, 0, sizeof(job));
@@ -528,7 +549,7 @@ static int encode(ref_mphf *h, const uint8_t *taken_global) {
   w[H_P] = h->prm.partition_size;
   memcpy(&w[H_LAMBDA], &h->prm.lambda, 8);
   w[H_ALPHA] = (uint64_t)h->prm.alpha_num | ((uint64_t)h->prm.alpha_den << 32);
-  w[H_CODING] = h->prm.coding;
+  w[H_CODING] = h->prm.coding | ((uint64_t)h->prm.bucket_fn << 8); /* coding, bucket function */
   w[H_SEED] = h->prm.hash_seed;
   w[H_TOTAL] = Ttot;
   w[H_DMIN] = (uint64_t)dmin;
@@ -618,7 +639,7 @@ static int build_from_hashes(uint64_t *hi, uint64_t *lo, uint64_t n, const ref_p
   uint64_t limit = prm->pilot_limit ? prm->pilot_limit : 0xFFFFFFFFULL;
 
   uint64_t T[TABLE_SIZE + 1];
-  phobic_ref_bucket_table(prm->lambda, prm->partition_size, prm->alpha_num, prm->alpha_den, T);
+  phobic_ref_bucket_table_fn(prm->lambda, prm->partition_size, prm->alpha_num, prm->alpha_den, prm->bucket_fn, T);
 
   /* 2. partition j = floor(hi K / 2^64); group the keys by partition */
   uint64_t *kbeg = calloc(K + 1, sizeof(uint64_t));
@@ -722,7 +743,8 @@ static uint64_t select_one(const uint64_t *unary, const uint64_t *sel, uint64_t 
 static void image_table(const uint64_t *w, uint64_t *T) {
   double lambda;
   memcpy(&lambda, &w[H_LAMBDA], 8);
-  phobic_ref_bucket_table(lambda, (uint32_t)w[H_P], (uint32_t)w[H_ALPHA], (uint32_t)(w[H_ALPHA] >> 32), T);
+  phobic_ref_bucket_table_fn(lambda, (uint32_t)w[H_P], (uint32_t)w[H_ALPHA], (uint32_t)(w[H_ALPHA] >> 32),
+                             (uint32_t)(w[H_CODING] >> 8), T);
 }
 
 static uint64_t query_hash(const uint64_t *w, const uint64_t *T, uint64_t hi, uint64_t lo) {
@@ -746,7 +768,7 @@ static uint64_t query_hash(const uint64_t *w, const uint64_t *T, uint64_t hi, ui
   unsigned wd = (unsigned)(e & 0xFF);
   uint64_t p = get_bits(w + w[H_SEC_DATA], (e >> 8) + j * wd, wd);
   const uint64_t c = w[H_NCOMPACT]; /* encoders below c are Compact */
-  if (w[H_CODING] == 0 && i >= c) {
+  if ((w[H_CODING] & 0xFF) == 0 && i >= c) {
     uint64_t t = (uint64_t)(i - c) * K + j;
     const uint64_t *un = w + w[H_SEC_UNARY], *sel = w + w[H_SEC_SEL];
     uint64_t pt = select_one(un, sel, t);

@@ -156,6 +156,78 @@ def test_beta_star_matches_paper_figure(ref):
     assert err < 2e-6  # the figure prints six significant digits
 
 
+def _figure_curve(name):
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", f"bucket_fn_figure_{name}.txt")
+    return np.array([tuple(map(float, ln.split())) for ln in open(path) if ln.strip() and not ln.startswith("#")])
+
+
+@pytest.mark.parametrize("fn,curve", [("uniform", "uniform"), ("skew", "skew"), ("beta_star", None)])
+def test_bucket_functions_match_paper_figure(ref, fn, curve):
+    # the comparison functions against the figure's printed data (Sec. 3.1): CHD's uniform function,
+    # PTHash's skewed one (60% of the hash range onto 30% of the buckets), and beta_* itself
+    pts = _golden_beta_star() if curve is None else _figure_curve(curve)
+    assert len(pts) == 500
+    err = max(abs(ref.gamma(x, fn) - y) for x, y in pts)
+    assert err < 2e-6  # the figure prints six significant digits
+    # eps plays no part outside beta_eps
+    assert ref.gamma(0.37, fn, 0.2) == ref.gamma(0.37, fn, 0.0)
+
+
+@pytest.mark.parametrize("fn", ["beta_star", "skew", "uniform"])
+def test_tables_of_the_comparison_functions(ref, fn):
+    # T[k] = round(2^32 gamma(k / 2048)), endpoints exact, the same for every lambda and P
+    def closed(x):
+        if fn == "uniform":
+            return x
+        if fn == "skew":
+            return x / 2 if x <= 0.6 else 0.3 + 1.75 * (x - 0.6)
+        return x + (1 - x) * math.log1p(-x) if x < 1 else 1.0
+
+    T = ref.bucket_table(7.0, 2500, bucket_fn=fn)
+    assert T[0] == 0 and T[2048] == 1 << 32
+    assert np.array_equal(T, ref.bucket_table(3.0, 100, bucket_fn=fn))
+    for k in range(0, 2049, 13):
+        assert abs(int(T[k]) - closed(k / 2048) * 2**32) <= 0.5 + 1e-6
+    # alpha < 1 rescales every function the same way (App. B)
+    Ta = ref.bucket_table(7.0, 2500, (9, 10), bucket_fn=fn)
+    for k in range(0, 2049, 64):
+        assert abs(int(Ta[k]) - closed(0.9 * k / 2048) / closed(0.9) * 2**32) <= 0.5 + 1e-3
+
+
+def test_skewed_and_uniform_bucket_frequencies(ref):
+    # skewed: 60% of the keys in the first 30% of the buckets, each part spread evenly; uniform:
+    # every bucket equally likely (chi-square)
+    lam, P = 7.0, 2500
+    B = ref.num_buckets(P, lam)
+    N = 2_000_000
+    lo = np.random.default_rng(21).bit_generator.random_raw(N).astype(np.uint64)
+    cnt = np.bincount(ref.buckets(lo, ref.bucket_table(lam, P, bucket_fn="uniform"), B), minlength=B)
+    chi2 = ((cnt - N / B) ** 2 / (N / B)).sum()
+    assert chi2 < B + 6 * math.sqrt(2 * B)
+    cnt = np.bincount(ref.buckets(lo, ref.bucket_table(lam, P, bucket_fn="skew"), B), minlength=B)
+    split = 0.3 * B  # bucket boundary of the 60% point, 107.4 for B = 358
+    heavy = cnt[: int(split)].sum() + cnt[int(split)] * (split - int(split))
+    assert abs(heavy / N - 0.6) < 0.002
+    inner = cnt[5: int(split) - 5]
+    assert abs(inner.mean() / (N * 0.6 / split) - 1) < 0.01  # heavy buckets: 2 lambda expected keys
+    light = cnt[int(split) + 5: B - 5]
+    assert abs(light.mean() / (N * 0.4 / (B - split)) - 1) < 0.01
+
+
+@pytest.mark.parametrize("fn", ["beta_star", "skew", "uniform"])
+def test_bijection_with_each_bucket_function(ref, fn):
+    for n in [0, 1, 2, 7, 64, 65, 300, 5000]:
+        keys = synth.u64_keys(n, 300 + n)
+        for lam, P, alpha in [(3.0, 50, (1, 1)), (5.0, 2500, (1, 1)), (4.0, 100, (9, 10))]:
+            for coding in ("rice", "compact"):
+                h = ref.build_u64(keys, ref.params(partition_size=P, lam=lam, alpha=alpha, coding=coding, bucket_fn=fn))
+                assert _is_perm(h.query_u64(keys), n), (fn, n, lam, P, alpha)
+                assert np.array_equal(ref.query_image_u64(h.image(), keys), h.query_u64(keys))
+                assert (int(h.image()[7]) >> 8) == ref.BUCKET_FNS[fn]
+
+
 def test_table_is_beta_eps(ref):
     # T[k] = round(2^32 beta_eps(k / 2048)) with eps = lambda / (5 sqrt(P)) (App. C.1)
     for lam, P in [(5, 2500), (7, 2500), (9, 2500), (3.5, 100), (14, 2500)]:
@@ -276,7 +348,8 @@ def _replay_and_check_minimal(ref, keys, prm):
     off = h.offsets()
     hi, lo = ref.hash_u64(keys, prm.hash_seed)
     part = np.array([ref.partition_of(int(x), K) for x in hi], dtype=np.int64)
-    T = ref.bucket_table(prm.lambda_, prm.partition_size, (prm.alpha_num, prm.alpha_den))
+    fn = {v: k for k, v in ref.BUCKET_FNS.items()}[prm.bucket_fn]
+    T = ref.bucket_table(prm.lambda_, prm.partition_size, (prm.alpha_num, prm.alpha_den), fn)
     bk = ref.buckets(lo, T, B)
     for j in range(K):
         idx = np.nonzero(part == j)[0]
@@ -314,6 +387,8 @@ def test_pilots_are_minimal_bruteforce(ref):
     _replay_and_check_minimal(ref, synth.u64_keys(60, 5), ref.params(partition_size=30, lam=3.0))
     _replay_and_check_minimal(ref, synth.u64_keys(200, 6), ref.params(partition_size=100, lam=5.0))
     _replay_and_check_minimal(ref, synth.u64_keys(150, 8), ref.params(partition_size=150, lam=7.0))
+    for fn in ("beta_star", "skew", "uniform"):
+        _replay_and_check_minimal(ref, synth.u64_keys(120, 9), ref.params(partition_size=60, lam=4.0, bucket_fn=fn))
 
 
 def test_order_independence_and_determinism(ref):
