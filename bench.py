@@ -12,8 +12,9 @@
     timed region: lambda 5 and 9 on the same keys and lookups; the mixed-coding curve (query ns/key
     and bits/key for several counts of leading Compact encoders); 100M random strings (lengths 10-50,
     [a-z0-9]) at alpha 1 and 0.99 with 100M lookups; a short serving trace (p50/p99 per request kind,
-    plain vs served); and the oracle on the host cores (``cpu_baseline``). ``--no-extras`` skips all
-    but the last.
+    plain vs served); the bucket assignment functions compared in Sec. 3.1 (beta_*, PTHash's skewed,
+    CHD's uniform) on the same keys; and the oracle on the host cores (``cpu_baseline``).
+    ``--no-extras`` skips all but the last.
 --workload batch: 4096 MPHFs, key counts lognormal(median 50K, sigma 1.5) clipped to [1K, 10M]
     (seed 5), uniform uint64 keys (set t from seed 100 + t), P 2500, lambda 7; one batched build with
     an autotuned search shape versus 4096 sequential plain builds. ``value`` = batched ns/key.
@@ -303,6 +304,15 @@ def headline(args):
             curve.append({"n_compact": "all (Compact coding)" if c < 0 else c, "bits_per_key": round(bt / n, 4),
                           "query_ns_per_key": round(q_ms * 1e6 / n, 4), "build_ns_per_key": round(b_ms * 1e6 / n, 4)})
         out["mixed_coding_curve"] = curve
+        # the bucket assignment functions of the comparison in Sec. 3.1, same keys, lambda and coding
+        fns = {"optimized (beta_eps)": {"build_ns_per_key": out["build_ns_per_key"], "bits_per_key": out["bits_per_key"],
+                                        "search_ms": out["phases_ms"]["search_ms"]}}
+        for fn in ("beta_star", "skew", "uniform"):
+            log(f"bucket function {fn}")
+            ms, b_ms, q_ms, inf, bt = u64_run(binding.params(lam=args.lam, coding=args.coding, bucket_fn=fn), 1, 1)
+            fns[fn] = {"build_ns_per_key": round(b_ms * 1e6 / n, 4), "bits_per_key": round(bt / n, 4),
+                       "search_ms": round(_phases(inf)["search_ms"], 4), "query_ns_per_key": round(q_ms * 1e6 / n, 4)}
+        out["bucket_functions"] = fns
     del dk, dq, dp
     torch.cuda.empty_cache()
     if not args.no_extras:

@@ -39,6 +39,10 @@ typedef enum {
 } phobic_status;
 
 enum { PHOBIC_IC_RICE = 0, PHOBIC_IC_COMPACT = 1 };
+/* Bucket assignment functions (Sec. 3.1, Sec. 3.2): PHOBIC's beta_eps (the default), beta_* itself,
+ * and for comparison the skewed function of PTHash and FCH (60% of the hash range onto the first 30%
+ * of the buckets) and the uniform one of CHD. */
+enum { PHOBIC_BF_OPTIMIZED = 0, PHOBIC_BF_BETA_STAR = 1, PHOBIC_BF_SKEW = 2, PHOBIC_BF_UNIFORM = 3 };
 enum { PHOBIC_FLAG_KEEP_PILOTS = 1u }; /* keep the raw pilot array for phobic_get_pilots() */
 
 /* Construction parameters (Sec. 4, Sec. 4.1, Sec. 5; App. B for alpha). */
@@ -54,6 +58,8 @@ typedef struct {
                               0 .. n_compact-1 (the largest, most queried buckets) use Compact and the
                               rest Golomb-Rice; 0 .. B.  With PHOBIC_IC_COMPACT it must be 0 or B. */
   uint32_t flags;          /* PHOBIC_FLAG_* */
+  uint32_t bucket_function; /* PHOBIC_BF_*; stored in the image (bits 8.. of the coding word) */
+  uint32_t reserved;        /* must be 0 */
 } phobic_params;
 
 typedef struct phobic_mphf phobic_mphf;

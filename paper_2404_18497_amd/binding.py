@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libphobic.so")
 
 OK, E_INVALID, E_DUPLICATE, E_OOM, E_PILOT_OVERFLOW, E_DEVICE, E_FORMAT, E_CAPACITY = range(8)
 RICE, COMPACT = 0, 1
+BUCKET_FNS = {"optimized": 0, "beta_star": 1, "skew": 2, "uniform": 3}
 FLAG_KEEP_PILOTS = 1
 
 EXPORTS = [
@@ -40,7 +41,8 @@ class PhobicError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("partition_size", C.c_uint32), ("coding", C.c_uint32), ("lambda_", C.c_double),
                 ("alpha_num", C.c_uint32), ("alpha_den", C.c_uint32), ("hash_seed", C.c_uint64),
-                ("pilot_limit", C.c_uint64), ("n_compact", C.c_uint32), ("flags", C.c_uint32)]
+                ("pilot_limit", C.c_uint64), ("n_compact", C.c_uint32), ("flags", C.c_uint32),
+                ("bucket_function", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class SearchConfig(C.Structure):
@@ -136,7 +138,7 @@ def _check(code: int):
 
 
 def params(partition_size=2500, lam=7.0, alpha=(1, 1), coding="rice", hash_seed=0x5EED, pilot_limit=0,
-           keep_pilots=False, n_compact=0) -> Params:
+           keep_pilots=False, n_compact=0, bucket_fn="optimized") -> Params:
     p = Params()
     lib().phobic_params_default(C.byref(p))
     p.partition_size = partition_size
@@ -146,6 +148,7 @@ def params(partition_size=2500, lam=7.0, alpha=(1, 1), coding="rice", hash_seed=
     p.hash_seed = hash_seed
     p.pilot_limit = pilot_limit
     p.n_compact = n_compact
+    p.bucket_function = BUCKET_FNS[bucket_fn]
     p.flags = FLAG_KEEP_PILOTS if keep_pilots else 0
     return p
 

@@ -39,6 +39,8 @@ phobic_status validate_params(const phobic_params* p, uint32_t* B) {
   if (p->alpha_den == 0 || p->alpha_num == 0 || p->alpha_num > p->alpha_den)
     return fail(PHOBIC_E_INVALID, "alpha must be in (0, 1]");
   if (p->coding > 1) return fail(PHOBIC_E_INVALID, "unknown coding");
+  if (p->bucket_function > PHOBIC_BF_UNIFORM) return fail(PHOBIC_E_INVALID, "unknown bucket function");
+  if (p->reserved != 0) return fail(PHOBIC_E_INVALID, "params.reserved must be 0");
   if (p->pilot_limit > 0xFFFFFFFFULL) return fail(PHOBIC_E_INVALID, "pilot_limit exceeds 2^32 - 1");
   double b = std::ceil((double)p->partition_size / p->lambda);  // B = P / lambda (Sec. 4.1)
   if (b < 1.0 || b > 65535.0) return fail(PHOBIC_E_INVALID, "B = ceil(P / lambda) must be in [1, 65535]");
@@ -52,19 +54,28 @@ phobic_status validate_params(const phobic_params* p, uint32_t* B) {
   return PHOBIC_OK;
 }
 
-// beta_* (Sec. 3.2), beta_eps with eps = lambda / (5 sqrt(P)) (Thm. 2, App. C.1), rescaled to
-// gamma_alpha for alpha < 1 (App. B); tabulated at 2049 points as round(2^32 gamma(k / 2048)).
+// beta_* (Sec. 3.2), beta_eps with eps = lambda / (5 sqrt(P)) (Thm. 2, App. C.1), and the functions
+// of related work it is compared with (Sec. 3.1): PTHash's skewed one (the first 60% of the hash
+// range spread over the first 30% of the buckets, the rest over the others) and CHD's uniform one.
+// Rescaled to gamma_alpha for alpha < 1 (App. B); tabulated at 2049 points as round(2^32 gamma(k / 2048)).
 static double beta_star(double x) { return x >= 1.0 ? 1.0 : x + (1.0 - x) * std::log1p(-x); }
 
-void bucket_table(double lambda, uint32_t P, uint32_t an, uint32_t ad, uint64_t* T) {
+void bucket_table(double lambda, uint32_t P, uint32_t an, uint32_t ad, uint32_t fn, uint64_t* T) {
   double eps = lambda / (5.0 * std::sqrt((double)P));
   if (eps > 1.0) eps = 1.0;
-  auto beps = [eps](double x) { return eps * x + (1.0 - eps) * beta_star(x); };
+  auto gamma = [eps, fn](double x) {
+    switch (fn) {
+      case PHOBIC_BF_BETA_STAR: return beta_star(x);
+      case PHOBIC_BF_SKEW: return x <= 0.6 ? 0.5 * x : 0.3 + 1.75 * (x - 0.6);
+      case PHOBIC_BF_UNIFORM: return x;
+      default: return eps * x + (1.0 - eps) * beta_star(x);
+    }
+  };
   const double alpha = (double)an / (double)ad;
-  const double norm = beps(alpha);
+  const double norm = gamma(alpha);
   for (uint32_t k = 0; k <= kTableIntervals; k++) {
     const double x = (double)k / kTableIntervals;
-    const double g = an == ad ? beps(x) : beps(alpha * x) / norm;
+    const double g = an == ad ? gamma(x) : gamma(alpha * x) / norm;
     T[k] = (uint64_t)std::llround(std::ldexp(g, 32));
   }
   T[0] = 0;
@@ -89,9 +100,9 @@ namespace {
 struct TableKey {
   int device;
   uint64_t lambda_bits;
-  uint32_t P, an, ad;
+  uint32_t P, an, ad, fn;
   bool operator<(const TableKey& o) const {
-    return std::tie(device, lambda_bits, P, an, ad) < std::tie(o.device, o.lambda_bits, o.P, o.an, o.ad);
+    return std::tie(device, lambda_bits, P, an, ad, fn) < std::tie(o.device, o.lambda_bits, o.P, o.an, o.ad, o.fn);
   }
 };
 std::mutex g_table_mu;
@@ -131,7 +142,7 @@ hipError_t pool_alloc(void** p, size_t bytes, hipStream_t st) {
 }
 
 phobic_status upload_table(phobic_mphf* h, hipStream_t st) {
-  TableKey key{h->device, 0, h->prm.partition_size, h->prm.alpha_num, h->prm.alpha_den};
+  TableKey key{h->device, 0, h->prm.partition_size, h->prm.alpha_num, h->prm.alpha_den, h->prm.bucket_function};
   std::memcpy(&key.lambda_bits, &h->prm.lambda, 8);
   std::lock_guard<std::mutex> lock(g_table_mu);
   auto it = g_tables.find(key);
@@ -140,7 +151,8 @@ phobic_status upload_table(phobic_mphf* h, hipStream_t st) {
     return PHOBIC_OK;
   }
   std::vector<uint64_t> T(kTableIntervals + 1);
-  bucket_table(h->prm.lambda, h->prm.partition_size, h->prm.alpha_num, h->prm.alpha_den, T.data());
+  bucket_table(h->prm.lambda, h->prm.partition_size, h->prm.alpha_num, h->prm.alpha_den, h->prm.bucket_function,
+               T.data());
   uint64_t* d = nullptr;
   PHOBIC_HIP(hipMalloc(&d, T.size() * sizeof(uint64_t)));
   hipError_t e = hipMemcpyAsync(d, T.data(), T.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st);
@@ -170,7 +182,7 @@ std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phob
   hdr[kHP] = prm.partition_size;
   std::memcpy(&hdr[kHLambda], &prm.lambda, 8);
   hdr[kHAlpha] = (uint64_t)prm.alpha_num | ((uint64_t)prm.alpha_den << 32);
-  hdr[kHCoding] = prm.coding;
+  hdr[kHCoding] = prm.coding | ((uint64_t)prm.bucket_function << 8);  // coding, bucket function
   hdr[kHSeed] = prm.hash_seed;
   hdr[kHTotal] = total;
   hdr[kHDmin] = (uint64_t)dmin;
@@ -209,7 +221,7 @@ void fill_query_args(phobic_mphf* h) {
   a.seed = H[kHSeed];
   a.B = (uint32_t)H[kHB];
   a.woff = (uint32_t)H[kHWoff];
-  a.coding = (uint32_t)H[kHCoding];
+  a.coding = (uint32_t)(H[kHCoding] & 0xFF);
   a.wremap = (uint32_t)H[kHWremap];
   a.ncompact = (uint32_t)H[kHNcompact];
 }
@@ -231,9 +243,10 @@ static phobic_status check_image(const uint64_t* w, uint64_t nwords) {
   if (nwords < kHeaderWords || w[kHMagic] != kMagic) return bad("magic");
   if (w[kHWords] != nwords) return bad("length");
   const uint64_t n = w[kHN], K = w[kHK], B = w[kHB], total = w[kHTotal];
-  if (K == 0 || B == 0 || B > 65535 || w[kHCoding] > 1 || total < n) return bad("sizes");
+  const uint64_t coding = w[kHCoding] & 0xFF, bfn = w[kHCoding] >> 8;
+  if (K == 0 || B == 0 || B > 65535 || coding > 1 || bfn > PHOBIC_BF_UNIFORM || total < n) return bad("sizes");
   const uint64_t c = w[kHNcompact];  // Compact encoders before the Rice ones (Rice images only)
-  if (c > B || (w[kHCoding] != PHOBIC_IC_RICE && c != 0)) return bad("mixed coding");
+  if (c > B || (coding != PHOBIC_IC_RICE && c != 0)) return bad("mixed coding");
   const uint32_t an = (uint32_t)w[kHAlpha], ad = (uint32_t)(w[kHAlpha] >> 32);
   if (an == 0 || ad == 0 || an > ad || w[kHP] == 0 || w[kHP] > 0xFFFFFFFFULL) return bad("parameters");
   double lambda;
@@ -263,7 +276,7 @@ static phobic_status check_image(const uint64_t* w, uint64_t nwords) {
     if (wd > 32 || (e >> 8) + (uint64_t)wd * K > data_bits) return bad("encoder table");
   }
   const uint64_t nvals = K * (B - c);  // values of the Rice encoders: one one each in the unary stream
-  if (w[kHCoding] == PHOBIC_IC_RICE) {
+  if (coding == PHOBIC_IC_RICE) {
     const uint64_t ubits = w[kHUbits];
     if (su + (ubits + 63) / 64 + 1 != ss) return bad("unary length");
     uint64_t ones = 0;
@@ -389,7 +402,8 @@ extern "C" phobic_status phobic_deserialize(const void* h_buf, uint64_t bytes, v
   std::memcpy(&h->prm.lambda, &w[kHLambda], 8);
   h->prm.alpha_num = (uint32_t)w[kHAlpha];
   h->prm.alpha_den = (uint32_t)(w[kHAlpha] >> 32);
-  h->prm.coding = (uint32_t)w[kHCoding];
+  h->prm.coding = (uint32_t)(w[kHCoding] & 0xFF);
+  h->prm.bucket_function = (uint32_t)(w[kHCoding] >> 8);
   h->prm.n_compact = (uint32_t)w[kHNcompact];
   h->prm.hash_seed = w[kHSeed];
   h->nwords = nwords;

@@ -2107,7 +2107,7 @@ __global__ __launch_bounds__(256) void k_batch_pack_vals(const uint32_t* __restr
   uint64_t* data = img + h[kHSecData];
   uint64_t* unary = img + h[kHSecUnary];
   const uint32_t nc = (uint32_t)h[kHNcompact];  // mixed coding: encoders below nc are Compact
-  const bool rice = h[kHCoding] == PHOBIC_IC_RICE && i >= nc;
+  const bool rice = (h[kHCoding] & 0xFF) == PHOBIC_IC_RICE && i >= nc;
   const uint64_t e = encw[item];
   const uint32_t w = (uint32_t)(e & 0xFF);
   const uint64_t base = e >> 8;

@@ -86,7 +86,7 @@ phobic_status fail(phobic_status s, const std::string& msg);
 // Host planning shared by build and deserialize.
 phobic_status validate_params(const phobic_params* p, uint32_t* B);
 uint64_t num_partitions(uint64_t n, uint32_t P);
-void bucket_table(double lambda, uint32_t P, uint32_t an, uint32_t ad, uint64_t* T);
+void bucket_table(double lambda, uint32_t P, uint32_t an, uint32_t ad, uint32_t fn, uint64_t* T);
 uint32_t rice_parameter(uint64_t sum, uint64_t count);
 phobic_status upload_table(phobic_mphf* h, hipStream_t st);
 std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phobic_params& prm, uint64_t total,

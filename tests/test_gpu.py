@@ -33,11 +33,12 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
 
 
-def _both(torch, keys, lam=7.0, P=2500, alpha=(1, 1), coding="rice", seed=0x5EED, pilot_limit=0, n_compact=0):
+def _both(torch, keys, lam=7.0, P=2500, alpha=(1, 1), coding="rice", seed=0x5EED, pilot_limit=0, n_compact=0,
+          bucket_fn="optimized"):
     gp = binding.params(partition_size=P, lam=lam, alpha=alpha, coding=coding, hash_seed=seed, pilot_limit=pilot_limit,
-                        keep_pilots=True, n_compact=n_compact)
+                        keep_pilots=True, n_compact=n_compact, bucket_fn=bucket_fn)
     rp = oracle.params(partition_size=P, lam=lam, alpha=alpha, coding=coding, hash_seed=seed, pilot_limit=pilot_limit,
-                       n_compact=n_compact)
+                       n_compact=n_compact, bucket_fn=bucket_fn)
     g = binding.build_u64(_dev(torch, keys), gp)
     r = oracle.build_u64(keys, rp, threads=8)
     return g, r
@@ -100,6 +101,20 @@ def test_lambda14_parity(torch):
     _say("lambda", 14)
     g, r = _both(torch, keys, lam=14.0)
     _check_same(torch, g, r, keys)
+
+
+@pytest.mark.parametrize("fn", ["beta_star", "skew", "uniform"])
+@pytest.mark.parametrize("lam,alpha,coding", [(5.0, (1, 1), "rice"), (7.0, (1, 1), "compact"), (6.0, (9, 10), "rice")])
+def test_bucket_function_parity(torch, fn, lam, alpha, coding):
+    """The comparison bucket assignment functions (Sec. 3.1: beta_*, PTHash's skewed and CHD's
+    uniform one): pilots, image and queries against the oracle."""
+    keys = synth.u64_keys(200_000, 41)
+    _say("bucket function", fn, lam, alpha, coding)
+    g, r = _both(torch, keys, lam=lam, alpha=alpha, coding=coding, bucket_fn=fn)
+    assert int(g.serialize()[7]) >> 8 == binding.BUCKET_FNS[fn]
+    _check_same(torch, g, r, keys)
+    h = binding.deserialize(g.serialize())  # the function travels with the image
+    assert np.array_equal(h.query_u64(_dev(torch, keys)).cpu().numpy().view(np.uint64), r.query_u64(keys))
 
 
 @pytest.mark.parametrize("c", [0, 1, 16, 179, 358])
