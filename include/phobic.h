@@ -115,6 +115,19 @@ phobic_status phobic_query_multi_u64(const phobic_mphf* const* h_handles, const 
                                      const uint64_t* h_counts, uint64_t* const* h_outs, uint32_t count,
                                      void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): phobic_query_multi_u64 without any allocation.  Same arguments
+ * and outputs; the per-call job table goes to a fixed device array of the library (one per GPU, about
+ * 0.7 MB, held until the process ends) instead of the library's memory pool.  At most
+ * PHOBIC_NOALLOC_MAX_REQUESTS requests per call (more give PHOBIC_E_INVALID and no work).  Every call
+ * on one GPU shares that GPU's array, so calls must not overlap on a GPU: issue them on one stream,
+ * or order them (events, synchronization); overlapping calls race on the table.  Asynchronous on
+ * hip_stream like phobic_query_multi_u64. */
+#define PHOBIC_NOALLOC_MAX_REQUESTS 4096
+phobic_status phobic_query_multi_u64_noalloc(const phobic_mphf* const* h_handles, const uint64_t* const* h_keys,
+                                             const uint64_t* h_counts, uint64_t* const* h_outs, uint32_t count,
+                                             void* hip_stream);
+
 /* Size of the structure in bits = 8 x serialized bytes, header and tables included; divided by n it
  * is the space measure (bits per key) of Sec. 5 and Table 1. */
 uint64_t phobic_size_bits(const phobic_mphf* h);

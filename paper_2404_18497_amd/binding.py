@@ -25,11 +25,13 @@ EXPORTS = [
     "phobic_size_bits", "phobic_num_keys", "phobic_num_partitions", "phobic_num_buckets", "phobic_get_pilots",
     "phobic_get_build_info", "phobic_serialize", "phobic_deserialize", "phobic_partition_u64", "phobic_free",
     "phobic_status_str", "phobic_last_error", "phobic_set_search_config", "phobic_get_search_config",
-    "phobic_build_batch_u64", "phobic_query_multi_u64", "phobic_server_create", "phobic_server_submit_build",
+    "phobic_build_batch_u64", "phobic_query_multi_u64", "phobic_query_multi_u64_noalloc",
+    "phobic_server_create", "phobic_server_submit_build",
     "phobic_server_submit_query", "phobic_server_poll", "phobic_server_mphf", "phobic_server_release",
     "phobic_server_get_stats", "phobic_server_now", "phobic_server_destroy",
 ]
 REQ_BUILD, REQ_QUERY = 0, 1
+NOALLOC_MAX_REQUESTS = 4096
 
 
 class PhobicError(RuntimeError):
@@ -103,6 +105,8 @@ def lib() -> C.CDLL:
         L.phobic_set_search_config.argtypes = [C.POINTER(SearchConfig)]
         L.phobic_get_search_config.argtypes = [C.POINTER(SearchConfig)]
         L.phobic_query_multi_u64.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(u64), C.POINTER(vp), u32, vp]
+        L.phobic_query_multi_u64_noalloc.argtypes = [C.POINTER(vp), C.POINTER(vp), C.POINTER(u64), C.POINTER(vp), u32,
+                                                     vp]
         L.phobic_server_create.argtypes = [C.POINTER(ServerConfig), P, C.POINTER(vp)]
         L.phobic_server_submit_build.argtypes = [vp, vp, u64, C.POINTER(u64)]
         L.phobic_server_submit_query.argtypes = [vp, u64, vp, u64, vp, C.POINTER(u64)]
@@ -124,7 +128,8 @@ def lib() -> C.CDLL:
         for name in ["phobic_build_u64", "phobic_build_str", "phobic_query_u64", "phobic_query_str",
                      "phobic_get_pilots", "phobic_get_build_info", "phobic_serialize", "phobic_deserialize",
                      "phobic_partition_u64", "phobic_build_batch_u64", "phobic_set_search_config",
-                     "phobic_get_search_config", "phobic_query_multi_u64", "phobic_server_create",
+                     "phobic_get_search_config", "phobic_query_multi_u64", "phobic_query_multi_u64_noalloc",
+                     "phobic_server_create",
                      "phobic_server_submit_build", "phobic_server_submit_query", "phobic_server_poll",
                      "phobic_server_release", "phobic_server_get_stats"]:
             getattr(L, name).restype = C.c_int
@@ -257,14 +262,16 @@ def build_batch_u64(key_tensors, prm: Params, stream=None) -> list:
     return [MPHF(C.c_void_p(outs[t])) for t in range(count)]
 
 
-def query_multi_u64(handles, key_tensors, out_tensors, stream=None):
-    """One launch for several (MPHF, keys) requests; out_tensors receive the positions."""
+def query_multi_u64(handles, key_tensors, out_tensors, stream=None, noalloc=False):
+    """One launch for several (MPHF, keys) requests; out_tensors receive the positions. noalloc=True
+    calls the allocation-free entry point (at most NOALLOC_MAX_REQUESTS requests)."""
     count = len(handles)
     hs = (C.c_void_p * max(count, 1))(*[h.h.value if isinstance(h.h, C.c_void_p) else h.h for h in handles])
     ks = (C.c_void_p * max(count, 1))(*[_dptr(k).value for k in key_tensors])
     ns = (C.c_uint64 * max(count, 1))(*[k.numel() for k in key_tensors])
     os_ = (C.c_void_p * max(count, 1))(*[_dptr(o).value for o in out_tensors])
-    _check(lib().phobic_query_multi_u64(hs, ks, ns, os_, count, _stream(stream)))
+    fn = lib().phobic_query_multi_u64_noalloc if noalloc else lib().phobic_query_multi_u64
+    _check(fn(hs, ks, ns, os_, count, _stream(stream)))
 
 
 class Server:

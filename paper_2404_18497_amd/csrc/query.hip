@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -303,6 +304,22 @@ __global__ __launch_bounds__(kQBlock) void k_query_multi(const QueryJob* __restr
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Allocation-free multi-request query: the job table lives in `scratch`, a fixed device array of
+// this library (one per GPU, kept until the process ends), instead of a pool allocation.  Its
+// layout: kNoAllocRequests jobs, then kNoAllocRequests block starts.
+// ---------------------------------------------------------------------------------------------
+constexpr uint32_t kNoAllocRequests = 4096;
+constexpr size_t kNoAllocJobBytes = (size_t)kNoAllocRequests * sizeof(QueryJob);
+constexpr size_t kNoAllocBytes = kNoAllocJobBytes + (size_t)kNoAllocRequests * sizeof(uint64_t);
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;                   // guards the table below and the host staging
+void* g_noalloc_dev[kNoAllocDevices] = {};  // device address of `scratch` per device
+// Host staging of one call's table (pageable; a copy from it is staged before the copy call returns).
+alignas(64) uint8_t g_noalloc_host[kNoAllocBytes];
+
 uint32_t query_grid(uint64_t n, uint32_t per_thread = 1) {
   uint64_t g = (n + (uint64_t)kQBlock * per_thread - 1) / ((uint64_t)kQBlock * per_thread);
   return (uint32_t)(g < 1 ? 1 : (g > 1048576 ? 1048576 : g));
@@ -386,5 +403,48 @@ extern "C" phobic_status phobic_query_multi_u64(const phobic_mphf* const* h_hand
   }
   (void)hipFreeAsync(dbuf, st);
   if (e != hipSuccess) return fail(PHOBIC_E_DEVICE, std::string("query_multi: ") + hipGetErrorString(e));
+  return PHOBIC_OK;
+}
+
+extern "C" phobic_status phobic_query_multi_u64_noalloc(const phobic_mphf* const* h_handles,
+                                                        const uint64_t* const* h_keys, const uint64_t* h_counts,
+                                                        uint64_t* const* h_outs, uint32_t count, void* hip_stream) {
+  if (count == 0) return PHOBIC_OK;
+  if (!h_handles || !h_keys || !h_counts || !h_outs) return fail(PHOBIC_E_INVALID, "null argument");
+  if (count > kNoAllocRequests)
+    return fail(PHOBIC_E_INVALID, "at most " + std::to_string(kNoAllocRequests) + " requests per call");
+  int dev = 0;
+  PHOBIC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices) return fail(PHOBIC_E_INVALID, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_dev[dev]) {  // once per device, with that device current: the array's own address
+    void* ptr = nullptr;
+    PHOBIC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(PHOBIC_E_DEVICE, "no device address for the query scratch array");
+    g_noalloc_dev[dev] = ptr;
+  }
+  uint8_t* dscr = (uint8_t*)g_noalloc_dev[dev];
+  QueryJob* jobs = (QueryJob*)g_noalloc_host;
+  uint64_t* bstart = (uint64_t*)(g_noalloc_host + kNoAllocJobBytes);
+  uint32_t nj = 0;
+  uint64_t blocks = 0;
+  for (uint32_t r = 0; r < count; r++) {
+    if (!h_handles[r]) return fail(PHOBIC_E_INVALID, "null handle in request " + std::to_string(r));
+    const uint64_t n = h_counts[r];
+    if (n == 0) continue;
+    if (!h_keys[r] || !h_outs[r]) return fail(PHOBIC_E_INVALID, "null pointer in request " + std::to_string(r));
+    jobs[nj] = QueryJob{h_handles[r]->qa, h_keys[r], h_outs[r], n};
+    bstart[nj] = blocks;
+    nj++;
+    blocks += (n + (uint64_t)kQBlock * kMultiItems - 1) / ((uint64_t)kQBlock * kMultiItems);
+  }
+  if (nj == 0) return PHOBIC_OK;
+  if (blocks > 0x7FFFFFFFULL) return fail(PHOBIC_E_INVALID, "too many keys in one call");
+  hipStream_t st = (hipStream_t)hip_stream;
+  PHOBIC_HIP(hipMemcpyAsync(dscr, jobs, nj * sizeof(QueryJob), hipMemcpyHostToDevice, st));
+  PHOBIC_HIP(hipMemcpyAsync(dscr + kNoAllocJobBytes, bstart, nj * sizeof(uint64_t), hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(k_query_multi, dim3((uint32_t)blocks), dim3(kQBlock), 0, st, (const QueryJob*)dscr,
+                     (const uint64_t*)(dscr + kNoAllocJobBytes), nj);
+  PHOBIC_HIP(hipGetLastError());
   return PHOBIC_OK;
 }
