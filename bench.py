@@ -24,6 +24,9 @@
     per-request FIFO execution, at the same arrival trace, for each load in ``--loads`` (fractions of
     the measured plain capacity). ``value`` = p99 query latency (ms) at the first load.
 
+--workload psweep: the 100M-key build at lambda 7 for several partition sizes P (1K to 200K): build ns/key,
+    search time, bits/key, and the pilot payload in interleaved versus mono Rice coding.
+
 --workload copy: a plain 1 GiB device-to-device copy, repeated; the reference kernel whose HBM counter
     readings (FETCH_SIZE, WRITE_SIZE) calibrate the traffic figures of the other kernels, and a
     measured copy bandwidth next to the 8 TB/s peak.
@@ -55,7 +58,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="build_query", choices=["build_query", "batch", "serve", "copy"])
+    ap.add_argument("--workload", default="build_query", choices=["build_query", "batch", "serve", "copy", "psweep"])
+    ap.add_argument("--psizes", default="1000,2500,10000,50000,200000", help="psweep: partition sizes")
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--lam", type=float, default=7.0)
     ap.add_argument("--coding", default="rice", choices=["rice", "compact"])
@@ -529,6 +533,72 @@ def serve_mode(args):
     print(json.dumps(out), flush=True)
 
 
+def rice_width(total: int, count: int) -> int:
+    """Golomb-Rice parameter of a geometric source of the given mean (Kiely's rule, as the library
+    uses it); reporting only."""
+    import math
+
+    if total == 0 or count == 0:
+        return 0
+    mu = total / count
+    b = 1 + math.floor(math.log2(math.log((math.sqrt(5) - 1) / 2) / math.log(mu / (mu + 1))))
+    return max(0, min(32, b))
+
+
+def rice_payload_bits(v: np.ndarray) -> int:
+    """Bits of one Golomb-Rice code over the values v: b + 1 + (v >> b) each, b by Kiely's rule."""
+    v = v.astype(np.uint64, copy=False)
+    b = rice_width(int(v.sum()), v.size)
+    return int(v.size) * (b + 1) + int((v >> np.uint64(b)).sum())
+
+
+def psweep_mode(args):
+    """Partition-size sweep (the paper's partition-size experiments): for each P, the 100M-key workload
+    at lambda 7 (Rice): build ns/key and search time, bits/key of the whole structure, and the pilot
+    payload under interleaved Rice coding (one Rice code per bucket index, Sec. 4.1) against one Rice
+    code for all pilots (mono)."""
+    import torch
+
+    from paper_2404_18497_amd import binding, synth
+
+    torch.cuda.set_device(0)
+    binding.lib()
+    n = args.n
+    log(f"generating {n} keys")
+    keys = synth.u64_keys(n, 1)
+    dk = torch.from_numpy(keys.view(np.int64)).cuda()
+    del keys
+    rows = []
+    for P in [int(x) for x in args.psizes.split(",")]:
+        prm = binding.params(partition_size=P, lam=args.lam, keep_pilots=True)
+        log(f"P = {P}")
+        h = binding.build_u64(dk, prm)  # warm-up
+        h.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = binding.build_u64(dk, prm)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        info = h.build_info()
+        pil = h.pilots()  # K x B
+        ic = sum(rice_payload_bits(pil[:, i]) for i in range(pil.shape[1]))
+        mono = rice_payload_bits(pil.reshape(-1))
+        rows.append({"P": P, "K": h.K, "B": h.B, "build_ms": round(ms, 3), "build_ns_per_key": round(ms * 1e6 / n, 4),
+                     "search_ms": round(info["search_ms"], 3), "partition_path": info["partition_path"],
+                     "max_partition_keys": info["max_partition_keys"], "bits_per_key": round(h.size_bits() / n, 4),
+                     "pilot_bits_per_key_ic_rice": round(ic / n, 4), "pilot_bits_per_key_mono_rice": round(mono / n, 4)})
+        log(json.dumps(rows[-1]))
+        h.close()
+    out = {"metric": "partition-size sweep: build ns/key, bits/key, interleaved vs mono Rice pilot bits/key",
+           "value": rows[0]["build_ns_per_key"], "unit": "ns/key", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": rows[0]["build_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u64", "data": "synthetic",
+           "config": {"workload": f"{n} distinct uniform u64 keys (seed 1), lambda {args.lam:g}, alpha 1, interleaved "
+                                  f"Rice, P in {args.psizes}"},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def copy_mode(args):
     import torch
 
@@ -563,7 +633,8 @@ def main():
         print("bench.py runs on one GPU: this library has no multi-GPU path; partitions are independent, so a "
               "multi-GPU build would give each GPU a range of partitions", file=sys.stderr)
         sys.exit(2)
-    {"build_query": headline, "batch": batch_mode, "serve": serve_mode, "copy": copy_mode}[args.workload](args)
+    {"build_query": headline, "batch": batch_mode, "serve": serve_mode, "copy": copy_mode,
+     "psweep": psweep_mode}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -141,6 +141,20 @@ hipError_t pool_alloc(void** p, size_t bytes, hipStream_t st) {
   return hipMallocFromPoolAsync(p, bytes, pool, st);
 }
 
+size_t max_lds_per_group() {
+  static std::mutex mu;
+  static std::map<int, size_t> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 64 * 1024;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(dev);
+  if (it != cache.end()) return it->second;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 64 * 1024;
+  cache[dev] = (size_t)v;
+  return (size_t)v;
+}
+
 phobic_status upload_table(phobic_mphf* h, hipStream_t st) {
   TableKey key{h->device, 0, h->prm.partition_size, h->prm.alpha_num, h->prm.alpha_den, h->prm.bucket_function};
   std::memcpy(&key.lambda_bits, &h->prm.lambda, 8);

@@ -275,6 +275,114 @@ __global__ __launch_bounds__(kBlock) void k_bucket_sort(const ulonglong2* __rest
 }
 
 // ---------------------------------------------------------------------------------------------
+// Bucket mapping and ordering for wide partitions (more keys or buckets than one workgroup holds
+// in LDS), one workgroup of kWideThreads per partition.  The per-bucket counts, then start
+// offsets, live in a global row cnt[j B .. j B + B) (zero on entry) and every key's rank inside its
+// bucket in rank[]; only the sort keys (size << 16 | bucket) of the nbpad buckets are in LDS.
+// Keys of one partition are read twice (bucket and rank, then the scatter) and their buckets
+// computed twice.  A bucket of 65536 or more keys sets the capacity bit.
+// ---------------------------------------------------------------------------------------------
+constexpr int kWideThreads = 1024;
+
+__device__ __forceinline__ uint32_t load_l2_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kWideThreads) void k_bucket_sort_wide(const ulonglong2* __restrict__ codes,
+                                                                   const uint64_t* __restrict__ off,
+                                                                   const uint64_t* __restrict__ T, uint32_t B,
+                                                                   uint32_t nbpad, uint32_t* __restrict__ cnt,
+                                                                   uint32_t* __restrict__ rank,
+                                                                   uint64_t* __restrict__ sortedf,
+                                                                   uint32_t* __restrict__ blist,
+                                                                   uint32_t* __restrict__ nbk, uint32_t* __restrict__ info) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t* key = lds;  // [nbpad]
+  __shared__ uint32_t part[kWideThreads];
+  __shared__ uint32_t nonempty, toolarge;
+  const uint32_t tid = threadIdx.x;
+  const uint64_t j = blockIdx.x;
+  const uint64_t base = off[j];
+  const uint32_t nj = (uint32_t)(off[j + 1] - base);
+  uint32_t* row = cnt + j * B;
+  if (tid == 0) {
+    nonempty = 0;
+    toolarge = 0;
+  }
+  for (uint32_t i = tid; i < nj; i += kWideThreads) {
+    const uint32_t b = bucket_of(codes[base + i].y, T, B);
+    rank[base + i] = atomicAdd(&row[b], 1u);
+  }
+  __threadfence();
+  __syncthreads();
+  uint32_t ne = 0, big = 0;
+  for (uint32_t x = tid; x < nbpad; x += kWideThreads) {
+    const uint32_t c = x < B ? load_l2_u32(&row[x]) : 0u;
+    big |= c > 0xFFFFu;
+    key[x] = c ? ((min(c, 0xFFFFu) << 16) | x) : 0u;
+    ne += c != 0;
+  }
+  atomicAdd(&nonempty, ne);
+  if (big) atomicOr(&toolarge, 1u);
+  __syncthreads();
+  if (toolarge) {
+    if (tid == 0) atomicOr(&info[0], 1u << PHOBIC_E_CAPACITY);
+    return;
+  }
+  // bitonic sort of key[] into descending order: size first, then bucket index
+  for (uint32_t k = 2; k <= nbpad; k <<= 1) {
+    for (uint32_t sd = k >> 1; sd > 0; sd >>= 1) {
+      for (uint32_t x = tid; x < nbpad; x += kWideThreads) {
+        const uint32_t y = x ^ sd;
+        if (y > x) {
+          const uint32_t a = key[x], b = key[y];
+          if ((x & k) == 0 ? (a < b) : (a > b)) {
+            key[x] = b;
+            key[y] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // exclusive prefix of the sizes in processing order: every bucket's start inside the partition
+  const uint32_t ipt = (nbpad + kWideThreads - 1) / kWideThreads;
+  const uint32_t x0 = min(nbpad, tid * ipt), x1 = min(nbpad, x0 + ipt);
+  uint32_t local = 0;
+  for (uint32_t x = x0; x < x1; x++) local += key[x] >> 16;
+  part[tid] = local;
+  __syncthreads();
+  for (uint32_t d = 1; d < kWideThreads; d <<= 1) {
+    const uint32_t v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[tid] - local;
+  const uint32_t nb = nonempty;
+  for (uint32_t x = x0; x < x1; x++) {
+    const uint32_t kx = key[x];
+    if (x < nb) {
+      row[kx & 0xFFFF] = run;
+      blist[j * B + x] = kx;
+    }
+    run += kx >> 16;
+  }
+  if (tid == 0) {
+    nbk[j] = nb;
+    if (nb) atomicMax(&info[1], key[0] >> 16);
+  }
+  __threadfence();
+  __syncthreads();
+  for (uint32_t i = tid; i < nj; i += kWideThreads) {
+    const ulonglong2 c = codes[base + i];
+    const uint32_t b = bucket_of(c.y, T, B);
+    sortedf[base + load_l2_u32(&row[b]) + rank[base + i]] = fingerprint(c.x, c.y);
+  }
+}
+
+
+// ---------------------------------------------------------------------------------------------
 // Hash, partition, bucket and order, main path: coarse bins of G = 2^gshift consecutive partitions,
 // and digits of 2^dshift consecutive coarse bins (at most kMaxDigits digits).
 //
@@ -1480,9 +1588,9 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   uint32_t B = 0;
   phobic_status vs = validate_params(params, &B);
   if (vs != PHOBIC_OK) return vs;
-  if (B > kMaxBuckets)
+  if (B > kWideMaxBuckets)
     return fail(PHOBIC_E_CAPACITY, "B = ceil(P / lambda) = " + std::to_string(B) + " exceeds the device limit " +
-                                       std::to_string(kMaxBuckets));
+                                       std::to_string(kWideMaxBuckets));
   if (in.n > 0 && ((in.src == Src::U64 && !in.keys) || (in.src == Src::Str && (!in.bytes || !in.offs))))
     return fail(PHOBIC_E_INVALID, "null key pointer");
   configure_pool_once();
@@ -1551,7 +1659,8 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     }
   }
   const uint64_t C = gshift >= 0 ? (K + (1ULL << gshift) - 1) >> gshift : 0;
-  const bool coarse_path = gshift >= 0 && C <= kMaxCoarse && n < (1ULL << 32);
+  const bool coarse_path = gshift >= 0 && C <= kMaxCoarse && n < (1ULL << 32) && B <= kMaxBuckets;
+  bool wide = false;  // partitions beyond the LDS of the per-partition workgroups (general path only)
   uint64_t* old_info;  // pinned: max n_j, max m_j, table total of the fallback path
   PHOBIC_HIP(S.host(&old_info, 3));
   old_info[0] = old_info[1] = old_info[2] = 0;
@@ -1670,9 +1779,13 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     PHOBIC_HIP(hipGetLastError());
     PHOBIC_HIP(hipMemcpyAsync(old_info, dinfo, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     PHOBIC_HIP(hipStreamSynchronize(st));
-    if (old_info[0] > kMaxPartitionKeys)
-      return fail(PHOBIC_E_CAPACITY, "a partition holds " + std::to_string(old_info[0]) +
-                                         " keys; the device path holds at most " + std::to_string(kMaxPartitionKeys));
+    // wide partitions: bucketing with global counts and a search whose bucket list and pilots stay
+    // in global memory (the LDS keeps the slot bitmaps and the current bucket's positions only)
+    wide = B > kMaxBuckets || old_info[0] > kMaxPartitionKeys || old_info[1] > kMaxTableSlots;
+    if (wide && old_info[1] >= kWideMaxTableSlots)
+      return fail(PHOBIC_E_CAPACITY, "a partition needs " + std::to_string(old_info[1]) +
+                                         " slots; the device path holds fewer than " +
+                                         std::to_string(kWideMaxTableSlots));
     if (!str)
       hipLaunchKernelGGL(k_scatter_u64, dim3(grid_for(n)), dim3(kBlock), 0, st, in.keys, n, prm.hash_seed, K, off,
                          cnt, codes);
@@ -1681,9 +1794,22 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     tm.mark();  // 3
     if (part_codes_out)
       PHOBIC_HIP(hipMemcpyAsync(part_codes_out, codes, n * sizeof(ulonglong2), hipMemcpyDeviceToDevice, st));
-    const size_t sort_lds = (2 * (size_t)nbpad + std::max<uint64_t>(old_info[0], 1)) * sizeof(uint32_t);
-    hipLaunchKernelGGL(k_bucket_sort, dim3((uint32_t)K), dim3(kBlock), sort_lds, st, codes, off, h->d_table, B,
-                       nbpad, sortedf, blist, nbk, err + 1);
+    if (wide) {
+      const size_t sort_lds = (size_t)nbpad * sizeof(uint32_t);
+      if (sort_lds > max_lds_per_group())
+        return fail(PHOBIC_E_CAPACITY, "B = " + std::to_string(B) + " buckets do not fit the LDS of one workgroup");
+      uint32_t *wcnt, *wrank;
+      PHOBIC_HIP(S.get(&wcnt, K * B));
+      PHOBIC_HIP(S.get(&wrank, n));
+      hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(K * B)), dim3(kBlock), 0, st, wcnt, K * B, 0u);
+      PHOBIC_HIP(allow_lds(k_bucket_sort_wide, sort_lds));
+      hipLaunchKernelGGL(k_bucket_sort_wide, dim3((uint32_t)K), dim3(kWideThreads), sort_lds, st, codes, off,
+                         h->d_table, B, nbpad, wcnt, wrank, sortedf, blist, nbk, err);
+    } else {
+      const size_t sort_lds = (2 * (size_t)nbpad + std::max<uint64_t>(old_info[0], 1)) * sizeof(uint32_t);
+      hipLaunchKernelGGL(k_bucket_sort, dim3((uint32_t)K), dim3(kBlock), sort_lds, st, codes, off, h->d_table, B,
+                         nbpad, sortedf, blist, nbk, err + 1);
+    }
     tm.mark();  // 4
     PHOBIC_HIP(hipGetLastError());
   }
@@ -1696,7 +1822,8 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   PHOBIC_HIP(hipMemcpyAsync(htotp, d64, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipStreamSynchronize(st));
   if (hinfo[0] & (1u << PHOBIC_E_CAPACITY))
-    return fail(PHOBIC_E_CAPACITY, "a group of partitions exceeds the LDS of the bucket-sort workgroup");
+    return fail(PHOBIC_E_CAPACITY, wide ? "a bucket holds 65536 or more keys"
+                                        : "a group of partitions exceeds the LDS of the bucket-sort workgroup");
   if (part_offsets_out) {  // hashing and partitioning only
     PHOBIC_HIP(hipMemcpyAsync(part_offsets_out, off, (K + 1) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
     PHOBIC_HIP(hipStreamSynchronize(st));
@@ -1709,7 +1836,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   h->info.max_partition_keys = max_nj;
   h->info.max_bucket_keys = hmaxb;
   h->info.partition_path = coarse_path ? 0u : 1u;
-  if (max_m > kMaxTableSlots)
+  if (!wide && max_m > kMaxTableSlots)
     return fail(PHOBIC_E_CAPACITY, "a partition needs " + std::to_string(max_m) + " slots; the device path holds " +
                                        std::to_string(kMaxTableSlots));
 
@@ -1739,10 +1866,13 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   sa.f2_words = up4((2 * mm + 127) / 32 + 1);
   sa.scr_words = up4((mm + 31) / 32 + 1);
   sa.rb_cap = up4(mb) + 4;
-  sa.bl_cap = up4(B);
+  sa.bl_cap = wide ? 0u : up4(B);  // wide: bucket list and pilots in global memory
   sa.cm_cap = (mb + 63) / 64 + 1;
   sa.max_m = mm;
+  sa.wide = wide ? 1u : 0u;
   sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
+  if (wide && sa.wave_lds > max_lds_per_group())
+    return fail(PHOBIC_E_CAPACITY, "a partition of " + std::to_string(mm) + " slots does not fit the LDS of one workgroup");
   sa.owner = nullptr;
   sa.Kbase = nullptr;
   sa.Kt = nullptr;
@@ -2331,6 +2461,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   sa.bl_cap = up4(B);
   sa.cm_cap = (mb + 63) / 64 + 1;
   sa.max_m = mm;
+  sa.wide = 0;
   sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
   sa.owner = owner;
   sa.Kbase = d_Kbase;

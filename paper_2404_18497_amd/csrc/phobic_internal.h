@@ -22,6 +22,11 @@ namespace phobic {
 constexpr uint32_t kMaxPartitionKeys = 8192;  // n_j
 constexpr uint32_t kMaxTableSlots = 16384;    // m_j (alpha < 1 enlarges n_j)
 constexpr uint32_t kMaxBuckets = 2048;        // B
+// Wide partitions (beyond the three limits above) take a path that keeps only the slot bitmaps and
+// the current bucket's positions in LDS, one workgroup per partition; the LDS of one workgroup then
+// bounds m_j (and the bucket sort's B), and the position encoding of the search m_j < 2^19.
+constexpr uint32_t kWideMaxBuckets = 65535;
+constexpr uint64_t kWideMaxTableSlots = 1ULL << 19;
 constexpr uint32_t kTableIntervals = 2048;    // bucket-function table: 2048 intervals, 2049 points
 // Select samples of the unary stream, one 64-bit entry per kSelBlock ones: entry s holds the position
 // of one number kSelBlock s in its low 32 bits and, for k = 1, 2, 3, the distance from there to one
@@ -98,6 +103,16 @@ void fill_query_args(phobic_mphf* h);
 // repeated builds then reuse pages instead of mapping fresh ones.  Released with hipFreeAsync.
 constexpr uint64_t kPoolKeepBytes = 1ULL << 30;
 hipError_t pool_alloc(void** p, size_t bytes, hipStream_t st);
+
+// LDS one workgroup may use on the current device (bytes).
+size_t max_lds_per_group();
+// Lets `kernel` launch with `bytes` of dynamic LDS (beyond the default limit where one applies).
+template <typename F>
+hipError_t allow_lds(F kernel, size_t bytes) {
+  hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) (void)hipGetLastError();  // not needed on every runtime: the launch reports real errors
+  return hipSuccess;
+}
 
 // ---------------------------------------------------------------------------------------------
 // Device helpers.

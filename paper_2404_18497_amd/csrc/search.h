@@ -28,6 +28,7 @@ struct SearchArgs {
   uint32_t bl_cap;        // 32-bit bucket-list entries (multiple of 4); also the size of the pilot row
   uint32_t cm_cap;        // 64-bit collision masks
   uint32_t max_m;         // the largest table (slots) of the launch
+  uint32_t wide;          // 1: bucket list and pilot row in global memory (wide partitions, one MPHF)
   uint32_t wave_lds;      // bytes of LDS per wavefront (multiple of 16): F2, scratch, positions,
                           // bucket list, pilot row, collision masks
   // several MPHFs at once: partition J belongs to MPHF owner[J], whose partitions start at

@@ -40,6 +40,7 @@ __global__ void k_queue_reset(unsigned long long* q) {
 // between equal fingerprints means the bucket can never be placed: PHOBIC_E_DUPLICATE.
 // ---------------------------------------------------------------------------------------------
 constexpr uint32_t kSmallBucket = 24;
+constexpr uint32_t kSeedGroups = 8;  // seeds tried at once by a small bucket after its first one
 
 
 
@@ -148,8 +149,10 @@ __device__ __forceinline__ void note_failure(const SearchArgs& a, uint64_t j, ui
 // the scan), small ones (2 .. kSmallBucket keys; a repeat shows while marking) and single keys (no
 // repeat possible; seed 0 always finds a free slot).  Seed-0 positions come from the fingerprint
 // windows, hashed once per window instead of once per bucket.  kMulti: some table of the launch
-// has more than 4096 slots, so a displacement scan may need several passes.
-template <bool kMulti>
+// has more than 4096 slots, so a displacement scan may need several passes.  kWide: the bucket list
+// is read from global memory through 64-entry register windows and pilots are written to the
+// global row directly (partitions whose lists do not fit the LDS; one MPHF).
+template <bool kMulti, bool kWide>
 __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, uint32_t lane) {
   uint32_t* scr = F2 + a.f2_words;
   uint32_t* rbuf = scr + a.scr_words;
@@ -166,10 +169,35 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   }
   for (uint32_t w = lane; w < a.scr_words; w += 64) scr[w] = 0;
   const uint32_t nb = uniform(a.nbk[j]);
-  for (uint32_t x = lane; x < nb; x += 64) bl[x] = a.blist[j * a.B + x];
-  for (uint32_t x = lane; x < a.B; x += 64) pil[x] = 0;  // empty buckets keep pilot 0
+  const uint32_t* gbl = a.blist + j * a.B;
+  uint32_t bw0 = 0, bw1 = 0, bbase = 0;  // kWide: entries bbase + lane and bbase + 64 + lane
+  if (kWide) {
+    for (uint32_t x = lane; x < a.B; x += 64) a.pilots[j * a.B + x] = 0;  // empty buckets keep pilot 0
+    __threadfence_block();  // the zeros land before any pilot of this row
+    bw0 = lane < nb ? gbl[lane] : 0u;
+    bw1 = 64 + lane < nb ? gbl[64 + lane] : 0u;
+  } else {
+    for (uint32_t x = lane; x < nb; x += 64) bl[x] = gbl[x];
+    for (uint32_t x = lane; x < a.B; x += 64) pil[x] = 0;  // empty buckets keep pilot 0
+  }
   wave_sync();
   const char* F2b = (const char*)F2;
+  // bucket entry r (size << 16 | bucket) of the processing order; r never decreases
+  auto bucket_entry = [&](uint32_t r) -> uint32_t {
+    if (!kWide) return uniform(bl[r]);
+    if (r >= bbase + 64) {
+      bbase += 64;
+      bw0 = bw1;
+      bw1 = bbase + 64 + lane < nb ? gbl[bbase + 64 + lane] : 0u;
+    }
+    return __builtin_amdgcn_readlane(bw0, r - bbase);
+  };
+  auto set_pilot = [&](uint32_t bid, uint32_t p) {
+    if (kWide)
+      a.pilots[j * a.B + bid] = p;
+    else
+      pil[bid] = p;
+  };
 
   // this lane's displacement window of the first pass (d0 = 0): its bits below m, its byte offset
   const uint32_t dl0 = lane * 64;
@@ -268,7 +296,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
 
   // ---- big buckets: every seed's positions are checked for repeats first --------------------
   for (; r < nb; r++) {
-    const uint32_t e = uniform(bl[r]);
+    const uint32_t e = bucket_entry(r);
     const uint32_t bid = e & 0xFFFF, sz = e >> 16;
     if (sz <= kSmallBucket) break;
     advance();
@@ -302,7 +330,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         const uint32_t t2 = t + m;
         atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
       }
-      if (lane == 0) pil[bid] = s * m + d_found;
+      if (lane == 0) set_pilot(bid, s * m + d_found);
       wave_sync();
       break;
     }
@@ -315,7 +343,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   // ---- small buckets (2 .. kSmallBucket keys): a repeat shows while marking ------------------
   if (!overflow) {
     for (; r < nb; r++) {
-      const uint32_t e = uniform(bl[r]);
+      const uint32_t e = bucket_entry(r);
       const uint32_t bid = e & 0xFFFF, sz = e >> 16;
       if (sz < 2) break;
       advance();
@@ -368,7 +396,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
           const uint32_t t2 = t + m;
           atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
         }
-        if (lane == 0) pil[bid] = s * m + d_found;
+        if (lane == 0) set_pilot(bid, s * m + d_found);
         wave_sync();
         break;
       }
@@ -382,7 +410,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   // ---- single keys: seed 0, the first free slot at or after the key's position ---------------
   if (!overflow) {
     for (; r < nb; r++) {
-      const uint32_t bid = uniform(bl[r]) & 0xFFFF;
+      const uint32_t bid = bucket_entry(r) & 0xFFFF;
       advance();
       const uint32_t r0 = __builtin_amdgcn_readlane(p0w0, o - wbase);
       o += 1;
@@ -418,7 +446,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       if (lane < 2) {  // lane 0 the slot's bit, lane 1 its copy m bits further
         const uint32_t tt = t + lane * m;
         atomicAnd(&F2[tt >> 5], ~(1u << (tt & 31)));
-        if (lane == 0) pil[bid] = d_found;
+        if (lane == 0) set_pilot(bid, d_found);
       }
       wave_sync();
     }
@@ -426,7 +454,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
 
   if (overflow) {  // the partition has failed: only look for equal fingerprints in the rest
     for (; r < nb; r++) {
-      const uint32_t sz = uniform(bl[r]) >> 16;
+      const uint32_t sz = bucket_entry(r) >> 16;
       advance();
       keys = a.fp + kb + o;
       const uint64_t f0 = key_fp();
@@ -442,7 +470,9 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
     return;
   }
   wave_sync();
-  if (a.owner) {  // several MPHFs: MPHF t's pilots, encoder-major, at B Kbase_t (zero-filled before)
+  if (kWide) {
+    // the pilots are in place
+  } else if (a.owner) {  // several MPHFs: MPHF t's pilots, encoder-major, at B Kbase_t (zero-filled before)
     const uint32_t t = a.owner[j];
     const uint64_t jb = a.Kbase[t], kt = a.Kt[t];
     for (uint32_t x = lane; x < a.B; x += 64) {
@@ -469,7 +499,16 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(8, 
   const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const uint64_t j = (uint64_t)blockIdx.x * kWaves + wave;
   if (j >= a.K) return;
-  search_partition<kMulti>(a, j, lds32 + (size_t)wave * (a.wave_lds / 4), lane);
+  search_partition<kMulti, false>(a, j, lds32 + (size_t)wave * (a.wave_lds / 4), lane);
+}
+
+// Wide partitions: one wavefront per workgroup and partition, with the LDS it needs (up to what one
+// workgroup may hold).
+__global__ __launch_bounds__(64) void k_search_wide(SearchArgs a) {
+  extern __shared__ __align__(16) uint32_t lds32[];
+  const uint64_t j = blockIdx.x;
+  if (j >= a.K) return;
+  search_partition<true, true>(a, j, lds32, threadIdx.x & 63);
 }
 
 // Persistent: every wavefront takes `grab` partitions at a time from the queue until none is left.
@@ -485,7 +524,7 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(8, 
     if (item >= a.K) break;
     const uint64_t end = min((uint64_t)item + a.grab, a.K);
     for (uint64_t j = item; j < end; j++) {
-      search_partition<kMulti>(a, j, F2, lane);
+      search_partition<kMulti, false>(a, j, F2, lane);
       wave_sync();
     }
   }
@@ -540,6 +579,12 @@ hipError_t launch_search_m(SearchArgs& sa, uint64_t items, const phobic_search_c
 }
 
 hipError_t launch_search(SearchArgs& sa, uint64_t items, hipStream_t st, unsigned long long* queue) {
+  if (sa.wide) {
+    sa.queue = nullptr;
+    (void)allow_lds(k_search_wide, sa.wave_lds);
+    hipLaunchKernelGGL(k_search_wide, dim3((uint32_t)items), dim3(64), sa.wave_lds, st, sa);
+    return hipGetLastError();
+  }
   const phobic_search_config cfg = search_config();
   // tables of more than 4096 slots need scans of several passes
   return sa.max_m > 4096 ? launch_search_m<true>(sa, items, cfg, st, queue)

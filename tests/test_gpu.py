@@ -117,6 +117,34 @@ def test_bucket_function_parity(torch, fn, lam, alpha, coding):
     assert np.array_equal(h.query_u64(_dev(torch, keys)).cpu().numpy().view(np.uint64), r.query_u64(keys))
 
 
+@pytest.mark.parametrize("P,lam,alpha,coding", [(10_000, 7.0, (1, 1), "rice"), (50_000, 7.0, (1, 1), "compact"),
+                                                 (200_000, 7.0, (1, 1), "rice"), (50_000, 6.0, (99, 100), "rice"),
+                                                 (2500, 1.0, (1, 1), "rice")])
+def test_wide_partition_parity(torch, P, lam, alpha, coding):
+    """Partitions beyond the LDS of the per-partition workgroups (more than 8192 keys or 2048
+    buckets): global bucket counts and a search with the bucket list and pilots in global memory.
+    Pilots, image and queries against the oracle, for 1M keys at P = 10K, 50K and 200K (lambda 7),
+    alpha 0.99 at P = 50K, and P = 2500 at lambda 1 (B = 2500 buckets)."""
+    keys = synth.u64_keys(1_000_000, 51)
+    _say("wide partitions", P, lam, alpha, coding)
+    g, r = _both(torch, keys, lam=lam, P=P, alpha=alpha, coding=coding)
+    if P >= 50_000 or g.B > 2048:  # 10K-key partitions still fit the coarse bins of one partition
+        assert g.build_info()["partition_path"] == 1
+    _check_same(torch, g, r, keys)
+
+
+def test_wide_partition_strings(torch):
+    buf, offs = synth.ascii_strings(400_000, 52)
+    _say("wide partitions, strings")
+    gp = binding.params(partition_size=40_000, lam=7.0, keep_pilots=True)
+    g = binding.build_str(torch.from_numpy(buf).cuda(), _dev(torch, offs), gp)
+    r = oracle.build_str(buf, offs, oracle.params(partition_size=40_000, lam=7.0), threads=8)
+    assert np.array_equal(g.pilots(), r.pilots())
+    assert np.array_equal(g.serialize(), r.image())
+    pos = g.query_str(torch.from_numpy(buf).cuda(), _dev(torch, offs)).cpu().numpy().view(np.uint64)
+    assert np.array_equal(pos, r.query_str(buf, offs))
+
+
 @pytest.mark.parametrize("c", [0, 1, 16, 179, 358])
 def test_mixed_coding_parity(torch, c):
     """Mixed interleaved coding (Sec. 4.1): the first c of B = 358 encoders Compact, the rest Rice;
@@ -233,8 +261,8 @@ def test_errors(torch):
         with pytest.raises(oracle.OracleError) as e:
             oracle.build_u64(dup, oracle.params(lam=9.0, pilot_limit=lim))
         assert e.value.code == binding.E_DUPLICATE
-    with pytest.raises(binding.PhobicError) as e:
-        binding.build_u64(_dev(torch, keys), binding.params(lam=0.5, partition_size=2500))
+    with pytest.raises(binding.PhobicError) as e:  # B = 62500 buckets: beyond one workgroup's LDS
+        binding.build_u64(_dev(torch, keys), binding.params(lam=0.04, partition_size=2500))
     assert e.value.code == binding.E_CAPACITY
     # the oracle agrees on the first three
     with pytest.raises(oracle.OracleError) as e:
