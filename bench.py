@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--lam", type=float, default=7.0)
     ap.add_argument("--coding", default="rice", choices=["rice", "compact"])
+    ap.add_argument("--n-compact", type=int, default=0, help="leading Compact encoders (mixed coding)")
     ap.add_argument("--batch", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
@@ -230,8 +231,8 @@ def headline(args):
         return _timed(torch, lambda: binding.build_u64(dk, prm), queries, steps, warmup)
 
     log(f"timing {args.steps} steps")
-    ms_per_step, build_ms, query_ms, infos, bits = u64_run(binding.params(lam=args.lam, coding=args.coding),
-                                                           args.steps, args.warmup)
+    ms_per_step, build_ms, query_ms, infos, bits = u64_run(
+        binding.params(lam=args.lam, coding=args.coding, n_compact=args.n_compact), args.steps, args.warmup)
     phase = _phases(infos)
     bits /= n
     nlaunch = (n + batch - 1) // batch
@@ -277,10 +278,11 @@ def headline(args):
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": f"{n} distinct uniform u64 keys (seed 1), P 2500, lambda {args.lam:g}, alpha 1, "
-                               f"interleaved {args.coding}; {n} uniform lookups (seed 2) in batches of {batch} "
-                               f"on {len(qstreams)} streams",
+                               f"interleaved {args.coding}"
+                               + (f" with the first {args.n_compact} encoders Compact" if args.n_compact else "")
+                               + f"; {n} uniform lookups (seed 2) in batches of {batch} on {len(qstreams)} streams",
                    "n_keys": n, "lambda": args.lam, "partition_size": 2500, "coding": args.coding,
-                   "query_batch": batch},
+                   "n_compact": args.n_compact, "query_batch": batch},
         "build_ns_per_key": round(build_ms * 1e6 / n, 4),
         "query_ns_per_key": round(query_ms * 1e6 / n, 4),
         "bits_per_key": round(bits, 4),
@@ -586,7 +588,8 @@ def psweep_mode(args):
         rows.append({"P": P, "K": h.K, "B": h.B, "build_ms": round(ms, 3), "build_ns_per_key": round(ms * 1e6 / n, 4),
                      "search_ms": round(info["search_ms"], 3), "partition_path": info["partition_path"],
                      "max_partition_keys": info["max_partition_keys"], "bits_per_key": round(h.size_bits() / n, 4),
-                     "pilot_bits_per_key_ic_rice": round(ic / n, 4), "pilot_bits_per_key_mono_rice": round(mono / n, 4)})
+                     "pilot_bits_per_key_ic_rice": round(ic / n, 4), "pilot_bits_per_key_mono_rice": round(mono / n, 4),
+                     "phases_ms": {k: round(v, 3) for k, v in _phases([info]).items()}})
         log(json.dumps(rows[-1]))
         h.close()
     out = {"metric": "partition-size sweep: build ns/key, bits/key, interleaved vs mono Rice pilot bits/key",

@@ -17,7 +17,6 @@ namespace phobic {
 
 namespace {
 thread_local std::string g_last_error;
-uint32_t host_bit_length_pub(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
 }
 
 void set_error(const std::string& msg) { g_last_error = msg; }
@@ -84,14 +83,40 @@ void bucket_table(double lambda, uint32_t P, uint32_t an, uint32_t ad, uint32_t 
 
 // Golomb-Rice parameter by Kiely's rule for a geometric source of mean mu (Sec. 4.1):
 // b = max(0, 1 + floor(log2(ln(phi - 1) / ln(mu / (mu + 1))))).
-uint32_t rice_parameter(uint64_t sum, uint64_t count) {
-  if (sum == 0 || count == 0) return 0;
-  const double mu = (double)sum / (double)count;
+static uint32_t rice_of_mean(double mu) {
   const double phi = (1.0 + std::sqrt(5.0)) / 2.0;
   double b = 1.0 + std::floor(std::log2(std::log(phi - 1.0) / std::log(mu / (mu + 1.0))));
   if (b < 0.0) b = 0.0;
   if (b > 32.0) b = 32.0;
   return (uint32_t)b;
+}
+
+uint32_t rice_parameter(uint64_t sum, uint64_t count) {
+  if (sum == 0 || count == 0) return 0;
+  return rice_of_mean((double)sum / (double)count);
+}
+
+// mu_t = the smallest positive double with rice_of_mean(mu) >= t + 1, by bisection over the bit
+// patterns of positive doubles (ordered like their values, and the formula does not decrease with mu).
+const RiceThresholds& rice_thresholds() {
+  static RiceThresholds th;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    auto as_double = [](uint64_t bits) {
+      double d;
+      std::memcpy(&d, &bits, 8);
+      return d;
+    };
+    for (uint32_t t = 0; t < 32; t++) {
+      uint64_t lo = 1, hi = 0x4340000000000000ULL;  // 2^53, where the parameter is 32
+      while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (rice_of_mean(as_double(mid)) >= t + 1) hi = mid; else lo = mid + 1;
+      }
+      th.mu[t] = as_double(lo);
+    }
+  });
+  return th;
 }
 
 // Device copies of bucket-function tables, one per (device, lambda, P, alpha); they live until the
@@ -183,36 +208,13 @@ phobic_status upload_table(phobic_mphf* h, hipStream_t st) {
 // Header words of an image; the section layout follows from the sizes (see the format notes).
 std::vector<uint64_t> make_header(uint64_t n, uint64_t K, uint32_t B, const phobic_params& prm, uint64_t total,
                                   int64_t dmin, uint32_t woff, uint64_t data_bits, uint64_t unary_bits, uint64_t R) {
-  const bool rice = prm.coding == PHOBIC_IC_RICE;
-  const uint32_t c = rice ? prm.n_compact : 0;  // leading Compact encoders of a mixed image
-  const uint64_t nremap = total - n;
-  const uint32_t wremap = n > 1 ? host_bit_length_pub(n - 1) : 0;
-  const uint64_t nsel = rice ? (K * (B - c) + kSelBlock - 1) / kSelBlock : 0;
   std::vector<uint64_t> hdr(kHeaderWords, 0);
-  hdr[kHMagic] = kMagic;
-  hdr[kHN] = n;
-  hdr[kHK] = K;
-  hdr[kHB] = B;
-  hdr[kHP] = prm.partition_size;
-  std::memcpy(&hdr[kHLambda], &prm.lambda, 8);
-  hdr[kHAlpha] = (uint64_t)prm.alpha_num | ((uint64_t)prm.alpha_den << 32);
-  hdr[kHCoding] = prm.coding | ((uint64_t)prm.bucket_function << 8);  // coding, bucket function
-  hdr[kHSeed] = prm.hash_seed;
-  hdr[kHTotal] = total;
-  hdr[kHDmin] = (uint64_t)dmin;
-  hdr[kHWoff] = woff;
-  hdr[kHSecOff] = kHeaderWords;
-  hdr[kHSecEnc] = hdr[kHSecOff] + ((K + 1) * woff + 63) / 64 + 1;
-  hdr[kHSecData] = hdr[kHSecEnc] + B + 1;
-  hdr[kHSecUnary] = hdr[kHSecData] + (data_bits + 63) / 64 + 1;
-  hdr[kHSecSel] = hdr[kHSecUnary] + (rice ? (unary_bits + 63) / 64 + 1 : 0);
-  hdr[kHSecRemap] = hdr[kHSecSel] + (rice ? nsel + 1 : 0);
-  hdr[kHWremap] = wremap;
-  hdr[kHNremap] = nremap;
-  hdr[kHUbits] = rice ? unary_bits : 0;
-  hdr[kHWords] = hdr[kHSecRemap] + (nremap ? (nremap * wremap + 63) / 64 + 1 : 0);
-  hdr[kHR] = R;
-  hdr[kHNcompact] = c;
+  uint64_t lambda_bits;
+  std::memcpy(&lambda_bits, &prm.lambda, 8);
+  fill_header(hdr.data(), n, K, B, prm.partition_size, lambda_bits,
+              (uint64_t)prm.alpha_num | ((uint64_t)prm.alpha_den << 32),
+              prm.coding | ((uint64_t)prm.bucket_function << 8), prm.hash_seed, total, dmin, woff, data_bits,
+              unary_bits, R, prm.coding == PHOBIC_IC_RICE ? prm.n_compact : 0);
   return hdr;
 }
 

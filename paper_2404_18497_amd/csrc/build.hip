@@ -115,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_hash_count_str(const uint8_t* __rest
     uint64_t hi, lo;
     hash_key_str(bytes + a, b - a, seed, hi, lo);
     stage[i] = make_ulonglong2(hi, lo);
-    atomicAdd(&cnt[__umul64hi(hi, K)], 1u);
+    if (K) atomicAdd(&cnt[__umul64hi(hi, K)], 1u);  // K = 0: hashing only (the counts come later)
   }
 }
 
@@ -126,6 +126,51 @@ __global__ __launch_bounds__(kBlock) void k_scatter_codes(const ulonglong2* __re
     ulonglong2 c = stage[i];
     uint64_t j = __umul64hi(c.x, K);
     codes[off[j] + atomicAdd(&cur[j], 1u)] = c;
+  }
+}
+
+// Few partitions (K <= kLdsParts): per-key global atomics on K counters contend, so each workgroup
+// takes a contiguous chunk of the keys, counts its partitions in LDS, and adds or reserves them with
+// one global atomic per (workgroup, partition); the scatter then ranks its keys in LDS inside the
+// reserved ranges.  kCodes: the input is the staged (hi, lo) codes of strings.
+constexpr uint32_t kLdsParts = 12288;
+
+template <bool kCodes>
+__device__ __forceinline__ ulonglong2 general_code(const uint64_t* keys, const ulonglong2* stage, uint64_t i,
+                                                   uint64_t seed) {
+  if (kCodes) return stage[i];
+  uint64_t hi, lo;
+  hash_key_u64(keys[i], seed, hi, lo);
+  return make_ulonglong2(hi, lo);
+}
+
+template <bool kCodes, bool kScatter>
+__global__ __launch_bounds__(kBlock) void k_general_lds(const uint64_t* __restrict__ keys,
+                                                        const ulonglong2* __restrict__ stage, uint64_t n,
+                                                        uint64_t per, uint64_t seed, uint64_t K,
+                                                        const uint64_t* __restrict__ off, uint32_t* __restrict__ cnt,
+                                                        ulonglong2* __restrict__ codes) {
+  extern __shared__ __align__(16) uint32_t hist[];  // [K]
+  const uint64_t c0 = blockIdx.x * per, c1 = min(n, c0 + per);
+  for (uint32_t j = threadIdx.x; j < K; j += kBlock) hist[j] = 0;
+  __syncthreads();
+  for (uint64_t i = c0 + threadIdx.x; i < c1; i += kBlock)
+    atomicAdd(&hist[__umul64hi(general_code<kCodes>(keys, stage, i, seed).x, K)], 1u);
+  __syncthreads();
+  // counting: add the chunk's counts; scatter: reserve the chunk's ranges (cnt is the cursor)
+  for (uint32_t j = threadIdx.x; j < K; j += kBlock) {
+    const uint32_t c = hist[j];
+    if (c) {
+      const uint32_t b = atomicAdd(&cnt[j], c);
+      if (kScatter) hist[j] = b;
+    }
+  }
+  if (!kScatter) return;
+  __syncthreads();
+  for (uint64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
+    const ulonglong2 c = general_code<kCodes>(keys, stage, i, seed);
+    const uint64_t j = __umul64hi(c.x, K);
+    codes[off[j] + atomicAdd(&hist[j], 1u)] = c;
   }
 }
 
@@ -824,8 +869,13 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(4, 
   const uint32_t ghere = (uint32_t)min<uint64_t>(G, jend - j0);
   const uint64_t base = cbase[c];  // inside this launch's code array
   const uint32_t ns = (uint32_t)(cbase[c + 1] - base);
-  if (ns > seg_cap) {
+  if (ns > seg_cap) {  // the build fails; its partitions are left empty (the last one spans the bin)
     if (tid == 0) atomicOr(&info[0], 1u << PHOBIC_E_CAPACITY);
+    if (tid < ghere) {
+      off[j0 + tid] = kbase + base;
+      nbk[j0 + tid] = 0;
+    }
+    if (tid == 0 && j0 + ghere == jend) off[jend] = kbase + base + ns;
     return;
   }
   for (uint32_t x = tid; x < span; x += kSegThreads) cnt[x] = 0;
@@ -1582,8 +1632,21 @@ struct BuildInput {
   uint64_t n;
 };
 
+// Bound on the largest bucket of a partition of about P keys: bucket 0 is the largest in
+// expectation (the bucket function is convex), P x0 keys with x0 the hash range it covers, plus
+// seven standard deviations.
+static uint32_t bucket_size_bound(const phobic_params& prm, uint32_t B, uint64_t part_bound) {
+  std::vector<uint64_t> T(kTableIntervals + 1);
+  bucket_table(prm.lambda, prm.partition_size, prm.alpha_num, prm.alpha_den, prm.bucket_function, T.data());
+  uint32_t k = 1;
+  while (k < kTableIntervals && (unsigned __int128)T[k] * B < ((unsigned __int128)1 << 32)) k++;
+  const double e0 = (double)prm.partition_size * (double)k / kTableIntervals;
+  const double b = e0 + 7.0 * std::sqrt(e0) + 16.0;
+  return (uint32_t)std::min<double>(b, (double)part_bound);
+}
+
 phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipStream_t st, phobic_mphf** out,
-                         uint64_t* part_offsets_out, uint64_t* part_codes_out) {
+                         uint64_t* part_offsets_out, uint64_t* part_codes_out, bool exact_sizes = false) {
   if (out) *out = nullptr;
   uint32_t B = 0;
   phobic_status vs = validate_params(params, &B);
@@ -1768,11 +1831,20 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, cnt, K + 1, 0u);
     hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, dinfo, (uint64_t)8, (uint64_t)0);
     tm.mark();  // 0
-    if (!str)
-      hipLaunchKernelGGL(k_hash_count_u64, dim3(grid_for(n)), dim3(kBlock), 0, st, in.keys, n, prm.hash_seed, K, cnt);
-    else
+    const bool lds_parts = K <= kLdsParts;  // few partitions: LDS counts per chunk of keys
+    const uint32_t chunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(2048, (n + 8191) / 8192));
+    const uint64_t per = std::max<uint64_t>(1, (n + chunks - 1) / chunks);
+    if (str)  // strings are hashed once into the staging array
       hipLaunchKernelGGL(k_hash_count_str, dim3(grid_for(n)), dim3(kBlock), 0, st, in.bytes, in.offs, n,
-                         prm.hash_seed, K, stage, cnt);
+                         prm.hash_seed, lds_parts ? (uint64_t)0 : K, stage, cnt);
+    if (lds_parts && str)
+      hipLaunchKernelGGL((k_general_lds<true, false>), dim3(chunks), dim3(kBlock), K * sizeof(uint32_t), st,
+                         in.keys, stage, n, per, prm.hash_seed, K, off, cnt, codes);
+    else if (lds_parts)
+      hipLaunchKernelGGL((k_general_lds<false, false>), dim3(chunks), dim3(kBlock), K * sizeof(uint32_t), st,
+                         in.keys, stage, n, per, prm.hash_seed, K, off, cnt, codes);
+    else if (!str)
+      hipLaunchKernelGGL(k_hash_count_u64, dim3(grid_for(n)), dim3(kBlock), 0, st, in.keys, n, prm.hash_seed, K, cnt);
     tm.mark();  // 1
     hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(1024), 0, st, cnt, K, an, ad, off, toff, dinfo);
     tm.mark();  // 2
@@ -1786,7 +1858,13 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
       return fail(PHOBIC_E_CAPACITY, "a partition needs " + std::to_string(old_info[1]) +
                                          " slots; the device path holds fewer than " +
                                          std::to_string(kWideMaxTableSlots));
-    if (!str)
+    if (lds_parts && str)
+      hipLaunchKernelGGL((k_general_lds<true, true>), dim3(chunks), dim3(kBlock), K * sizeof(uint32_t), st, in.keys,
+                         stage, n, per, prm.hash_seed, K, off, cnt, codes);
+    else if (lds_parts)
+      hipLaunchKernelGGL((k_general_lds<false, true>), dim3(chunks), dim3(kBlock), K * sizeof(uint32_t), st,
+                         in.keys, stage, n, per, prm.hash_seed, K, off, cnt, codes);
+    else if (!str)
       hipLaunchKernelGGL(k_scatter_u64, dim3(grid_for(n)), dim3(kBlock), 0, st, in.keys, n, prm.hash_seed, K, off,
                          cnt, codes);
     else
@@ -1818,23 +1896,39 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   uint64_t* htotp;
   PHOBIC_HIP(S.host(&hinfo, 4));
   PHOBIC_HIP(S.host(&htotp, 1));
-  PHOBIC_HIP(hipMemcpyAsync(hinfo, err, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(htotp, d64, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipStreamSynchronize(st));
-  if (hinfo[0] & (1u << PHOBIC_E_CAPACITY))
-    return fail(PHOBIC_E_CAPACITY, wide ? "a bucket holds 65536 or more keys"
-                                        : "a group of partitions exceeds the LDS of the bucket-sort workgroup");
-  if (part_offsets_out) {  // hashing and partitioning only
-    PHOBIC_HIP(hipMemcpyAsync(part_offsets_out, off, (K + 1) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+  // Minimal coarse-path builds size the search from bounds known before the data (partitions of at
+  // most P + 7 sqrt(P) + 16 keys, buckets within seven standard deviations of the largest expected
+  // one: exceeded about once in 10^7 builds of 10^8 keys), so the host does not wait for the
+  // bucketing; a partition beyond the bounds is flagged by the search and the build repeats with
+  // the exact sizes.
+  const bool early = coarse_path && an == ad && !part_offsets_out && !exact_sizes;
+  uint64_t max_nj, max_m, total;
+  uint32_t hmaxb;
+  if (early) {
+    const double P = (double)prm.partition_size;
+    max_nj = std::min<uint64_t>((uint64_t)std::ceil(P + 7.0 * std::sqrt(P) + 16.0), std::max<uint64_t>(n, 1));
+    max_m = max_nj;
+    total = n;
+    hmaxb = bucket_size_bound(prm, B, max_nj);
+  } else {
+    PHOBIC_HIP(hipMemcpyAsync(hinfo, err, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    PHOBIC_HIP(hipMemcpyAsync(htotp, d64, sizeof(uint64_t), hipMemcpyDeviceToHost, st));
     PHOBIC_HIP(hipStreamSynchronize(st));
-    return PHOBIC_OK;
+    if (hinfo[0] & (1u << PHOBIC_E_CAPACITY))
+      return fail(PHOBIC_E_CAPACITY, wide ? "a bucket holds 65536 or more keys"
+                                          : "a group of partitions exceeds the LDS of the bucket-sort workgroup");
+    if (part_offsets_out) {  // hashing and partitioning only
+      PHOBIC_HIP(hipMemcpyAsync(part_offsets_out, off, (K + 1) * sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+      PHOBIC_HIP(hipStreamSynchronize(st));
+      return PHOBIC_OK;
+    }
+    max_nj = coarse_path ? hinfo[2] : old_info[0];
+    max_m = coarse_path ? (an != ad ? hinfo[3] : max_nj) : old_info[1];
+    total = coarse_path ? (an != ad ? *htotp : n) : old_info[2];
+    hmaxb = hinfo[1];
+    h->info.max_partition_keys = max_nj;
+    h->info.max_bucket_keys = hmaxb;
   }
-  const uint64_t max_nj = coarse_path ? hinfo[2] : old_info[0];
-  const uint64_t max_m = coarse_path ? (an != ad ? hinfo[3] : max_nj) : old_info[1];
-  const uint64_t total = coarse_path ? (an != ad ? *htotp : n) : old_info[2];
-  const uint32_t hmaxb = hinfo[1];
-  h->info.max_partition_keys = max_nj;
-  h->info.max_bucket_keys = hmaxb;
   h->info.partition_path = coarse_path ? 0u : 1u;
   if (!wide && max_m > kMaxTableSlots)
     return fail(PHOBIC_E_CAPACITY, "a partition needs " + std::to_string(max_m) + " slots; the device path holds " +
@@ -1869,6 +1963,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   sa.bl_cap = wide ? 0u : up4(B);  // wide: bucket list and pilots in global memory
   sa.cm_cap = (mb + 63) / 64 + 1;
   sa.max_m = mm;
+  sa.max_bucket = mb;
   sa.wide = wide ? 1u : 0u;
   sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
   if (wide && sa.wave_lds > max_lds_per_group())
@@ -1877,9 +1972,16 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   sa.Kbase = nullptr;
   sa.Kt = nullptr;
   sa.fail_part = nullptr;
+  sa.order = nullptr;
   unsigned long long* queue;
   PHOBIC_HIP(S.get(&queue, 1));
   tm.mark();  // 5
+  if (!wide && K > 1) {  // costly partitions first
+    uint32_t *order, *oscr;
+    PHOBIC_HIP(S.get(&order, K));
+    PHOBIC_HIP(S.get(&oscr, 512));
+    PHOBIC_HIP(order_partitions(sa, order, oscr, st));
+  }
   PHOBIC_HIP(launch_search(sa, K, st, queue));
   tm.mark();  // 6
 
@@ -1908,11 +2010,9 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   hipLaunchKernelGGL(k_offset_stats, dim3(grid_for(K + 1, kBlock, 64)), dim3(kBlock), 0, st, toff, K, R, dmm);
   PHOBIC_HIP(hipGetLastError());
   uint64_t* hstats;  // pinned
-  uint32_t* herrp;
   PHOBIC_HIP(S.host(&hstats, nstat));
-  PHOBIC_HIP(S.host(&herrp, 1));
   PHOBIC_HIP(hipMemcpyAsync(hstats, stats, nstat * 8, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(herrp, err, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(hinfo, err, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   {  // while the device searches: take and give back a block of the likely image size (3 bits/key
      // and 40 per partition), so that the image allocation after the round trip finds mapped memory
      // in the pool instead of mapping pages on the critical path
@@ -1926,7 +2026,15 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   const uint64_t* hsh = hstats;
   const long long* hmm = (const long long*)(hstats + (uint64_t)B * 33);
   const uint32_t* hmax = (const uint32_t*)(hstats + (uint64_t)B * 33 + 2);
-  const uint32_t herr = *herrp;
+  const uint32_t herr = hinfo[0];
+  if (early) {
+    if (herr & (1u << PHOBIC_E_CAPACITY))
+      return fail(PHOBIC_E_CAPACITY, "a group of partitions exceeds the LDS of the bucket-sort workgroup");
+    if (herr & (1u << kErrResize))  // a partition or bucket beyond the bounds: size exactly
+      return build_impl(in, params, st, out, nullptr, nullptr, true);
+    h->info.max_partition_keys = hinfo[2];
+    h->info.max_bucket_keys = hinfo[1];
+  }
   if (herr & (1u << PHOBIC_E_DUPLICATE)) return fail(PHOBIC_E_DUPLICATE, "two keys of one bucket share their 64-bit fingerprint");
   if (herr & (1u << PHOBIC_E_PILOT_OVERFLOW))
     return fail(PHOBIC_E_PILOT_OVERFLOW, "a bucket needs a pilot above " + std::to_string(limit));
@@ -2166,6 +2274,59 @@ __global__ __launch_bounds__(256) void k_batch_offstats(const uint64_t* __restri
     mm[2 * t] = lmin;
     mm[2 * t + 1] = lmax;
   }
+}
+
+// Encoder widths of every (MPHF t, encoder i): Kiely's parameter of the mean (Rice encoders) from
+// the thresholds the host found with the same formula, else the bit length of the maximum.
+__global__ __launch_bounds__(kBlock) void k_batch_widths(const BatchDesc* __restrict__ d, uint32_t count, uint32_t B,
+                                                         const uint64_t* __restrict__ sum,
+                                                         const uint32_t* __restrict__ mx, uint32_t rice, uint32_t ncomp,
+                                                         RiceThresholds th, uint8_t* __restrict__ width) {
+  for (uint64_t it = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; it < (uint64_t)count * B;
+       it += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t t = (uint32_t)(it / B), i = (uint32_t)(it % B);
+    const uint32_t v = mx[it];
+    width[it] = (uint8_t)(rice && i >= ncomp ? rice_from_thresholds(sum[it], d[t].K, th) : (v ? 32 - __clz(v) : 0));
+  }
+}
+
+// Everything an image's packing needs that depends on the whole MPHF, one thread per MPHF: encoder
+// words (data bit base << 8 | width), unary bases, the header, and the image's size in words.
+struct BatchPlan {
+  uint64_t lambda_bits, alpha_word, coding_word, seed;
+  uint32_t P, ncomp;
+};
+
+__global__ __launch_bounds__(kBlock) void k_batch_plan(const BatchDesc* __restrict__ d, uint32_t count, uint32_t B,
+                                                       const uint8_t* __restrict__ width,
+                                                       const uint64_t* __restrict__ ubits,
+                                                       const long long* __restrict__ mm, BatchPlan pl,
+                                                       uint64_t* __restrict__ encw, uint64_t* __restrict__ ubase,
+                                                       uint64_t* __restrict__ hdrs, uint64_t* __restrict__ words,
+                                                       uint32_t* __restrict__ err) {
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const BatchDesc e = d[t];
+  const bool rice = (pl.coding_word & 0xFF) == PHOBIC_IC_RICE;
+  uint64_t data_bits = 0, unary_bits = 0;
+  for (uint32_t i = 0; i < B; i++) {
+    const uint64_t it = (uint64_t)t * B + i;
+    const uint32_t w = width[it];
+    encw[it] = (data_bits << 8) | w;
+    data_bits += (uint64_t)w * e.K;
+    ubase[it] = unary_bits;
+    if (rice && i >= pl.ncomp) unary_bits += ubits[it];  // Compact encoders have no unary part
+  }
+  if (rice && unary_bits > 0xFFFFFFFFULL) atomicOr(&err[0], 1u << PHOBIC_E_CAPACITY);
+  const long long dmin = mm[2 * t], dmax = mm[2 * t + 1];
+  const uint64_t span = (uint64_t)(dmax - dmin);
+  const uint32_t woff = span ? 64 - __clzll(span) : 0;
+  uint64_t* h = hdrs + (uint64_t)t * kHeaderWords;
+  uint64_t hv[kHeaderWords];
+  fill_header(hv, e.n, e.K, B, pl.P, pl.lambda_bits, pl.alpha_word, pl.coding_word, pl.seed, e.n, dmin, woff,
+              data_bits, unary_bits, e.R, pl.ncomp);
+  for (uint32_t x = 0; x < kHeaderWords; x++) h[x] = hv[x];
+  words[t] = hv[kHWords];
 }
 
 // One workgroup per MPHF: header and encoder words into its image.
@@ -2461,38 +2622,61 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   sa.bl_cap = up4(B);
   sa.cm_cap = (mb + 63) / 64 + 1;
   sa.max_m = mm;
+  sa.max_bucket = mb;
   sa.wide = 0;
   sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + 15) & ~15u;
   sa.owner = owner;
   sa.Kbase = d_Kbase;
   sa.Kt = d_Kt;
   sa.fail_part = (unsigned long long*)(err + 4);
+  sa.order = nullptr;
   tm.mark();  // 2
   PHOBIC_HIP(launch_search(sa, Ktot, st, queue));
   tm.mark();  // 3
 
-  // encoding: statistics, parameters on the host, then packing
+  // encoding: statistics, then every encoder's parameter and every MPHF's header planned on the
+  // device; the host learns only the image sizes (one round trip) to allocate them
   const uint64_t items = (uint64_t)count * B;
-  uint64_t* sum;
+  const bool rice = prm.coding == PHOBIC_IC_RICE;
+  const uint32_t ncomp = rice ? prm.n_compact : 0;  // mixed coding: encoders below it are Compact
+  uint64_t *sum, *dub, *dh, *de, *du, *dib, *dwords;
   uint32_t* mx;
+  uint8_t* dw;
   long long* dmm;
   PHOBIC_HIP(S.get(&sum, items));
   PHOBIC_HIP(S.get(&mx, items));
   PHOBIC_HIP(S.get(&dmm, 2 * (uint64_t)count));
+  PHOBIC_HIP(S.get(&dw, items));
+  PHOBIC_HIP(S.get(&dub, items));
+  PHOBIC_HIP(S.get(&dh, (uint64_t)count * kHeaderWords));
+  PHOBIC_HIP(S.get(&de, items));
+  PHOBIC_HIP(S.get(&du, items));
+  PHOBIC_HIP(S.get(&dib, count));
+  PHOBIC_HIP(S.get(&dwords, count));
   const uint32_t item_groups = (uint32_t)((items + 3) / 4), mphf_groups = (count + 3) / 4;
   hipLaunchKernelGGL(k_batch_stats, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, sum, mx);
   hipLaunchKernelGGL(k_batch_offstats, dim3(mphf_groups), dim3(256), 0, st, off, d_desc, count, dmm);
+  hipLaunchKernelGGL(k_batch_widths, dim3(grid_for(items)), dim3(kBlock), 0, st, d_desc, count, B, sum, mx,
+                     (uint32_t)rice, ncomp, rice_thresholds(), dw);
+  if (rice)
+    hipLaunchKernelGGL(k_batch_unary, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, dw, dub);
+  BatchPlan plan;
+  std::memcpy(&plan.lambda_bits, &prm.lambda, 8);
+  plan.alpha_word = (uint64_t)prm.alpha_num | ((uint64_t)prm.alpha_den << 32);
+  plan.coding_word = prm.coding | ((uint64_t)prm.bucket_function << 8);
+  plan.seed = prm.hash_seed;
+  plan.P = prm.partition_size;
+  plan.ncomp = ncomp;
+  hipLaunchKernelGGL(k_batch_plan, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d_desc, count, B, dw, dub,
+                     dmm, plan, de, du, dh, dwords, err);
   PHOBIC_HIP(hipGetLastError());
-  uint64_t* hsum;  // pinned
-  uint32_t *hmx, *herr;
-  long long* hmm;
-  PHOBIC_HIP(S.host(&hsum, items));
-  PHOBIC_HIP(S.host(&hmx, items));
-  PHOBIC_HIP(S.host(&hmm, 2 * (uint64_t)count));
+  uint64_t *hwords, *ibase, *hdrs;  // pinned
+  uint32_t* herr;
+  PHOBIC_HIP(S.host(&hwords, (uint64_t)count));
+  PHOBIC_HIP(S.host(&ibase, (uint64_t)count));
+  PHOBIC_HIP(S.host(&hdrs, (uint64_t)count * kHeaderWords));
   PHOBIC_HIP(S.host(&herr, 6));
-  PHOBIC_HIP(hipMemcpyAsync(hsum, sum, items * 8, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(hmx, mx, items * 4, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipMemcpyAsync(hmm, dmm, 2 * (size_t)count * 8, hipMemcpyDeviceToHost, st));
+  PHOBIC_HIP(hipMemcpyAsync(hwords, dwords, (size_t)count * 8, hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipMemcpyAsync(herr, err, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipStreamSynchronize(st));
   if (herr[0] & ((1u << PHOBIC_E_DUPLICATE) | (1u << PHOBIC_E_PILOT_OVERFLOW))) {
@@ -2502,61 +2686,15 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
     return fail(dup ? PHOBIC_E_DUPLICATE : PHOBIC_E_PILOT_OVERFLOW,
                 "MPHF " + std::to_string(t) + (dup ? ": two keys share their hash code" : ": pilot overflow"));
   }
-  const bool rice = prm.coding == PHOBIC_IC_RICE;
-  const uint32_t ncomp = rice ? prm.n_compact : 0;  // mixed coding: encoders below it are Compact
-  uint8_t* hw;  // pinned
-  uint64_t* hub;
-  PHOBIC_HIP(S.host(&hw, items));
-  PHOBIC_HIP(S.host(&hub, items));
-  parallel_for(items, [&](uint64_t it) {
-    const bool enc_rice = rice && it % B >= ncomp;
-    hw[it] = (uint8_t)(enc_rice ? rice_parameter(hsum[it], desc[it / B].K) : bit_length(hmx[it]));
-    hub[it] = 0;
-  });
-  if (rice) {
-    uint8_t* dw;
-    uint64_t* dub;
-    PHOBIC_HIP(S.get(&dw, items));
-    PHOBIC_HIP(S.get(&dub, items));
-    PHOBIC_HIP(hipMemcpyAsync(dw, hw, items, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_batch_unary, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, dw, dub);
-    PHOBIC_HIP(hipMemcpyAsync(hub, dub, items * 8, hipMemcpyDeviceToHost, st));
-    PHOBIC_HIP(hipStreamSynchronize(st));
-  }
-  uint64_t *hdrs, *encw, *ubase, *ibase;  // pinned
-  PHOBIC_HIP(S.host(&hdrs, (uint64_t)count * kHeaderWords));
-  PHOBIC_HIP(S.host(&encw, items));
-  PHOBIC_HIP(S.host(&ubase, items));
-  PHOBIC_HIP(S.host(&ibase, (uint64_t)count));
+  if (herr[0] & (1u << PHOBIC_E_CAPACITY)) return fail(PHOBIC_E_CAPACITY, "a unary stream exceeds 2^32 bits");
   uint64_t total_words = 0;
   for (uint32_t t = 0; t < count; t++) {
-    uint64_t data_bits = 0, unary_bits = 0;
-    for (uint32_t i = 0; i < B; i++) {
-      const uint64_t it = (uint64_t)t * B + i;
-      encw[it] = (data_bits << 8) | hw[it];
-      data_bits += (uint64_t)hw[it] * desc[t].K;
-      ubase[it] = unary_bits;
-      if (i >= ncomp) unary_bits += hub[it];  // Compact encoders have no unary part
-    }
-    if (rice && unary_bits > 0xFFFFFFFFULL) return fail(PHOBIC_E_CAPACITY, "a unary stream exceeds 2^32 bits");
-    const long long dmin = hmm[2 * t], dmax = hmm[2 * t + 1];
-    const std::vector<uint64_t> h = make_header(desc[t].n, desc[t].K, B, prm, desc[t].n, dmin,
-                                                bit_length((uint64_t)(dmax - dmin)), data_bits, unary_bits, desc[t].R);
-    std::copy(h.begin(), h.end(), hdrs + (size_t)t * kHeaderWords);
     ibase[t] = total_words;
-    total_words += h[kHWords];
+    total_words += hwords[t];
   }
   void* big = nullptr;
   PHOBIC_HIP(pool_alloc(&big, total_words * 8, st));
   std::shared_ptr<void> shared(big, [](void* p) { (void)hipFreeAsync(p, nullptr); });
-  uint64_t *dh, *de, *du, *dib;
-  PHOBIC_HIP(S.get(&dh, (uint64_t)count * kHeaderWords));
-  PHOBIC_HIP(S.get(&de, items));
-  PHOBIC_HIP(S.get(&du, items));
-  PHOBIC_HIP(S.get(&dib, count));
-  PHOBIC_HIP(hipMemcpyAsync(dh, hdrs, (size_t)count * kHeaderWords * 8, hipMemcpyHostToDevice, st));
-  PHOBIC_HIP(hipMemcpyAsync(de, encw, items * 8, hipMemcpyHostToDevice, st));
-  PHOBIC_HIP(hipMemcpyAsync(du, ubase, items * 8, hipMemcpyHostToDevice, st));
   PHOBIC_HIP(hipMemcpyAsync(dib, ibase, (size_t)count * 8, hipMemcpyHostToDevice, st));
   uint64_t* bufw = (uint64_t*)big;
   hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(total_words)), dim3(kBlock), 0, st, bufw, total_words, (uint64_t)0);
@@ -2568,6 +2706,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
     hipLaunchKernelGGL(k_batch_sel_fill, dim3(count), dim3(256), 0, st, d_desc, B, dh, dib, bufw);
   PHOBIC_HIP(hipGetLastError());
   tm.mark();  // 4
+  PHOBIC_HIP(hipMemcpyAsync(hdrs, dh, (size_t)count * kHeaderWords * 8, hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipStreamSynchronize(st));
   phobic_build_info info{};
   info.bucket_sort_ms = tm.ms(0, 1);  // hashing, partitioning and bucketing of all chunks

@@ -88,6 +88,61 @@ phobic_status fail(phobic_status s, const std::string& msg);
                             std::string(#call) + ": " + hipGetErrorString(e_));                    \
   } while (0)
 
+// Header words of an image from its sizes: the section layout follows from them (the same on the
+// host and in device planning kernels).  coding_word = coding | bucket function << 8; c = leading
+// Compact encoders of a mixed Rice image.
+__host__ __device__ inline void fill_header(uint64_t* hdr, uint64_t n, uint64_t K, uint32_t B, uint32_t P,
+                                            uint64_t lambda_bits, uint64_t alpha_word, uint64_t coding_word,
+                                            uint64_t seed, uint64_t total, int64_t dmin, uint32_t woff,
+                                            uint64_t data_bits, uint64_t unary_bits, uint64_t R, uint32_t c) {
+  const bool rice = (coding_word & 0xFF) == PHOBIC_IC_RICE;
+  const uint64_t nremap = total - n;
+  uint32_t wremap = 0;
+  for (uint64_t v = n > 1 ? n - 1 : 0; v; v >>= 1) wremap++;  // bit length of n - 1
+  const uint64_t nsel = rice ? (K * (B - c) + kSelBlock - 1) / kSelBlock : 0;
+  for (uint32_t x = 0; x < kHeaderWords; x++) hdr[x] = 0;
+  hdr[kHMagic] = kMagic;
+  hdr[kHN] = n;
+  hdr[kHK] = K;
+  hdr[kHB] = B;
+  hdr[kHP] = P;
+  hdr[kHLambda] = lambda_bits;
+  hdr[kHAlpha] = alpha_word;
+  hdr[kHCoding] = coding_word;
+  hdr[kHSeed] = seed;
+  hdr[kHTotal] = total;
+  hdr[kHDmin] = (uint64_t)dmin;
+  hdr[kHWoff] = woff;
+  hdr[kHSecOff] = kHeaderWords;
+  hdr[kHSecEnc] = hdr[kHSecOff] + ((K + 1) * woff + 63) / 64 + 1;
+  hdr[kHSecData] = hdr[kHSecEnc] + B + 1;
+  hdr[kHSecUnary] = hdr[kHSecData] + (data_bits + 63) / 64 + 1;
+  hdr[kHSecSel] = hdr[kHSecUnary] + (rice ? (unary_bits + 63) / 64 + 1 : 0);
+  hdr[kHSecRemap] = hdr[kHSecSel] + (rice ? nsel + 1 : 0);
+  hdr[kHWremap] = wremap;
+  hdr[kHNremap] = nremap;
+  hdr[kHUbits] = rice ? unary_bits : 0;
+  hdr[kHWords] = hdr[kHSecRemap] + (nremap ? (nremap * wremap + 63) / 64 + 1 : 0);
+  hdr[kHR] = R;
+  hdr[kHNcompact] = rice ? c : 0;
+}
+
+// Kiely's Golomb-Rice parameter depends on the mean mu = sum / count only and does not decrease with
+// it, so it is fixed by 32 thresholds on mu: b = #{t : mu >= mu_t}.  The thresholds are found once
+// on the host from the same double formula (and checked at both sides of each), so a device that
+// divides in IEEE double picks exactly the parameter the host would.
+struct RiceThresholds {
+  double mu[32];
+};
+const RiceThresholds& rice_thresholds();
+__host__ __device__ inline uint32_t rice_from_thresholds(uint64_t sum, uint64_t count, const RiceThresholds& t) {
+  if (sum == 0 || count == 0) return 0;
+  const double mu = (double)sum / (double)count;
+  uint32_t b = 0;
+  while (b < 32 && mu >= t.mu[b]) b++;
+  return b;
+}
+
 // Host planning shared by build and deserialize.
 phobic_status validate_params(const phobic_params* p, uint32_t* B);
 uint64_t num_partitions(uint64_t n, uint32_t P);

@@ -27,7 +27,8 @@ struct SearchArgs {
   uint32_t rb_cap;        // 32-bit position entries (multiple of 4)
   uint32_t bl_cap;        // 32-bit bucket-list entries (multiple of 4); also the size of the pilot row
   uint32_t cm_cap;        // 64-bit collision masks
-  uint32_t max_m;         // the largest table (slots) of the launch
+  uint32_t max_m;         // the largest table (slots) the LDS layout holds
+  uint32_t max_bucket;    // the largest bucket (keys) the LDS layout holds
   uint32_t wide;          // 1: bucket list and pilot row in global memory (wide partitions, one MPHF)
   uint32_t wave_lds;      // bytes of LDS per wavefront (multiple of 16): F2, scratch, positions,
                           // bucket list, pilot row, collision masks
@@ -40,10 +41,19 @@ struct SearchArgs {
   unsigned long long* queue;
   uint32_t grab;
   unsigned long long* fail_part;  // non-null: receives the lowest failing partition index (atomic min)
+  const uint32_t* order;          // non-null: the launch takes partitions in this order (one MPHF)
 };
 
 // Launches the search over `items` partitions (sa.K of them in the partition index space) on the
 // stream with the configured launch shape; `queue` is one device word used by the persistent shape.
 hipError_t launch_search(SearchArgs& sa, uint64_t items, hipStream_t st, unsigned long long* queue);
+
+// Orders the K partitions of one MPHF by an estimate of their search cost, largest first, into
+// order[0 .. K) (scratch: 512 words); sets sa.order.  The order changes no result.
+hipError_t order_partitions(SearchArgs& sa, uint32_t* order, uint32_t* scratch, hipStream_t st);
+
+// Error bit of a partition or bucket larger than the search's LDS layout was sized for (the build
+// then repeats with exact sizes); beyond the phobic_status values.
+constexpr uint32_t kErrResize = 16;
 
 }  // namespace phobic

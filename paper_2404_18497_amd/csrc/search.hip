@@ -162,6 +162,14 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
 
   const uint64_t kb = uniform64(a.off[j]);
   const uint32_t m = uniform((uint32_t)(a.toff[j + 1] - a.toff[j]));
+  {  // the LDS layout was sized from bounds: a larger table or bucket is left to an exact resize
+    const uint32_t nb0 = uniform(a.nbk[j]);
+    const uint32_t big0 = nb0 ? uniform(a.blist[j * a.B]) >> 16 : 0u;
+    if (m > a.max_m || big0 > a.max_bucket) {
+      if (lane == 0) note_failure(a, j, kErrResize);
+      return;
+    }
+  }
   const uint32_t twom = 2 * m;
   for (uint32_t w = lane; w < a.f2_words; w += 64) {
     const uint32_t lo = w * 32;
@@ -492,13 +500,70 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Launch order.  A partition's search time is dominated by per-bucket work (about proportional to
+// its buckets and keys) plus the seeds its biggest buckets need before their positions stop
+// repeating, about exp(k (k - 1) / (2 m)) for a bucket of k keys in m slots.  Starting the costly
+// partitions first shortens the tail of the launch, where fewer and fewer wavefronts run.  The
+// estimate is binned on a log scale (kOrderBins bins, 16 per octave) and the partitions are
+// counting-sorted by bin, largest first; the order inside a bin is arbitrary.
+// ---------------------------------------------------------------------------------------------
+constexpr uint32_t kOrderBins = 256;
+
+__device__ __forceinline__ uint32_t order_bin(const SearchArgs& a, uint64_t j) {
+  const uint32_t nb = a.nbk[j];
+  const uint32_t nj = (uint32_t)(a.off[j + 1] - a.off[j]);
+  const float m = (float)max(1u, (uint32_t)(a.toff[j + 1] - a.toff[j]));
+  float cost = 60.0f * (float)nb + 4.0f * (float)nj + 1.0f;
+  for (uint32_t x = 0; x < nb; x++) {
+    const uint32_t k = a.blist[j * a.B + x] >> 16;
+    if (k < 8) break;  // sizes are non-increasing
+    const float e = min((float)k * (float)(k - 1) / (2.0f * m), 40.0f);
+    cost += (60.0f + 4.0f * (float)k) * (__expf(e) - 1.0f);
+  }
+  const int bin = (int)(__log2f(cost) * 16.0f) - 160;
+  return (uint32_t)min(max(bin, 0), (int)kOrderBins - 1);
+}
+
+__global__ void k_order_clear(uint32_t* __restrict__ hist) { hist[threadIdx.x] = 0; }
+
+__global__ void k_order_count(SearchArgs a, uint32_t* __restrict__ hist) {
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < a.K; j += (uint64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[order_bin(a, j)], 1u);
+}
+
+// hist[b] -> start of bin b when the bins run from the largest estimate down; cursor cleared
+__global__ void k_order_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor) {
+  __shared__ uint32_t v[kOrderBins];
+  const uint32_t t = threadIdx.x;
+  v[t] = hist[kOrderBins - 1 - t];
+  __syncthreads();
+  for (uint32_t d = 1; d < kOrderBins; d <<= 1) {
+    const uint32_t y = t >= d ? v[t - d] : 0u;
+    __syncthreads();
+    v[t] += y;
+    __syncthreads();
+  }
+  hist[kOrderBins - 1 - t] = v[t] - hist[kOrderBins - 1 - t];
+  cursor[t] = 0;
+}
+
+__global__ void k_order_scatter(SearchArgs a, const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
+                                uint32_t* __restrict__ order) {
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < a.K; j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = order_bin(a, j);
+    order[start[b] + atomicAdd(&cursor[b], 1u)] = (uint32_t)j;
+  }
+}
+
 // One wavefront per partition.
 template <int kWaves, bool kMulti>
 __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_search(SearchArgs a) {
   extern __shared__ __align__(16) uint32_t lds32[];
   const uint32_t wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const uint64_t j = (uint64_t)blockIdx.x * kWaves + wave;
-  if (j >= a.K) return;
+  const uint64_t x = (uint64_t)blockIdx.x * kWaves + wave;
+  if (x >= a.K) return;
+  const uint64_t j = a.order ? (uint64_t)uniform(a.order[x]) : x;
   search_partition<kMulti, false>(a, j, lds32 + (size_t)wave * (a.wave_lds / 4), lane);
 }
 
@@ -523,7 +588,8 @@ __global__ __launch_bounds__(64 * kWaves) __attribute__((amdgpu_waves_per_eu(8, 
     item = lane_value64(item, 0);
     if (item >= a.K) break;
     const uint64_t end = min((uint64_t)item + a.grab, a.K);
-    for (uint64_t j = item; j < end; j++) {
+    for (uint64_t x = item; x < end; x++) {
+      const uint64_t j = a.order ? (uint64_t)uniform(a.order[x]) : x;
       search_partition<kMulti, false>(a, j, F2, lane);
       wave_sync();
     }
@@ -576,6 +642,19 @@ hipError_t launch_search_m(SearchArgs& sa, uint64_t items, const phobic_search_c
     case 8: return launch_search_w<8, kMulti>(sa, items, cfg, st, queue);
     default: return launch_search_w<4, kMulti>(sa, items, cfg, st, queue);
   }
+}
+
+hipError_t order_partitions(SearchArgs& sa, uint32_t* order, uint32_t* scratch, hipStream_t st) {
+  uint32_t* hist = scratch;
+  uint32_t* cursor = scratch + kOrderBins;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((sa.K + 255) / 256, 4096);
+  sa.order = nullptr;
+  hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(kOrderBins), 0, st, hist);
+  hipLaunchKernelGGL(k_order_count, dim3(grid), dim3(256), 0, st, sa, hist);
+  hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, st, hist, cursor);
+  hipLaunchKernelGGL(k_order_scatter, dim3(grid), dim3(256), 0, st, sa, (const uint32_t*)hist, cursor, order);
+  sa.order = order;
+  return hipGetLastError();
 }
 
 hipError_t launch_search(SearchArgs& sa, uint64_t items, hipStream_t st, unsigned long long* queue) {
