@@ -1393,31 +1393,111 @@ __global__ __launch_bounds__(kBlock) void k_remap_count(const uint64_t* __restri
   }
 }
 
-// exclusive scans of fc and oc in place, one workgroup
-__global__ __launch_bounds__(1024) void k_scan_pair(uint32_t* __restrict__ fc, uint32_t* __restrict__ oc, uint64_t nw) {
-  __shared__ uint64_t sf[1024], so[1024];
-  const uint32_t t = threadIdx.x;
-  const uint64_t per = (nw + 1023) / 1024;
-  const uint64_t a = min(nw, (uint64_t)t * per), b = min(nw, a + per);
+// Exclusive scans of fc and oc in place, in three steps: per-block sums (kScanBlock words per
+// workgroup), a scan of the block sums by one workgroup, then each block's local scan plus its
+// offset.
+constexpr uint32_t kScanThreads = 1024, kScanPer = 8, kScanBlock = kScanThreads * kScanPer;
+
+__global__ __launch_bounds__(kScanThreads) void k_pair_block_sums(const uint32_t* __restrict__ fc,
+                                                                  const uint32_t* __restrict__ oc, uint64_t nw,
+                                                                  uint64_t* __restrict__ bs) {
+  __shared__ uint64_t wf[kScanThreads / 64], wo[kScanThreads / 64];
+  const uint64_t w0 = (uint64_t)blockIdx.x * kScanBlock;
   uint64_t tf = 0, to = 0;
-  for (uint64_t w = a; w < b; w++) { tf += fc[w]; to += oc[w]; }
+  for (uint32_t x = threadIdx.x; x < kScanBlock; x += kScanThreads) {
+    const uint64_t w = w0 + x;
+    if (w < nw) {
+      tf += fc[w];
+      to += oc[w];
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    tf += __shfl_xor(tf, o);
+    to += __shfl_xor(to, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wf[threadIdx.x >> 6] = tf;
+    wo[threadIdx.x >> 6] = to;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t sf = 0, so = 0;
+    for (uint32_t x = 0; x < kScanThreads / 64; x++) {
+      sf += wf[x];
+      so += wo[x];
+    }
+    bs[2 * (uint64_t)blockIdx.x] = sf;
+    bs[2 * (uint64_t)blockIdx.x + 1] = so;
+  }
+}
+
+// exclusive scan of the nb block sums (pairs) in place, one workgroup
+__global__ __launch_bounds__(kScanThreads) void k_pair_scan_blocks(uint64_t* __restrict__ bs, uint64_t nb) {
+  __shared__ uint64_t sf[kScanThreads], so[kScanThreads];
+  const uint32_t t = threadIdx.x;
+  const uint64_t per = (nb + kScanThreads - 1) / kScanThreads;
+  const uint64_t a = min(nb, (uint64_t)t * per), b = min(nb, a + per);
+  uint64_t tf = 0, to = 0;
+  for (uint64_t x = a; x < b; x++) {
+    tf += bs[2 * x];
+    to += bs[2 * x + 1];
+  }
   sf[t] = tf;
   so[t] = to;
   __syncthreads();
-  for (uint32_t d = 1; d < 1024; d <<= 1) {
-    uint64_t vf = t >= d ? sf[t - d] : 0, vo = t >= d ? so[t - d] : 0;
+  for (uint32_t d = 1; d < kScanThreads; d <<= 1) {
+    const uint64_t vf = t >= d ? sf[t - d] : 0, vo = t >= d ? so[t - d] : 0;
     __syncthreads();
     sf[t] += vf;
     so[t] += vo;
     __syncthreads();
   }
   uint64_t pf = sf[t] - tf, po = so[t] - to;
-  for (uint64_t w = a; w < b; w++) {
-    uint32_t f = fc[w], o = oc[w];
-    fc[w] = (uint32_t)pf;
-    oc[w] = (uint32_t)po;
+  for (uint64_t x = a; x < b; x++) {
+    const uint64_t f = bs[2 * x], o = bs[2 * x + 1];
+    bs[2 * x] = pf;
+    bs[2 * x + 1] = po;
     pf += f;
     po += o;
+  }
+}
+
+// block b: its kScanBlock words scanned locally (kScanPer consecutive words per thread) plus the
+// block's offset from bs
+__global__ __launch_bounds__(kScanThreads) void k_pair_apply(uint32_t* __restrict__ fc, uint32_t* __restrict__ oc,
+                                                             uint64_t nw, const uint64_t* __restrict__ bs) {
+  __shared__ uint64_t sf[kScanThreads], so[kScanThreads];
+  const uint32_t t = threadIdx.x;
+  const uint64_t w0 = (uint64_t)blockIdx.x * kScanBlock + (uint64_t)t * kScanPer;
+  uint32_t f[kScanPer], o[kScanPer];
+  uint64_t tf = 0, to = 0;
+#pragma unroll
+  for (uint32_t x = 0; x < kScanPer; x++) {
+    const bool in = w0 + x < nw;
+    f[x] = in ? fc[w0 + x] : 0u;
+    o[x] = in ? oc[w0 + x] : 0u;
+    tf += f[x];
+    to += o[x];
+  }
+  sf[t] = tf;
+  so[t] = to;
+  __syncthreads();
+  for (uint32_t d = 1; d < kScanThreads; d <<= 1) {
+    const uint64_t vf = t >= d ? sf[t - d] : 0, vo = t >= d ? so[t - d] : 0;
+    __syncthreads();
+    sf[t] += vf;
+    so[t] += vo;
+    __syncthreads();
+  }
+  uint64_t pf = bs[2 * (uint64_t)blockIdx.x] + sf[t] - tf, po = bs[2 * (uint64_t)blockIdx.x + 1] + so[t] - to;
+#pragma unroll
+  for (uint32_t x = 0; x < kScanPer; x++) {
+    if (w0 + x < nw) {
+      fc[w0 + x] = (uint32_t)pf;
+      oc[w0 + x] = (uint32_t)po;
+    }
+    pf += f[x];
+    po += o[x];
   }
 }
 
@@ -2102,7 +2182,12 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     PHOBIC_HIP(S.get(&freeslot, nremap));
     hipLaunchKernelGGL(k_remap_count, dim3(grid_for(taken_words)), dim3(kBlock), 0, st, taken, taken_words, n, total,
                        fc, oc);
-    hipLaunchKernelGGL(k_scan_pair, dim3(1), dim3(1024), 0, st, fc, oc, taken_words);
+    const uint64_t nsb = (taken_words + kScanBlock - 1) / kScanBlock;
+    uint64_t* bsums;
+    PHOBIC_HIP(S.get(&bsums, 2 * nsb));
+    hipLaunchKernelGGL(k_pair_block_sums, dim3((uint32_t)nsb), dim3(kScanThreads), 0, st, fc, oc, taken_words, bsums);
+    hipLaunchKernelGGL(k_pair_scan_blocks, dim3(1), dim3(kScanThreads), 0, st, bsums, nsb);
+    hipLaunchKernelGGL(k_pair_apply, dim3((uint32_t)nsb), dim3(kScanThreads), 0, st, fc, oc, taken_words, bsums);
     hipLaunchKernelGGL(k_remap_free, dim3(grid_for(taken_words)), dim3(kBlock), 0, st, taken, taken_words, n, fc,
                        freeslot);
     hipLaunchKernelGGL(k_remap_fill, dim3(grid_for(nremap)), dim3(kBlock), 0, st, taken, n, total, oc, freeslot,

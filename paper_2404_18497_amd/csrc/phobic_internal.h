@@ -203,21 +203,24 @@ __device__ __forceinline__ void hash_key_u64(uint64_t key, uint64_t seed, uint64
   lo = mix_b(key ^ seed ^ kSqrt2);
 }
 
-// Byte string -> (hi, lo): two chains over little-endian 8-byte words, finished with the length.
+// The nb <= 8 bytes at p as a little-endian word, zero above them, from the aligned 8-byte words
+// that hold them (an aligned word that holds one byte of a buffer lies inside the buffer's pages).
+__device__ __forceinline__ uint64_t load_le_bytes(const uint8_t* p, uint32_t nb) {
+  const uintptr_t addr = (uintptr_t)p;
+  const uint64_t* w = (const uint64_t*)(addr & ~(uintptr_t)7);
+  const uint32_t sh = (uint32_t)(addr & 7);
+  uint64_t v = w[0] >> (8 * sh);
+  if (sh && sh + nb > 8) v |= w[1] << (64 - 8 * sh);
+  return nb >= 8 ? v : (v & ((1ULL << (8 * nb)) - 1));
+}
+
+// Byte string -> (hi, lo): two chains over little-endian 8-byte words (the last one zero-padded),
+// finished with the length.
 __device__ __forceinline__ void hash_key_str(const uint8_t* s, uint64_t len, uint64_t seed, uint64_t& hi,
                                              uint64_t& lo) {
   uint64_t a = seed, b = seed ^ kSqrt2;
-  uint64_t i = 0;
-  for (; i + 8 <= len; i += 8) {
-    uint64_t w = 0;
-#pragma unroll
-    for (int t = 0; t < 8; t++) w |= (uint64_t)s[i + t] << (8 * t);
-    a = mix_a(a ^ w);
-    b = mix_b(b ^ w);
-  }
-  if (i < len) {
-    uint64_t w = 0;
-    for (uint64_t t = 0; i + t < len; t++) w |= (uint64_t)s[i + t] << (8 * t);
+  for (uint64_t i = 0; i < len; i += 8) {
+    const uint64_t w = load_le_bytes(s + i, (uint32_t)min<uint64_t>(8, len - i));
     a = mix_a(a ^ w);
     b = mix_b(b ^ w);
   }
