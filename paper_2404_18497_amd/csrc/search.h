@@ -24,14 +24,14 @@ struct SearchArgs {
   uint32_t B;
   uint32_t f2_words;      // 32-bit words of F2 (multiple of 4)
   uint32_t scr_words;     // 32-bit words of the collision scratch (multiple of 4)
-  uint32_t rb_cap;        // 32-bit position entries (multiple of 4)
+  uint32_t rb_cap;        // 32-bit position entries (multiple of 4, at least kSearchMinPositions)
   uint32_t bl_cap;        // 32-bit bucket-list entries (multiple of 4); also the size of the pilot row
   uint32_t cm_cap;        // 64-bit collision masks
   uint32_t max_m;         // the largest table (slots) the LDS layout holds
   uint32_t max_bucket;    // the largest bucket (keys) the LDS layout holds
   uint32_t wide;          // 1: bucket list and pilot row in global memory (wide partitions, one MPHF)
   uint32_t wave_lds;      // bytes of LDS per wavefront (multiple of 16): F2, scratch, positions,
-                          // bucket list, pilot row, collision masks
+                          // bucket list, pilot row, collision masks, argument context
   // several MPHFs at once: partition J belongs to MPHF owner[J], whose partitions start at
   // Kbase[t] (K_t of them) and whose pilots start at B * Kbase[t]; null for a single MPHF
   const uint32_t* owner;
@@ -51,6 +51,11 @@ hipError_t launch_search(SearchArgs& sa, uint64_t items, hipStream_t st, unsigne
 // Orders the K partitions of one MPHF by an estimate of their search cost, largest first, into
 // order[0 .. K) (scratch: 512 words); sets sa.order.  The order changes no result.
 hipError_t order_partitions(SearchArgs& sa, uint32_t* order, uint32_t* scratch, hipStream_t st);
+
+// The position buffer holds at least one entry per lane (a small bucket's seeds are hashed 64
+// positions at a time), and each wavefront keeps kSearchCtxBytes of argument fields in LDS.
+constexpr uint32_t kSearchMinPositions = 64;
+constexpr uint32_t kSearchCtxBytes = 64;
 
 // Error bit of a partition or bucket larger than the search's LDS layout was sized for (the build
 // then repeats with exact sizes); beyond the phobic_status values.

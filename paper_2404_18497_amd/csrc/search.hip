@@ -40,7 +40,6 @@ __global__ void k_queue_reset(unsigned long long* q) {
 // between equal fingerprints means the bucket can never be placed: PHOBIC_E_DUPLICATE.
 // ---------------------------------------------------------------------------------------------
 constexpr uint32_t kSmallBucket = 24;
-constexpr uint32_t kSeedGroups = 8;  // seeds tried at once by a small bucket after its first one
 
 
 
@@ -137,9 +136,16 @@ __device__ __forceinline__ uint32_t bucket_positions(uint32_t* rbuf, const uint6
   return r0;
 }
 
-__device__ __forceinline__ void note_failure(const SearchArgs& a, uint64_t j, uint32_t status) {
-  atomicOr(a.err, 1u << status);
-  if (a.fail_part) atomicMin(a.fail_part, (unsigned long long)j);
+// Argument fields that only the failure and output paths use, kept in LDS for the partition so that
+// they need no registers during the bucket loops: error word, failing-partition word, pilots,
+// owner, Kbase, Kt, occupancy bitmap, table offsets.
+enum : uint32_t { kCtxErr, kCtxFail, kCtxPilots, kCtxOwner, kCtxKbase, kCtxKt, kCtxTaken, kCtxToff, kCtxWords };
+static_assert(kCtxWords * 8 == kSearchCtxBytes, "context size");
+
+__device__ __forceinline__ void note_failure(const uint64_t* ctx, uint64_t j, uint32_t status) {
+  atomicOr((uint32_t*)ctx[kCtxErr], 1u << status);
+  unsigned long long* fp = (unsigned long long*)ctx[kCtxFail];
+  if (fp) atomicMin(fp, (unsigned long long)j);
 }
 
 // Places every bucket of partition j (global index).  Uniform across the wavefront.
@@ -154,39 +160,59 @@ __device__ __forceinline__ void note_failure(const SearchArgs& a, uint64_t j, ui
 // global row directly (partitions whose lists do not fit the LDS; one MPHF).
 template <bool kMulti, bool kWide>
 __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, uint32_t lane) {
-  uint32_t* scr = F2 + a.f2_words;
-  uint32_t* rbuf = scr + a.scr_words;
+  const uint64_t* const fpa = a.fp;
+  const uint64_t* const offp = a.off;
+  const uint64_t* const toffp = a.toff;
+  const uint32_t* const blistp = a.blist;
+  const uint32_t* const nbkp = a.nbk;
+  const uint32_t f2_words = a.f2_words, scr_words = a.scr_words, bl_cap = a.bl_cap;
+  const uint32_t B = a.B;
+  uint32_t* const pilots_w = kWide ? a.pilots : nullptr;
+  uint32_t* scr = F2 + f2_words;
+  uint32_t* rbuf = scr + scr_words;
   uint32_t* bl = rbuf + a.rb_cap;
-  uint32_t* pil = bl + a.bl_cap;  // the partition's pilots, by bucket index
-  uint64_t* cm = (uint64_t*)(pil + a.bl_cap);
+  uint32_t* pil = bl + bl_cap;  // the partition's pilots, by bucket index
+  uint64_t* cm = (uint64_t*)(pil + bl_cap);
+  uint64_t* ctx = cm + a.cm_cap;
+  if (lane == 0) {
+    ctx[kCtxErr] = (uint64_t)a.err;
+    ctx[kCtxFail] = (uint64_t)a.fail_part;
+    ctx[kCtxPilots] = (uint64_t)a.pilots;
+    ctx[kCtxOwner] = (uint64_t)a.owner;
+    ctx[kCtxKbase] = (uint64_t)a.Kbase;
+    ctx[kCtxKt] = (uint64_t)a.Kt;
+    ctx[kCtxTaken] = (uint64_t)a.taken;
+    ctx[kCtxToff] = (uint64_t)a.toff;
+  }
+  wave_sync();
 
-  const uint64_t kb = uniform64(a.off[j]);
-  const uint32_t m = uniform((uint32_t)(a.toff[j + 1] - a.toff[j]));
+  const uint64_t kb = uniform64(offp[j]);
+  const uint32_t m = uniform((uint32_t)(toffp[j + 1] - toffp[j]));
   {  // the LDS layout was sized from bounds: a larger table or bucket is left to an exact resize
-    const uint32_t nb0 = uniform(a.nbk[j]);
-    const uint32_t big0 = nb0 ? uniform(a.blist[j * a.B]) >> 16 : 0u;
+    const uint32_t nb0 = uniform(nbkp[j]);
+    const uint32_t big0 = nb0 ? uniform(blistp[j * B]) >> 16 : 0u;
     if (m > a.max_m || big0 > a.max_bucket) {
-      if (lane == 0) note_failure(a, j, kErrResize);
+      if (lane == 0) note_failure(ctx, j, kErrResize);
       return;
     }
   }
   const uint32_t twom = 2 * m;
-  for (uint32_t w = lane; w < a.f2_words; w += 64) {
+  for (uint32_t w = lane; w < f2_words; w += 64) {
     const uint32_t lo = w * 32;
     F2[w] = lo + 32 <= twom ? 0xFFFFFFFFu : (lo >= twom ? 0u : ((1u << (twom - lo)) - 1u));
   }
-  for (uint32_t w = lane; w < a.scr_words; w += 64) scr[w] = 0;
-  const uint32_t nb = uniform(a.nbk[j]);
-  const uint32_t* gbl = a.blist + j * a.B;
+  for (uint32_t w = lane; w < scr_words; w += 64) scr[w] = 0;
+  const uint32_t nb = uniform(nbkp[j]);
+  const uint32_t* gbl = blistp + j * B;
   uint32_t bw0 = 0, bw1 = 0, bbase = 0;  // kWide: entries bbase + lane and bbase + 64 + lane
   if (kWide) {
-    for (uint32_t x = lane; x < a.B; x += 64) a.pilots[j * a.B + x] = 0;  // empty buckets keep pilot 0
+    for (uint32_t x = lane; x < B; x += 64) pilots_w[j * B + x] = 0;  // empty buckets keep pilot 0
     __threadfence_block();  // the zeros land before any pilot of this row
     bw0 = lane < nb ? gbl[lane] : 0u;
     bw1 = 64 + lane < nb ? gbl[64 + lane] : 0u;
   } else {
     for (uint32_t x = lane; x < nb; x += 64) bl[x] = gbl[x];
-    for (uint32_t x = lane; x < a.B; x += 64) pil[x] = 0;  // empty buckets keep pilot 0
+    for (uint32_t x = lane; x < B; x += 64) pil[x] = 0;  // empty buckets keep pilot 0
   }
   wave_sync();
   const char* F2b = (const char*)F2;
@@ -202,7 +228,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   };
   auto set_pilot = [&](uint32_t bid, uint32_t p) {
     if (kWide)
-      a.pilots[j * a.B + bid] = p;
+      pilots_w[j * B + bid] = p;
     else
       pil[bid] = p;
   };
@@ -212,20 +238,20 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   const uint64_t acc_first = dl0 < m ? (m - dl0 >= 64 ? ~0ULL : ((1ULL << (m - dl0)) - 1)) : 0ULL;
   const uint32_t loff_first = dl0 < m ? (dl0 >> 3) : 0u;
 
-  const uint32_t nj = uniform((uint32_t)(a.off[j + 1] - kb));
+  const uint32_t nj = uniform((uint32_t)(offp[j + 1] - kb));
   // s m > limit exactly when s > floor(limit / m); limit < 2^32, so every seed tried fits 32 bits.
   // The cap at 2^32 - 2 (which only m = 1 reaches, where the one key takes seed 0) keeps s + 1 from
   // wrapping.
-  const uint32_t smax = m ? (uint32_t)min<uint64_t>(a.limit / m, 0xFFFFFFFEULL) : 0u;
-  const uint32_t dlast = m ? (uint32_t)(a.limit - smax * m) : 0;  // largest d allowed with s = smax
+  const uint32_t smax = uniform(m ? (uint32_t)min<uint64_t>(a.limit / m, 0xFFFFFFFEULL) : 0u);
+  const uint32_t dlast = uniform(m ? (uint32_t)(a.limit - smax * m) : 0);  // largest d allowed with s = smax
 
   // Fingerprints arrive through a sliding window: lane l of win0 holds key wbase + l of the partition
   // (processing order), win1 the next 64.  The keys of consecutive buckets are consecutive, so one
   // load serves many small buckets, and the next window is in flight while the current one is used.
   // p0w0 holds win0's positions under seed 0; p0w1 win1's once a bucket has needed them (p1).
   uint32_t wbase = 0, o = 0;  // o: first key of the current bucket
-  uint64_t win0 = lane < nj ? a.fp[kb + lane] : 0;
-  uint64_t win1 = 64 + lane < nj ? a.fp[kb + 64 + lane] : 0;
+  uint64_t win0 = lane < nj ? fpa[kb + lane] : 0;
+  uint64_t win1 = 64 + lane < nj ? fpa[kb + 64 + lane] : 0;
   uint32_t p0w0 = pos_hash(win0, kPhi64, m), p0w1 = 0;
   bool p1 = false;
   // Moves the windows so that the bucket starting at key o lies in them (its first 64 keys).
@@ -237,19 +263,22 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         wbase += 64;
       } else {  // past both windows (after a big bucket)
         wbase = o;
-        win0 = wbase + lane < nj ? a.fp[kb + wbase + lane] : 0;
+        win0 = wbase + lane < nj ? fpa[kb + wbase + lane] : 0;
         p0w0 = pos_hash(win0, kPhi64, m);
       }
-      win1 = wbase + 64 + lane < nj ? a.fp[kb + wbase + 64 + lane] : 0;
+      win1 = wbase + 64 + lane < nj ? fpa[kb + wbase + 64 + lane] : 0;
       p1 = false;
     }
   };
   // key o + lane's fingerprint (lanes past the bucket get a neighbour's, unused)
-  auto key_fp = [&]() -> uint64_t {
-    const uint32_t widx = o - wbase + lane;
-    const uint64_t f0a = __shfl(win0, (int)(widx & 63)), f0b = __shfl(win1, (int)(widx & 63));
+  auto key_fp_at = [&](uint32_t ob, uint32_t sz) -> uint64_t {
+    const uint32_t widx = ob - wbase + lane;
+    const uint64_t f0a = __shfl(win0, (int)(widx & 63));
+    if (uniform(ob - wbase + sz) <= 64) return f0a;
+    const uint64_t f0b = __shfl(win1, (int)(widx & 63));
     return widx < 64 ? f0a : f0b;
   };
+  auto key_fp = [&](uint32_t sz) -> uint64_t { return key_fp_at(o, sz); };
   // key o + lane's position under seed 0, for a bucket of sz keys
   auto key_p0 = [&](uint32_t sz) -> uint32_t {
     if (o - wbase + sz > 64 && !p1) {  // the bucket reaches into win1
@@ -257,19 +286,21 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       p1 = true;
     }
     const uint32_t widx = o - wbase + lane;
-    const uint32_t pa = __shfl(p0w0, (int)(widx & 63)), pb = __shfl(p0w1, (int)(widx & 63));
+    const uint32_t pa = __shfl(p0w0, (int)(widx & 63));
+    if (uniform(o - wbase + sz) <= 64) return pa;
+    const uint32_t pb = __shfl(p0w1, (int)(widx & 63));
     return widx < 64 ? pa : pb;
   };
 
   // displacement scan: the lowest d such that every key's slot (r + d) mod m is free, for the szp
-  // encoded positions in rbuf.  A pass covers 4096 displacements from d0 (acc: this lane's window
+  // encoded positions at rb.  A pass covers 4096 displacements from d0 (acc: this lane's window
   // bits below m, loff: its byte offset); the first pass covers every m up to 4096, further passes
   // (kMulti) the larger ones.  ~0 when no displacement works.
-  auto scan = [&](uint32_t szp) -> uint32_t {
+  auto scan = [&](const uint32_t* rb, uint32_t szp) -> uint32_t {
     uint32_t d_found = 0xFFFFFFFFu;
     auto scan_pass = [&](uint32_t d0, uint64_t acc, uint32_t loff) {
-      for (uint32_t k = 0; k < szp; k += 4) {
-        const uint4 e4 = *(const uint4*)(rbuf + k);
+      auto four = [&](uint32_t k) {
+        const uint4 e4 = *(const uint4*)(rb + k);
         const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
 #pragma unroll
         for (int t = 0; t < 4; t++) {
@@ -278,9 +309,11 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
           acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, ev[t]) << 32) |
                  __builtin_amdgcn_alignbit(w1, w0, ev[t]);
         }
-        if (__ballot(acc != 0) == 0) break;
-      }
-      const uint64_t bal = __ballot(acc != 0);
+        return uniform64(__ballot(acc != 0));
+      };
+      // szp >= 4: the first four keys, then four at a time while some displacement survives
+      uint64_t bal = four(0);
+      for (uint32_t k = 4; bal != 0 && k < szp; k += 4) bal = four(k);
       if (bal) {
         const uint32_t L = (uint32_t)(__ffsll((long long)bal) - 1);
         const uint64_t accL = lane_value64(acc, L);
@@ -300,7 +333,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
 
   bool overflow = false;
   uint32_t r = 0;
-  const uint64_t* keys = a.fp + kb;  // the current bucket's keys
+  const uint64_t* keys = fpa + kb;  // the current bucket's keys
 
   // ---- big buckets: every seed's positions are checked for repeats first --------------------
   for (; r < nb; r++) {
@@ -308,8 +341,8 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
     const uint32_t bid = e & 0xFFFF, sz = e >> 16;
     if (sz <= kSmallBucket) break;
     advance();
-    keys = a.fp + kb + o;
-    const uint64_t f0 = key_fp();
+    keys = fpa + kb + o;
+    const uint64_t f0 = key_fp(sz);
     o += sz;
     uint64_t wseed = kPhi64;  // the seed's Weyl value (s + 1) phi, kept as a running sum
     for (uint32_t s = 0;; s++, wseed += kPhi64) {
@@ -320,12 +353,12 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       bucket_positions(rbuf, keys, f0, sz, wseed, m, lane);
       if (positions_repeat(scr, rbuf, sz, cm, lane)) {
         if (s == 0 && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
-          if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
+          if (lane == 0) note_failure(ctx, j, PHOBIC_E_DUPLICATE);
           return;
         }
         continue;
       }
-      const uint32_t d_found = scan((sz + 3) & ~3u);
+      const uint32_t d_found = scan(rbuf, (sz + 3) & ~3u);
       if (d_found == 0xFFFFFFFFu) continue;
       if (s == smax && d_found > dlast) {  // p > limit, with s <= smax
         overflow = true;
@@ -349,64 +382,115 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   }
 
   // ---- small buckets (2 .. kSmallBucket keys): a repeat shows while marking ------------------
+  // Seed 0 takes its positions from the fingerprint window.  Later seeds are hashed G at a time:
+  // the lanes form G groups of S lanes (S the smallest of 4, 8, 16, 32 that holds the bucket), lane
+  // x holding key x mod S (the last key past the bucket) under seed s + x / S, so one hash evaluation
+  // serves G seeds; group i's positions are entries i S .. i S + S of rbuf.
   if (!overflow) {
     for (; r < nb; r++) {
       const uint32_t e = bucket_entry(r);
       const uint32_t bid = e & 0xFFFF, sz = e >> 16;
       if (sz < 2) break;
       advance();
-      keys = a.fp + kb + o;
-      const uint64_t f0 = key_fp();
-      const uint32_t p0 = key_p0(sz);
+      const uint32_t ob = o;
+      keys = fpa + kb + o;
       o += sz;
       const uint32_t szp = (sz + 3) & ~3u;
-      uint64_t wseed = kPhi64;
-      for (uint32_t s = 0;; s++, wseed += kPhi64) {
-        if (s > smax) {
-          overflow = true;
-          break;
-        }
-        // positions: seed 0 from the window, later seeds hashed; padded with the last entry
-        const uint32_t rmine = s == 0 ? p0 : pos_hash(f0, wseed, m);
-        const uint32_t last = __builtin_amdgcn_readlane(rmine, sz - 1);
-        if (lane < szp) rbuf[lane] = enc_pos(lane < sz ? rmine : last);
-        wave_sync();
-        const uint32_t d_found = scan(szp);
-        // Without an admissible displacement at seed 0 the bucket is checked for equal keys here,
-        // so that they are reported as such and not as a pilot overflow.
-        const bool unplaced0 = d_found == 0xFFFFFFFFu || (s == smax && d_found > dlast);
-        if (unplaced0 && s == 0 && positions_repeat(scr, rbuf, sz, cm, lane) &&
-            equal_fingerprints(keys, rbuf, sz, cm, lane)) {
-          if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
-          return;
-        }
-        if (d_found == 0xFFFFFFFFu) continue;
-        if (s == smax && d_found > dlast) {
-          overflow = true;
-          break;
-        }
-        // mark the slots; two keys on one slot show as a slot this bucket has already cleared
-        bool mine = false;
-        uint32_t t = rmine + d_found;
+      // marks the slots of the keys whose positions are at rb for displacement d; false (and the
+      // table unchanged) when two of them share a slot
+      auto place = [&](const uint32_t* rb, uint32_t d) -> bool {
+        uint32_t t = dec_pos(rb[lane < sz ? lane : 0u]) + d;
         if (t >= m) t -= m;
+        bool mine = true;
         if (lane < sz) mine = (atomicAnd(&F2[t >> 5], ~(1u << (t & 31))) >> (t & 31)) & 1u;
         wave_sync();
-        if (__ballot(lane < sz && !mine)) {
-          if (mine) atomicOr(&F2[t >> 5], 1u << (t & 31));  // undo
+        if (uniform64(__ballot(!mine))) {
+          if (lane < sz && mine) atomicOr(&F2[t >> 5], 1u << (t & 31));  // undo
           wave_sync();
-          if (s == 0 && positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
-            if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
-            return;
-          }
-          continue;
+          return false;
         }
         if (lane < sz) {
           const uint32_t t2 = t + m;
           atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
         }
-        if (lane == 0) set_pilot(bid, s * m + d_found);
+        return true;
+      };
+      auto dup0 = [&]() -> bool {  // after a failure at seed 0 (positions in rbuf): equal keys?
+        return positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane);
+      };
+      // seed 0
+      {
+        const uint32_t widx = ob - wbase + (lane < sz ? lane : sz - 1);
+        const uint32_t pa = __shfl(p0w0, (int)(widx & 63));
+        uint32_t p0 = pa;
+        if (uniform(ob - wbase + sz) > 64) {
+          if (!p1) {
+            p0w1 = pos_hash(win1, kPhi64, m);
+            p1 = true;
+          }
+          const uint32_t pb = __shfl(p0w1, (int)(widx & 63));
+          p0 = widx < 64 ? pa : pb;
+        }
+        rbuf[lane] = enc_pos(p0);
         wave_sync();
-        break;
+        const uint32_t d = scan(rbuf, szp);
+        const bool in_limit = d != 0xFFFFFFFFu && !(smax == 0 && d > dlast);
+        if (in_limit && place(rbuf, d)) {
+          if (lane == 0) set_pilot(bid, d);
+          wave_sync();
+          continue;
+        }
+        if (dup0()) {
+          if (lane == 0) note_failure(ctx, j, PHOBIC_E_DUPLICATE);
+          return;
+        }
+        if (smax == 0) {
+          overflow = true;
+          r++;
+          break;
+        }
+      }
+      // seeds 1, 2, ...: G at a time
+      const uint32_t lgS = sz <= 4 ? 2u : (sz <= 8 ? 3u : (sz <= 16 ? 4u : 5u));
+      const uint32_t S = 1u << lgS, G = 64u >> lgS;
+      const uint32_t kx = lane & (S - 1);
+      uint64_t fS;  // fingerprint of key min(kx, sz - 1) of the bucket
+      {
+        const uint32_t widx = ob - wbase + (kx < sz ? kx : sz - 1);
+        const uint64_t fa = __shfl(win0, (int)(widx & 63));
+        fS = fa;
+        if (uniform(ob - wbase + sz) > 64) {
+          const uint64_t fb = __shfl(win1, (int)(widx & 63));
+          fS = widx < 64 ? fa : fb;
+        }
+      }
+      // Weyl value of this lane's seed, (s + 1 + x / S) phi, advanced by G phi per batch
+      uint64_t wl = (uint64_t)(2 + (lane >> lgS)) * kPhi64;
+      const uint64_t gstep = (uint64_t)G * kPhi64;
+      bool done = false;
+      for (uint32_t s = 1; !done; s += G, wl += gstep) {
+        rbuf[lane] = enc_pos(pos_hash(fS, wl, m));
+        wave_sync();
+        for (uint32_t i = 0; i < G; i++) {
+          const uint32_t sd = s + i;
+          if (sd > smax) {
+            overflow = true;
+            break;
+          }
+          const uint32_t* rb = rbuf + i * S;
+          const uint32_t d = scan(rb, szp);
+          if (d == 0xFFFFFFFFu) continue;
+          if (sd == smax && d > dlast) {
+            overflow = true;
+            break;
+          }
+          if (!place(rb, d)) continue;
+          if (lane == 0) set_pilot(bid, sd * m + d);
+          wave_sync();
+          done = true;
+          break;
+        }
+        if (overflow) break;
       }
       if (overflow) {
         r++;
@@ -464,38 +548,41 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
     for (; r < nb; r++) {
       const uint32_t sz = bucket_entry(r) >> 16;
       advance();
-      keys = a.fp + kb + o;
-      const uint64_t f0 = key_fp();
+      keys = fpa + kb + o;
+      const uint64_t f0 = key_fp(sz);
       o += sz;
       if (sz < 2) continue;
       bucket_positions(rbuf, keys, f0, sz, kPhi64, m, lane);
       if (positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
-        if (lane == 0) note_failure(a, j, PHOBIC_E_DUPLICATE);
+        if (lane == 0) note_failure(ctx, j, PHOBIC_E_DUPLICATE);
         return;
       }
     }
-    if (lane == 0) note_failure(a, j, PHOBIC_E_PILOT_OVERFLOW);
+    if (lane == 0) note_failure(ctx, j, PHOBIC_E_PILOT_OVERFLOW);
     return;
   }
   wave_sync();
+  uint32_t* const pilots = (uint32_t*)uniform64(ctx[kCtxPilots]);
+  const uint32_t* const owner = (const uint32_t*)uniform64(ctx[kCtxOwner]);
   if (kWide) {
     // the pilots are in place
-  } else if (a.owner) {  // several MPHFs: MPHF t's pilots, encoder-major, at B Kbase_t (zero-filled before)
-    const uint32_t t = a.owner[j];
-    const uint64_t jb = a.Kbase[t], kt = a.Kt[t];
-    for (uint32_t x = lane; x < a.B; x += 64) {
+  } else if (owner) {  // several MPHFs: MPHF t's pilots, encoder-major, at B Kbase_t (zero-filled before)
+    const uint32_t t = owner[j];
+    const uint64_t jb = ((const uint64_t*)uniform64(ctx[kCtxKbase]))[t], kt = ((const uint64_t*)uniform64(ctx[kCtxKt]))[t];
+    for (uint32_t x = lane; x < B; x += 64) {
       const uint32_t v = pil[x];
-      if (v) a.pilots[(uint64_t)a.B * jb + (uint64_t)x * kt + (j - jb)] = v;
+      if (v) pilots[(uint64_t)B * jb + (uint64_t)x * kt + (j - jb)] = v;
     }
   } else {  // one MPHF: row j of the partition-major array, written whole
-    for (uint32_t x = lane; x < a.B; x += 64) a.pilots[j * a.B + x] = pil[x];
+    for (uint32_t x = lane; x < B; x += 64) pilots[j * B + x] = pil[x];
   }
-  if (a.taken) {
-    const uint64_t tb = a.toff[j];
+  uint64_t* const taken = (uint64_t*)uniform64(ctx[kCtxTaken]);
+  if (taken) {
+    const uint64_t tb = ((const uint64_t*)uniform64(ctx[kCtxToff]))[j];
     for (uint32_t w = lane; w * 32 < m; w += 64) {
       const uint32_t nbits = min(32u, m - w * 32);
       const uint32_t busy = ~F2[w] & (nbits == 32 ? 0xFFFFFFFFu : ((1u << nbits) - 1));
-      put_bits_atomic(a.taken, tb + (uint64_t)w * 32, busy, nbits);
+      put_bits_atomic(taken, tb + (uint64_t)w * 32, busy, nbits);
     }
   }
 }
