@@ -396,10 +396,10 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       keys = fpa + kb + o;
       o += sz;
       const uint32_t szp = (sz + 3) & ~3u;
-      // marks the slots of the keys whose positions are at rb for displacement d; false (and the
-      // table unchanged) when two of them share a slot
-      auto place = [&](const uint32_t* rb, uint32_t d) -> bool {
-        uint32_t t = dec_pos(rb[lane < sz ? lane : 0u]) + d;
+      // marks the slots of the keys (lane k < sz: key k at position pos) for displacement d; false
+      // (and the table unchanged) when two of them share a slot
+      auto place = [&](uint32_t pos, uint32_t d) -> bool {
+        uint32_t t = pos + d;
         if (t >= m) t -= m;
         bool mine = true;
         if (lane < sz) mine = (atomicAnd(&F2[t >> 5], ~(1u << (t & 31))) >> (t & 31)) & 1u;
@@ -435,7 +435,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         wave_sync();
         const uint32_t d = scan(rbuf, szp);
         const bool in_limit = d != 0xFFFFFFFFu && !(smax == 0 && d > dlast);
-        if (in_limit && place(rbuf, d)) {
+        if (in_limit && place(p0, d)) {
           if (lane == 0) set_pilot(bid, d);
           wave_sync();
           continue;
@@ -484,7 +484,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
             overflow = true;
             break;
           }
-          if (!place(rb, d)) continue;
+          if (!place(dec_pos(rb[lane < sz ? lane : 0u]), d)) continue;
           if (lane == 0) set_pilot(bid, sd * m + d);
           wave_sync();
           done = true;
