@@ -84,6 +84,11 @@ inline T __shfl(T v, int src, int width = 64) {
   (void)width;
   return emu_exchange(v, (unsigned)src);
 }
+template <typename T>
+inline T __shfl_xor(T v, int mask, int width = 64) {
+  (void)width;
+  return emu_exchange(v, (threadIdx.x & 63) ^ (unsigned)mask);
+}
 inline uint32_t emu_readfirstlane(uint32_t v) { return emu_exchange(v, 0); }
 inline uint32_t emu_readlane(uint32_t v, uint32_t l) {
   if (l > 63) {

@@ -22,7 +22,8 @@ from paper_2404_18497_amd import binding, synth
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SEARCH_SRC = os.path.join(ROOT, "paper_2404_18497_amd", "csrc", "search.hip")
+# EMU_SEARCH_SRC: check another copy of search.hip (a change in progress) with the same cases
+SEARCH_SRC = os.environ.get("EMU_SEARCH_SRC", os.path.join(ROOT, "paper_2404_18497_amd", "csrc", "search.hip"))
 M64 = (1 << 64) - 1
 
 
