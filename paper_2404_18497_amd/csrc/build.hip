@@ -2292,50 +2292,56 @@ __global__ __launch_bounds__(kBlock) void k_batch_owner(const BatchDesc* __restr
   }
 }
 
-__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-  for (int o = 32; o > 0; o >>= 1) v = max(v, (uint64_t)__shfl_xor(v, o));
+// Statistics of every (MPHF t, encoder i) item: 16 lanes per item, 16 items per workgroup (most
+// items hold a few dozen values, so a wavefront per item would spend its time reducing).
+constexpr uint32_t kItemLanes = 16, kItemsPerGroup = 256 / kItemLanes;
+__device__ __forceinline__ uint64_t item_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int o = 1; o < (int)kItemLanes; o <<= 1) v += __shfl_xor(v, o, kItemLanes);
   return v;
 }
 
-// One wavefront per (MPHF t, encoder i): sum and maximum of the K_t pilots of bucket i.
+// sum and maximum of the item's values
 __global__ __launch_bounds__(256) void k_batch_stats(const uint32_t* __restrict__ pilots,
                                                      const BatchDesc* __restrict__ d, uint32_t count, uint32_t B,
                                                      uint64_t* __restrict__ sum, uint32_t* __restrict__ mx) {
-  const uint64_t item = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const uint32_t lane = threadIdx.x & 63;
-  if (item >= (uint64_t)count * B) return;
-  const uint32_t t = (uint32_t)(item / B), i = (uint32_t)(item % B);
-  const uint64_t K = d[t].K;
-  const uint32_t* col = pilots + (uint64_t)B * d[t].Kbase + (uint64_t)i * K;
-  uint64_t s = 0, m = 0;
-  for (uint64_t j = lane; j < K; j += 64) {
-    const uint64_t v = col[j];
+  const uint64_t item = (uint64_t)blockIdx.x * kItemsPerGroup + threadIdx.x / kItemLanes;
+  const uint32_t q = threadIdx.x % kItemLanes;
+  const bool ok = item < (uint64_t)count * B;
+  const uint32_t t = ok ? (uint32_t)(item / B) : 0u, i = ok ? (uint32_t)(item % B) : 0u;
+  const uint64_t K = ok ? d[t].K : 0;
+  const uint32_t* col = pilots + (uint64_t)B * (ok ? d[t].Kbase : 0) + (uint64_t)i * K;
+  uint64_t s = 0;
+  uint32_t m = 0;
+  for (uint64_t j = q; j < K; j += kItemLanes) {
+    const uint32_t v = col[j];
     s += v;
     m = max(m, v);
   }
-  s = wave_sum_u64(s);
-  m = wave_max_u64(m);
-  if (lane == 0) {
+  s = item_sum_u64(s);
+#pragma unroll
+  for (int o = 1; o < (int)kItemLanes; o <<= 1) m = max(m, (uint32_t)__shfl_xor(m, o, kItemLanes));
+  if (ok && q == 0) {
     sum[item] = s;
-    mx[item] = (uint32_t)m;
+    mx[item] = m;
   }
 }
 
-// One wavefront per (t, i): bits of the unary stream, sum (v >> w) + K_t.
+// bits of the item's unary stream: sum (v >> w) + K_t
 __global__ __launch_bounds__(256) void k_batch_unary(const uint32_t* __restrict__ pilots,
                                                      const BatchDesc* __restrict__ d, uint32_t count, uint32_t B,
                                                      const uint8_t* __restrict__ width, uint64_t* __restrict__ ubits) {
-  const uint64_t item = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const uint32_t lane = threadIdx.x & 63;
-  if (item >= (uint64_t)count * B) return;
-  const uint32_t t = (uint32_t)(item / B), i = (uint32_t)(item % B);
-  const uint64_t K = d[t].K;
-  const uint32_t w = width[item];
-  const uint32_t* col = pilots + (uint64_t)B * d[t].Kbase + (uint64_t)i * K;
+  const uint64_t item = (uint64_t)blockIdx.x * kItemsPerGroup + threadIdx.x / kItemLanes;
+  const uint32_t q = threadIdx.x % kItemLanes;
+  const bool ok = item < (uint64_t)count * B;
+  const uint32_t t = ok ? (uint32_t)(item / B) : 0u, i = ok ? (uint32_t)(item % B) : 0u;
+  const uint64_t K = ok ? d[t].K : 0;
+  const uint32_t w = ok ? width[item] : 0u;
+  const uint32_t* col = pilots + (uint64_t)B * (ok ? d[t].Kbase : 0) + (uint64_t)i * K;
   uint64_t s = 0;
-  for (uint64_t j = lane; j < K; j += 64) s += (uint64_t)col[j] >> w;
-  s = wave_sum_u64(s);
-  if (lane == 0) ubits[item] = s + K;
+  for (uint64_t j = q; j < K; j += kItemLanes) s += (uint64_t)col[j] >> w;
+  s = item_sum_u64(s);
+  if (ok && q == 0) ubits[item] = s + K;
 }
 
 // One wavefront per MPHF: minimum and maximum offset residue.
@@ -2382,26 +2388,48 @@ struct BatchPlan {
   uint32_t P, ncomp;
 };
 
-__global__ __launch_bounds__(kBlock) void k_batch_plan(const BatchDesc* __restrict__ d, uint32_t count, uint32_t B,
-                                                       const uint8_t* __restrict__ width,
-                                                       const uint64_t* __restrict__ ubits,
-                                                       const long long* __restrict__ mm, BatchPlan pl,
-                                                       uint64_t* __restrict__ encw, uint64_t* __restrict__ ubase,
-                                                       uint64_t* __restrict__ hdrs, uint64_t* __restrict__ words,
-                                                       uint32_t* __restrict__ err) {
-  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
+// One wavefront per MPHF (four per workgroup): the encoders' bit bases are prefix sums over the
+// encoders in order, taken 64 encoders at a time with a wavefront scan.
+constexpr uint32_t kPlanWaves = 4;
+__global__ __launch_bounds__(64 * kPlanWaves) void k_batch_plan(const BatchDesc* __restrict__ d, uint32_t count,
+                                                                uint32_t B, const uint8_t* __restrict__ width,
+                                                                const uint64_t* __restrict__ ubits,
+                                                                const long long* __restrict__ mm, BatchPlan pl,
+                                                                uint64_t* __restrict__ encw,
+                                                                uint64_t* __restrict__ ubase,
+                                                                uint64_t* __restrict__ hdrs,
+                                                                uint64_t* __restrict__ words,
+                                                                uint32_t* __restrict__ err) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t t = blockIdx.x * kPlanWaves + (threadIdx.x >> 6);
+  if (t >= count) return;  // whole wavefronts leave together
   const BatchDesc e = d[t];
   const bool rice = (pl.coding_word & 0xFF) == PHOBIC_IC_RICE;
-  uint64_t data_bits = 0, unary_bits = 0;
-  for (uint32_t i = 0; i < B; i++) {
+  uint64_t data_bits = 0, unary_bits = 0;  // totals of the encoders before the current 64
+  for (uint32_t i0 = 0; i0 < B; i0 += 64) {
+    const uint32_t i = i0 + lane;
     const uint64_t it = (uint64_t)t * B + i;
-    const uint32_t w = width[it];
-    encw[it] = (data_bits << 8) | w;
-    data_bits += (uint64_t)w * e.K;
-    ubase[it] = unary_bits;
-    if (rice && i >= pl.ncomp) unary_bits += ubits[it];  // Compact encoders have no unary part
+    const uint32_t w = i < B ? width[it] : 0u;
+    uint64_t db = (uint64_t)w * e.K;
+    uint64_t ub = i < B && rice && i >= pl.ncomp ? ubits[it] : 0;  // Compact encoders have no unary part
+    // inclusive wavefront scans of both
+    uint64_t sdb = db, sub = ub;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint64_t a = __shfl_up(sdb, o), b = __shfl_up(sub, o);
+      if (lane >= (uint32_t)o) {
+        sdb += a;
+        sub += b;
+      }
+    }
+    if (i < B) {
+      encw[it] = ((data_bits + sdb - db) << 8) | w;
+      ubase[it] = unary_bits + sub - ub;
+    }
+    data_bits += __shfl(sdb, 63);
+    unary_bits += __shfl(sub, 63);
   }
+  if (lane != 0) return;
   if (rice && unary_bits > 0xFFFFFFFFULL) atomicOr(&err[0], 1u << PHOBIC_E_CAPACITY);
   const long long dmin = mm[2 * t], dmax = mm[2 * t + 1];
   const uint64_t span = (uint64_t)(dmax - dmin);
@@ -2739,12 +2767,13 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   PHOBIC_HIP(S.get(&dib, count));
   PHOBIC_HIP(S.get(&dwords, count));
   const uint32_t item_groups = (uint32_t)((items + 3) / 4), mphf_groups = (count + 3) / 4;
-  hipLaunchKernelGGL(k_batch_stats, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, sum, mx);
+  const uint32_t stat_groups = (uint32_t)((items + kItemsPerGroup - 1) / kItemsPerGroup);
+  hipLaunchKernelGGL(k_batch_stats, dim3(stat_groups), dim3(256), 0, st, pilots, d_desc, count, B, sum, mx);
   hipLaunchKernelGGL(k_batch_offstats, dim3(mphf_groups), dim3(256), 0, st, off, d_desc, count, dmm);
   hipLaunchKernelGGL(k_batch_widths, dim3(grid_for(items)), dim3(kBlock), 0, st, d_desc, count, B, sum, mx,
                      (uint32_t)rice, ncomp, rice_thresholds(), dw);
   if (rice)
-    hipLaunchKernelGGL(k_batch_unary, dim3(item_groups), dim3(256), 0, st, pilots, d_desc, count, B, dw, dub);
+    hipLaunchKernelGGL(k_batch_unary, dim3(stat_groups), dim3(256), 0, st, pilots, d_desc, count, B, dw, dub);
   BatchPlan plan;
   std::memcpy(&plan.lambda_bits, &prm.lambda, 8);
   plan.alpha_word = (uint64_t)prm.alpha_num | ((uint64_t)prm.alpha_den << 32);
@@ -2752,8 +2781,8 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   plan.seed = prm.hash_seed;
   plan.P = prm.partition_size;
   plan.ncomp = ncomp;
-  hipLaunchKernelGGL(k_batch_plan, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, st, d_desc, count, B, dw, dub,
-                     dmm, plan, de, du, dh, dwords, err);
+  hipLaunchKernelGGL(k_batch_plan, dim3((count + kPlanWaves - 1) / kPlanWaves), dim3(64 * kPlanWaves), 0, st, d_desc,
+                     count, B, dw, dub, dmm, plan, de, du, dh, dwords, err);
   PHOBIC_HIP(hipGetLastError());
   uint64_t *hwords, *ibase, *hdrs;  // pinned
   uint32_t* herr;
