@@ -2253,21 +2253,33 @@ __global__ __launch_bounds__(kCoarseThreads) void k_batch_coarse(const BatchDesc
   }
   __syncthreads();
   const uint64_t a = (uint64_t)blockIdx.x * per, b = min(nchunk, a + per);
-  uint64_t i = a + tid;
-  uint32_t t = i < b ? batch_owner(d, t0, t1, nb0 + i) : t0;
+  uint32_t t = a + tid < b ? batch_owner(d, t0, t1, nb0 + a + tid) : t0;
   const uint64_t gmask = (1ULL << gshift) - 1;
-  for (; i < b; i += kCoarseThreads) {
-    const uint64_t gi = nb0 + i;
-    while (t + 1 < t1 && d[t + 1].nbase <= gi) t++;
-    const uint64_t key = d[t].keys[gi - d[t].nbase];
-    const uint64_t J = d[t].Kbase + __umul64hi(mix_a(key ^ seed), d[t].K);
-    const uint32_t bin = (uint32_t)((J - Jc0) >> gshift);
-    if (kScatter) {
-      uint64_t hi, lo;
-      hash_key_u64(key, seed, hi, lo);
-      codes[atomicAdd(&hist[bin], 1u)] = make_ulonglong2(fingerprint(hi, lo), (lo & ~7ULL) | ((J - Jc0) & gmask));
-    } else {
-      atomicAdd(&hist[bin], 1u);
+  // four keys per thread and round: owners found (they only move forward) and keys loaded for all
+  // four before any is hashed, so that the loads are in flight together
+  constexpr int kU = 4;
+  for (uint64_t i0 = a + tid; i0 < b; i0 += (uint64_t)kU * kCoarseThreads) {
+    uint64_t key[kU];
+    uint32_t tt[kU];
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const uint64_t gi = nb0 + min(i0 + (uint64_t)u * kCoarseThreads, b - 1);
+      while (t + 1 < t1 && d[t + 1].nbase <= gi) t++;
+      tt[u] = t;
+      key[u] = d[t].keys[gi - d[t].nbase];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      if (i0 + (uint64_t)u * kCoarseThreads >= b) break;
+      const uint64_t J = d[tt[u]].Kbase + __umul64hi(mix_a(key[u] ^ seed), d[tt[u]].K);
+      const uint32_t bin = (uint32_t)((J - Jc0) >> gshift);
+      if (kScatter) {
+        uint64_t hi, lo;
+        hash_key_u64(key[u], seed, hi, lo);
+        codes[atomicAdd(&hist[bin], 1u)] = make_ulonglong2(fingerprint(hi, lo), (lo & ~7ULL) | ((J - Jc0) & gmask));
+      } else {
+        atomicAdd(&hist[bin], 1u);
+      }
     }
   }
   if (!kScatter) {
