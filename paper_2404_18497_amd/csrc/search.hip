@@ -94,7 +94,7 @@ __device__ bool equal_fingerprints(const uint64_t* keys, const uint32_t* rbuf, u
   for (uint32_t g = 0; g < ng; g++) {
     uint64_t bm = cm[g];
     while (bm) {
-      const uint32_t c = g * 64 + (uint32_t)(__ffsll((long long)bm) - 1);
+      const uint32_t c = g * 64 + (uint32_t)__builtin_ctzll(bm);
       bm &= bm - 1;
       const uint32_t rc = rbuf[c];
       const uint64_t fc = keys[c];
@@ -226,11 +226,14 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
     }
     return __builtin_amdgcn_readlane(bw0, r - bbase);
   };
+  // every lane calls it: the LDS row takes the same value from all of them, the global row (wide
+  // partitions) from lane 0
   auto set_pilot = [&](uint32_t bid, uint32_t p) {
-    if (kWide)
-      pilots_w[j * B + bid] = p;
-    else
+    if (kWide) {
+      if (lane == 0) pilots_w[j * B + bid] = p;
+    } else {
       pil[bid] = p;
+    }
   };
 
   // this lane's displacement window of the first pass (d0 = 0): its bits below m, its byte offset
@@ -315,9 +318,9 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       uint64_t bal = four(0);
       for (uint32_t k = 4; bal != 0 && k < szp; k += 4) bal = four(k);
       if (bal) {
-        const uint32_t L = (uint32_t)(__ffsll((long long)bal) - 1);
+        const uint32_t L = (uint32_t)__builtin_ctzll(bal);
         const uint64_t accL = lane_value64(acc, L);
-        d_found = d0 + L * 64 + (uint32_t)(__ffsll((long long)accL) - 1);
+        d_found = d0 + L * 64 + (uint32_t)__builtin_ctzll(accL);
       }
     };
     scan_pass(0, acc_first, loff_first);
@@ -371,7 +374,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         const uint32_t t2 = t + m;
         atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
       }
-      if (lane == 0) set_pilot(bid, s * m + d_found);
+      set_pilot(bid, s * m + d_found);
       wave_sync();
       break;
     }
@@ -436,7 +439,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         const uint32_t d = scan(rbuf, szp);
         const bool in_limit = d != 0xFFFFFFFFu && !(smax == 0 && d > dlast);
         if (in_limit && place(p0, d)) {
-          if (lane == 0) set_pilot(bid, d);
+          set_pilot(bid, d);
           wave_sync();
           continue;
         }
@@ -485,7 +488,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
             break;
           }
           if (!place(dec_pos(rb[lane < sz ? lane : 0u]), d)) continue;
-          if (lane == 0) set_pilot(bid, sd * m + d);
+          set_pilot(bid, sd * m + d);
           wave_sync();
           done = true;
           break;
@@ -514,9 +517,9 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, r0) << 32) | __builtin_amdgcn_alignbit(w1, w0, r0);
         const uint64_t bal = __ballot(acc != 0);
         if (bal) {
-          const uint32_t L = (uint32_t)(__ffsll((long long)bal) - 1);
+          const uint32_t L = (uint32_t)__builtin_ctzll(bal);
           const uint64_t accL = lane_value64(acc, L);
-          d_found = d0 + L * 64 + (uint32_t)(__ffsll((long long)accL) - 1);
+          d_found = d0 + L * 64 + (uint32_t)__builtin_ctzll(accL);
         }
       };
       single_pass(0, acc_first, loff_first);
@@ -538,7 +541,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       if (lane < 2) {  // lane 0 the slot's bit, lane 1 its copy m bits further
         const uint32_t tt = t + lane * m;
         atomicAnd(&F2[tt >> 5], ~(1u << (tt & 31)));
-        if (lane == 0) set_pilot(bid, d_found);
+        set_pilot(bid, d_found);
       }
       wave_sync();
     }
