@@ -108,10 +108,10 @@ __device__ bool equal_fingerprints(const uint64_t* keys, const uint32_t* rbuf, u
 }
 
 // Positions of a bucket's keys under the seed value w, encoded into rbuf, padded to a multiple of
-// four with the last entry.  Returns lane k's position for k < 64 (the keys a small bucket marks).
+// eight with the last entry.  Returns lane k's position for k < 64 (the keys a small bucket marks).
 __device__ __forceinline__ uint32_t bucket_positions(uint32_t* rbuf, const uint64_t* keys, uint64_t f0, uint32_t sz,
                                                      uint64_t w, uint32_t m, uint32_t lane) {
-  const uint32_t szp = (sz + 3) & ~3u;
+  const uint32_t szp = (sz + 7) & ~7u;
   // keys 0..63: every lane hashes (those past the bucket a neighbour's fingerprint, unused), so no
   // lane mask is set up; the padding lanes store the last key's position
   const uint32_t r0 = pos_hash(f0, w, m);
@@ -334,6 +334,36 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
     return d_found;
   };
 
+  // Short scan for big buckets early in the partition: the lanes form 8 windows of 64 displacements
+  // (d < 512) times 8 key groups (lane = 8 g + w); group g ANDs every eighth key of the bucket into
+  // its windows and the groups' windows are ANDed together at the end, so a step covers eight keys.
+  // Returns the lowest d < 512, or ~0 when none is admissible there (the full scan then runs).
+  const uint32_t gw = lane & 7, gg = lane >> 3;
+  const uint64_t acc8 = 64 * gw < m ? (m - 64 * gw >= 64 ? ~0ULL : ((1ULL << (m - 64 * gw)) - 1)) : 0ULL;
+  const uint32_t loff8 = 64 * gw < m ? gw * 8 : 0u;
+  auto scan8 = [&](uint32_t szp8) -> uint32_t {
+    uint64_t acc = acc8;
+    for (uint32_t k = 0;;) {
+      const uint32_t e = rbuf[k + gg];
+      const uint32_t* wp = (const uint32_t*)(F2b + (e >> 16) + loff8);
+      const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
+      acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, e) << 32) | __builtin_amdgcn_alignbit(w1, w0, e);
+      k += 8;
+      if (k >= szp8) break;
+      // a key group with all eight windows empty empties the AND: some byte of the ballot is zero
+      const uint64_t b = uniform64(__ballot(acc != 0));
+      if (((b - 0x0101010101010101ULL) & ~b & 0x8080808080808080ULL) != 0) return 0xFFFFFFFFu;
+    }
+    acc &= __shfl_xor(acc, 8);
+    acc &= __shfl_xor(acc, 16);
+    acc &= __shfl_xor(acc, 32);
+    const uint64_t b = uniform64(__ballot(acc != 0)) & 0xFFull;
+    if (!b) return 0xFFFFFFFFu;
+    const uint32_t L = (uint32_t)__builtin_ctzll(b);
+    return L * 64 + (uint32_t)__builtin_ctzll(lane_value64(acc, L));
+  };
+  uint32_t placed = 0;  // keys placed so far
+
   bool overflow = false;
   uint32_t r = 0;
   const uint64_t* keys = fpa + kb;  // the current bucket's keys
@@ -361,7 +391,11 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         }
         continue;
       }
-      const uint32_t d_found = scan(rbuf, (sz + 3) & ~3u);
+      // the short scan first while the bucket expects at least three admissible displacements below
+      // 512 (512 f^sz >= 3 for the free fraction f); the choice only decides which scan runs first
+      uint32_t d_found = 0xFFFFFFFFu;
+      if (m > 512 && (float)sz * __logf((float)(m - placed) / (float)m) >= -5.14f) d_found = scan8((sz + 7) & ~7u);
+      if (d_found == 0xFFFFFFFFu) d_found = scan(rbuf, (sz + 3) & ~3u);
       if (d_found == 0xFFFFFFFFu) continue;
       if (s == smax && d_found > dlast) {  // p > limit, with s <= smax
         overflow = true;
@@ -375,6 +409,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
       }
       set_pilot(bid, s * m + d_found);
+      placed += sz;
       wave_sync();
       break;
     }

@@ -115,6 +115,7 @@ inline int __popcll(uint64_t x) { return __builtin_popcountll(x); }
 inline int __clzll(long long x) { return x ? __builtin_clzll(x) : 64; }
 inline float __expf(float x) { return std::exp(x); }
 inline float __log2f(float x) { return std::log2(x); }
+inline float __logf(float x) { return std::log(x); }
 inline uint64_t __umul64hi(uint64_t a, uint64_t b) { return (uint64_t)(((unsigned __int128)a * b) >> 64); }
 inline uint32_t __umulhi(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
 // one host thread runs every lane, so plain read-modify-writes are atomic
