@@ -2036,16 +2036,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   sa.B = B;
   const uint32_t mm = (uint32_t)std::max<uint64_t>(max_m, 1);
   const uint32_t mb = std::max<uint32_t>(hmaxb, 1);
-  auto up4 = [](uint32_t v) { return (v + 3) & ~3u; };
-  sa.f2_words = up4((2 * mm + 127) / 32 + 1);
-  sa.scr_words = up4((mm + 31) / 32 + 1);
-  sa.rb_cap = std::max<uint32_t>(kSearchMinPositions, up4(mb) + 4);
-  sa.bl_cap = wide ? 0u : up4(B);  // wide: bucket list and pilots in global memory
-  sa.cm_cap = (mb + 63) / 64 + 1;
-  sa.max_m = mm;
-  sa.max_bucket = mb;
-  sa.wide = wide ? 1u : 0u;
-  sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + kSearchCtxBytes + 15) & ~15u;
+  size_search_lds(sa, mm, mb, B, wide);
   if (wide && sa.wave_lds > max_lds_per_group())
     return fail(PHOBIC_E_CAPACITY, "a partition of " + std::to_string(mm) + " slots does not fit the LDS of one workgroup");
   sa.owner = nullptr;
@@ -2740,16 +2731,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   sa.limit = limit;
   sa.B = B;
   const uint32_t mm = std::max<uint32_t>(hinfo[2], 1), mb = std::max<uint32_t>(hinfo[1], 1);
-  auto up4 = [](uint32_t v) { return (v + 3) & ~3u; };
-  sa.f2_words = up4((2 * mm + 127) / 32 + 1);
-  sa.scr_words = up4((mm + 31) / 32 + 1);
-  sa.rb_cap = std::max<uint32_t>(kSearchMinPositions, up4(mb) + 4);
-  sa.bl_cap = up4(B);
-  sa.cm_cap = (mb + 63) / 64 + 1;
-  sa.max_m = mm;
-  sa.max_bucket = mb;
-  sa.wide = 0;
-  sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + kSearchCtxBytes + 15) & ~15u;
+  size_search_lds(sa, mm, mb, B, false);
   sa.owner = owner;
   sa.Kbase = d_Kbase;
   sa.Kt = d_Kt;

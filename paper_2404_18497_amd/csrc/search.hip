@@ -59,19 +59,36 @@ __device__ __forceinline__ uint64_t lane_value64(uint64_t v, uint32_t lane) {
          __builtin_amdgcn_readlane((uint32_t)v, lane);
 }
 
-__device__ __forceinline__ uint32_t enc_pos(uint32_t r) { return ((r >> 5) << 18) | (r & 31); }
-__device__ __forceinline__ uint32_t dec_pos(uint32_t e) { return ((e >> 18) << 5) | (e & 31); }
+// Encoded positions: the high half of a code is the byte offset, from F2, of the load that starts at
+// the word holding bit r; the low five bits are r's funnel shift.  kShift (every path but the wide
+// one): F2 is followed, x bytes on, by its copy shifted by one word, F2s (F2s word w = F2 word
+// w + 1), and a position whose word index is odd is read from F2s, so that the load's first two
+// words are one aligned 64-bit LDS read; the low half is then r itself (r < 2^16).
+template <bool kShift>
+struct PosCode {
+  uint32_t x;
+  __device__ __forceinline__ uint32_t enc(uint32_t r) const {
+    if (!kShift) return ((r >> 5) << 18) | (r & 31);
+    const uint32_t a = r >> 5;
+    return ((4 * a + ((a & 1) ? x - 4 : 0u)) << 16) | r;
+  }
+  __device__ __forceinline__ uint32_t dec(uint32_t e) const {
+    return kShift ? (e & 0xFFFFu) : (((e >> 18) << 5) | (e & 31));
+  }
+};
 
 // Marks the positions of rbuf[0..sz) in the scratch bitmap; cm[g] gets the lanes of group g whose
 // position was already marked.  Leaves the scratch clear.  Returns whether a position repeats.
-__device__ bool positions_repeat(uint32_t* scr, const uint32_t* rbuf, uint32_t sz, uint64_t* cm, uint32_t lane) {
+template <class PC>
+__device__ bool positions_repeat(const PC& pc, uint32_t* scr, const uint32_t* rbuf, uint32_t sz, uint64_t* cm,
+                                 uint32_t lane) {
   bool any = false;
   const uint32_t ng = (sz + 63) >> 6;
   for (uint32_t g = 0; g < ng; g++) {
     const uint32_t k = g * 64 + lane;
     bool c = false;
     if (k < sz) {
-      const uint32_t rr = dec_pos(rbuf[k]), bit = 1u << (rr & 31);
+      const uint32_t rr = pc.dec(rbuf[k]), bit = 1u << (rr & 31);
       c = (atomicOr(&scr[rr >> 5], bit) & bit) != 0;
     }
     const uint64_t bm = __ballot(c);
@@ -80,7 +97,7 @@ __device__ bool positions_repeat(uint32_t* scr, const uint32_t* rbuf, uint32_t s
   }
   wave_sync();
   for (uint32_t k = lane; k < sz; k += 64) {
-    const uint32_t rr = dec_pos(rbuf[k]);
+    const uint32_t rr = pc.dec(rbuf[k]);
     atomicAnd(&scr[rr >> 5], ~(1u << (rr & 31)));
   }
   wave_sync();
@@ -109,31 +126,72 @@ __device__ bool equal_fingerprints(const uint64_t* keys, const uint32_t* rbuf, u
 
 // Positions of a bucket's keys under the seed value w, encoded into rbuf, padded to a multiple of
 // eight with the last entry.  Returns lane k's position for k < 64 (the keys a small bucket marks).
-__device__ __forceinline__ uint32_t bucket_positions(uint32_t* rbuf, const uint64_t* keys, uint64_t f0, uint32_t sz,
-                                                     uint64_t w, uint32_t m, uint32_t lane) {
+template <class PC>
+__device__ __forceinline__ uint32_t bucket_positions(const PC& pc, uint32_t* rbuf, const uint64_t* keys, uint64_t f0,
+                                                     uint32_t sz, uint64_t w, uint32_t m, uint32_t lane) {
   const uint32_t szp = (sz + 7) & ~7u;
   // keys 0..63: every lane hashes (those past the bucket a neighbour's fingerprint, unused), so no
   // lane mask is set up; the padding lanes store the last key's position
   const uint32_t r0 = pos_hash(f0, w, m);
   if (sz <= 64) {
     const uint32_t last = __builtin_amdgcn_readlane(r0, sz - 1);
-    if (lane < szp) rbuf[lane] = enc_pos(lane < sz ? r0 : last);
+    if (lane < szp) rbuf[lane] = pc.enc(lane < sz ? r0 : last);
   } else {
-    rbuf[lane] = enc_pos(r0);
+    rbuf[lane] = pc.enc(r0);
     uint32_t r = 0, k = lane;
     for (uint32_t g = 1; g * 64 < sz; g++) {  // keys 64 and on
       k = g * 64 + lane;
       r = 0;
       if (k < sz) {
         r = pos_hash(keys[k], w, m);
-        rbuf[k] = enc_pos(r);
+        rbuf[k] = pc.enc(r);
       }
     }
     const uint32_t last = __builtin_amdgcn_readlane(r, (sz - 1) & 63);
-    if (k >= sz && k < szp) rbuf[k] = enc_pos(last);
+    if (k >= sz && k < szp) rbuf[k] = pc.enc(last);
   }
   wave_sync();
   return r0;
+}
+
+// Positions of a big bucket's keys under the seed value w (keys 0..63 from f0, the lane's
+// fingerprint), written to rbuf and marked in the scratch bitmap 64 keys at a time, stopping at the
+// first group that repeats a position: most seeds of a big bucket repeat one within its first 64
+// keys, and the rest need not be hashed.  Leaves the scratch clear; without a repeat rbuf is padded
+// to a multiple of eight with the last entry.  Returns whether a position repeats.
+template <class PC>
+__device__ bool positions_repeat_early(const PC& pc, uint32_t* scr, uint32_t* rbuf, const uint64_t* keys, uint64_t f0,
+                                       uint32_t sz, uint64_t w, uint32_t m, uint32_t lane) {
+  bool rep = false;
+  uint32_t g = 0, r = 0;
+  for (; g * 64 < sz; g++) {
+    const uint32_t k = g * 64 + lane;
+    bool c = false;
+    if (k < sz) {
+      r = pos_hash(g == 0 ? f0 : keys[k], w, m);
+      rbuf[k] = pc.enc(r);
+      const uint32_t bit = 1u << (r & 31);
+      c = (atomicOr(&scr[r >> 5], bit) & bit) != 0;
+    }
+    if (__ballot(c)) {
+      rep = true;
+      g++;
+      break;
+    }
+  }
+  wave_sync();
+  const uint32_t marked = min(g * 64, sz);
+  for (uint32_t k = lane; k < marked; k += 64) {
+    const uint32_t rr = pc.dec(rbuf[k]);
+    atomicAnd(&scr[rr >> 5], ~(1u << (rr & 31)));
+  }
+  if (!rep) {
+    const uint32_t last = __builtin_amdgcn_readlane(r, (sz - 1) & 63);
+    const uint32_t k = sz + lane;
+    if (k < ((sz + 7) & ~7u)) rbuf[k] = pc.enc(last);
+  }
+  wave_sync();
+  return rep;
 }
 
 // Argument fields that only the failure and output paths use, kept in LDS for the partition so that
@@ -154,12 +212,14 @@ __device__ __forceinline__ void note_failure(const uint64_t* ctx, uint64_t j, ui
 // their own loops: big buckets (more than kSmallBucket keys; positions checked for repeats before
 // the scan), small ones (2 .. kSmallBucket keys; a repeat shows while marking) and single keys (no
 // repeat possible; seed 0 always finds a free slot).  Seed-0 positions come from the fingerprint
-// windows, hashed once per window instead of once per bucket.  kMulti: some table of the launch
-// has more than 4096 slots, so a displacement scan may need several passes.  kWide: the bucket list
-// is read from global memory through 64-entry register windows and pilots are written to the
-// global row directly (partitions whose lists do not fit the LDS; one MPHF).
+// windows, hashed once per window instead of once per bucket, and the bucket list is read from
+// global memory through 64-entry register windows.  kMulti: some table of the launch has more than
+// 4096 slots, so a displacement scan may need several passes.  kWide: pilots are written to the
+// global row directly and F2 has no shifted copy (partitions whose lists do not fit the LDS; one
+// MPHF).
 template <bool kMulti, bool kWide>
 __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, uint32_t lane) {
+  constexpr bool kShift = !kWide;
   const uint64_t* const fpa = a.fp;
   const uint64_t* const offp = a.off;
   const uint64_t* const toffp = a.toff;
@@ -168,11 +228,12 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   const uint32_t f2_words = a.f2_words, scr_words = a.scr_words, bl_cap = a.bl_cap;
   const uint32_t B = a.B;
   uint32_t* const pilots_w = kWide ? a.pilots : nullptr;
-  uint32_t* scr = F2 + f2_words;
+  uint32_t* const F2s = F2 + f2_words;  // kShift: F2 shifted by one word
+  uint32_t* scr = F2 + (kShift ? 2 : 1) * f2_words;
   uint32_t* rbuf = scr + scr_words;
-  uint32_t* bl = rbuf + a.rb_cap;
-  uint32_t* pil = bl + bl_cap;  // the partition's pilots, by bucket index
+  uint32_t* pil = rbuf + a.rb_cap;  // the partition's pilots, by bucket index
   uint64_t* cm = (uint64_t*)(pil + bl_cap);
+  const PosCode<kShift> pc{4 * f2_words};
   uint64_t* ctx = cm + a.cm_cap;
   if (lane == 0) {
     ctx[kCtxErr] = (uint64_t)a.err;
@@ -197,28 +258,53 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
     }
   }
   const uint32_t twom = 2 * m;
-  for (uint32_t w = lane; w < f2_words; w += 64) {
+  auto f2_init = [&](uint32_t w) -> uint32_t {  // word w of F2 with every slot free
     const uint32_t lo = w * 32;
-    F2[w] = lo + 32 <= twom ? 0xFFFFFFFFu : (lo >= twom ? 0u : ((1u << (twom - lo)) - 1u));
+    return lo + 32 <= twom ? 0xFFFFFFFFu : (lo >= twom ? 0u : ((1u << (twom - lo)) - 1u));
+  };
+  for (uint32_t w = lane; w < f2_words; w += 64) {
+    F2[w] = f2_init(w);
+    if (kShift) F2s[w] = f2_init(w + 1);
   }
   for (uint32_t w = lane; w < scr_words; w += 64) scr[w] = 0;
   const uint32_t nb = uniform(nbkp[j]);
   const uint32_t* gbl = blistp + j * B;
-  uint32_t bw0 = 0, bw1 = 0, bbase = 0;  // kWide: entries bbase + lane and bbase + 64 + lane
+  // the bucket list: entries bbase + lane (bw0) and bbase + 64 + lane (bw1)
+  uint32_t bw0 = lane < nb ? gbl[lane] : 0u, bw1 = 64 + lane < nb ? gbl[64 + lane] : 0u, bbase = 0;
   if (kWide) {
     for (uint32_t x = lane; x < B; x += 64) pilots_w[j * B + x] = 0;  // empty buckets keep pilot 0
     __threadfence_block();  // the zeros land before any pilot of this row
-    bw0 = lane < nb ? gbl[lane] : 0u;
-    bw1 = 64 + lane < nb ? gbl[64 + lane] : 0u;
   } else {
-    for (uint32_t x = lane; x < nb; x += 64) bl[x] = gbl[x];
     for (uint32_t x = lane; x < B; x += 64) pil[x] = 0;  // empty buckets keep pilot 0
   }
   wave_sync();
   const char* F2b = (const char*)F2;
+  // the 64 bits of F2 from bit (off's word) * 32 + sh on: one aligned 64-bit read and one 32-bit
+  // read (kShift), else three 32-bit reads
+  auto window = [&](uint32_t off, uint32_t sh) -> uint64_t {
+    const char* p = F2b + off;
+    uint32_t w0, w1;
+    if (kShift) {
+      const uint2 q = *(const uint2*)p;
+      w0 = q.x;
+      w1 = q.y;
+    } else {
+      w0 = ((const uint32_t*)p)[0];
+      w1 = ((const uint32_t*)p)[1];
+    }
+    const uint32_t w2 = ((const uint32_t*)p)[2];
+    return ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, sh) << 32) | __builtin_amdgcn_alignbit(w1, w0, sh);
+  };
+  // marks slot bit t (t < 2m) of F2 taken, and its copy in F2s, word (t >> 5) - 1 there: for t < 32
+  // that is F2's last word, which lies past every window read (padding), so no test is needed
+  auto take_bit = [&](uint32_t t) {
+    uint32_t* const w = F2 + (t >> 5);
+    const uint32_t mask = ~(1u << (t & 31));
+    atomicAnd(w, mask);
+    if (kShift) atomicAnd(w + (f2_words - 1), mask);
+  };
   // bucket entry r (size << 16 | bucket) of the processing order; r never decreases
   auto bucket_entry = [&](uint32_t r) -> uint32_t {
-    if (!kWide) return uniform(bl[r]);
     if (r >= bbase + 64) {
       bbase += 64;
       bw0 = bw1;
@@ -299,24 +385,25 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   // encoded positions at rb.  A pass covers 4096 displacements from d0 (acc: this lane's window
   // bits below m, loff: its byte offset); the first pass covers every m up to 4096, further passes
   // (kMulti) the larger ones.  ~0 when no displacement works.
+  // ANDs the windows of the szp encoded positions at rb (this lane's list; szp >= 4, a multiple of
+  // four) into acc, four keys at a time while some lane's window still has a bit; returns the
+  // ballot of the lanes with one.
+  auto keys_and = [&](const uint32_t* rb, uint64_t& acc, uint32_t loff, uint32_t szp) -> uint64_t {
+    auto four = [&](uint32_t k) {
+      const uint4 e4 = *(const uint4*)(rb + k);
+      const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
+#pragma unroll
+      for (int t = 0; t < 4; t++) acc &= window((ev[t] >> 16) + loff, ev[t]);
+      return uniform64(__ballot(acc != 0));
+    };
+    uint64_t bal = four(0);
+    for (uint32_t k = 4; bal != 0 && k < szp; k += 4) bal = four(k);
+    return bal;
+  };
   auto scan = [&](const uint32_t* rb, uint32_t szp) -> uint32_t {
     uint32_t d_found = 0xFFFFFFFFu;
     auto scan_pass = [&](uint32_t d0, uint64_t acc, uint32_t loff) {
-      auto four = [&](uint32_t k) {
-        const uint4 e4 = *(const uint4*)(rb + k);
-        const uint32_t ev[4] = {e4.x, e4.y, e4.z, e4.w};
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-          const uint32_t* wp = (const uint32_t*)(F2b + (ev[t] >> 16) + loff);
-          const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
-          acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, ev[t]) << 32) |
-                 __builtin_amdgcn_alignbit(w1, w0, ev[t]);
-        }
-        return uniform64(__ballot(acc != 0));
-      };
-      // szp >= 4: the first four keys, then four at a time while some displacement survives
-      uint64_t bal = four(0);
-      for (uint32_t k = 4; bal != 0 && k < szp; k += 4) bal = four(k);
+      const uint64_t bal = keys_and(rb, acc, loff, szp);
       if (bal) {
         const uint32_t L = (uint32_t)__builtin_ctzll(bal);
         const uint64_t accL = lane_value64(acc, L);
@@ -345,9 +432,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
     uint64_t acc = acc8;
     for (uint32_t k = 0;;) {
       const uint32_t e = rbuf[k + gg];
-      const uint32_t* wp = (const uint32_t*)(F2b + (e >> 16) + loff8);
-      const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
-      acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, e) << 32) | __builtin_amdgcn_alignbit(w1, w0, e);
+      acc &= window((e >> 16) + loff8, e);
       k += 8;
       if (k >= szp8) break;
       // a key group with all eight windows empty empties the AND: some byte of the ballot is zero
@@ -383,12 +468,16 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         overflow = true;
         break;
       }
-      bucket_positions(rbuf, keys, f0, sz, wseed, m, lane);
-      if (positions_repeat(scr, rbuf, sz, cm, lane)) {
-        if (s == 0 && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
-          if (lane == 0) note_failure(ctx, j, PHOBIC_E_DUPLICATE);
-          return;
+      if (s == 0) {  // all positions, for the duplicate check
+        bucket_positions(pc, rbuf, keys, f0, sz, wseed, m, lane);
+        if (positions_repeat(pc, scr, rbuf, sz, cm, lane)) {
+          if (equal_fingerprints(keys, rbuf, sz, cm, lane)) {
+            if (lane == 0) note_failure(ctx, j, PHOBIC_E_DUPLICATE);
+            return;
+          }
+          continue;
         }
+      } else if (positions_repeat_early(pc, scr, rbuf, keys, f0, sz, wseed, m, lane)) {
         continue;
       }
       // the short scan first while the bucket expects at least three admissible displacements below
@@ -402,11 +491,10 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
         break;
       }
       for (uint32_t k = lane; k < sz; k += 64) {
-        uint32_t t = dec_pos(rbuf[k]) + d_found;
+        uint32_t t = pc.dec(rbuf[k]) + d_found;
         if (t >= m) t -= m;
-        atomicAnd(&F2[t >> 5], ~(1u << (t & 31)));
-        const uint32_t t2 = t + m;
-        atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
+        take_bit(t);
+        take_bit(t + m);
       }
       set_pilot(bid, s * m + d_found);
       placed += sz;
@@ -424,6 +512,10 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
   // the lanes form G groups of S lanes (S the smallest of 4, 8, 16, 32 that holds the bucket), lane
   // x holding key x mod S (the last key past the bucket) under seed s + x / S, so one hash evaluation
   // serves G seeds; group i's positions are entries i S .. i S + S of rbuf.
+  // windows of 64 displacements per seed, and lane x's place in them: window x mod NW of seed x / NW
+  const uint32_t NW = (m + 63) >> 6;
+  const uint32_t lane_q = NW ? lane / NW : 0u, lane_r = lane - lane_q * NW;
+  const uint32_t q64 = NW ? 64u / NW : 0u, r64 = 64u - q64 * NW;
   if (!overflow) {
     for (; r < nb; r++) {
       const uint32_t e = bucket_entry(r);
@@ -448,13 +540,13 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
           return false;
         }
         if (lane < sz) {
-          const uint32_t t2 = t + m;
-          atomicAnd(&F2[t2 >> 5], ~(1u << (t2 & 31)));
+          if (kShift) atomicAnd(&F2[(t >> 5) + (f2_words - 1)], ~(1u << (t & 31)));  // F2s, see take_bit
+          take_bit(t + m);
         }
         return true;
       };
       auto dup0 = [&]() -> bool {  // after a failure at seed 0 (positions in rbuf): equal keys?
-        return positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane);
+        return positions_repeat(pc, scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane);
       };
       // seed 0
       {
@@ -469,7 +561,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
           const uint32_t pb = __shfl(p0w1, (int)(widx & 63));
           p0 = widx < 64 ? pa : pb;
         }
-        rbuf[lane] = enc_pos(p0);
+        rbuf[lane] = pc.enc(p0);
         wave_sync();
         const uint32_t d = scan(rbuf, szp);
         const bool in_limit = d != 0xFFFFFFFFu && !(smax == 0 && d > dlast);
@@ -506,8 +598,57 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       uint64_t wl = (uint64_t)(2 + (lane >> lgS)) * kPhi64;
       const uint64_t gstep = (uint64_t)G * kPhi64;
       bool done = false;
-      for (uint32_t s = 1; !done; s += G, wl += gstep) {
-        rbuf[lane] = enc_pos(pos_hash(fS, wl, m));
+      if (!kMulti) {
+        // The batch's G seeds times NW windows of 64 displacements, in pilot order (seed, then
+        // window), are scanned 64 windows at a time: lane x of chunk c takes window c 64 + x, so
+        // every lane has a window instead of the NW of one seed.  The lowest surviving lane holds
+        // the smallest pilot of the chunk; a seed whose positions repeat (marking fails) drops out.
+        const uint32_t nwin = G * NW;
+        for (uint32_t s = 1; !done; s += G, wl += gstep) {
+          rbuf[lane] = pc.enc(pos_hash(fS, wl, m));
+          wave_sync();
+          uint32_t t0 = 0, r0 = 0;  // chunk c starts at seed t0 of the batch, window r0
+          for (uint32_t c = 0; c < nwin; c += 64) {
+            uint32_t dw = r0 + lane_r, t = t0 + lane_q;
+            if (dw >= NW) {
+              dw -= NW;
+              t++;
+            }
+            const uint32_t dlo = dw * 64;
+            const bool act = t < G && s + t <= smax;
+            uint64_t acc = act ? (m - dlo >= 64 ? ~0ULL : ((1ULL << (m - dlo)) - 1)) : 0ULL;
+            uint64_t bal = keys_and(rbuf + (act ? t * S : 0u), acc, act ? dw * 8 : 0u, szp);
+            while (bal) {
+              const uint32_t L = (uint32_t)__builtin_ctzll(bal);
+              const uint32_t tL = __builtin_amdgcn_readlane(t, L);
+              const uint32_t d = __builtin_amdgcn_readlane(dlo, L) + (uint32_t)__builtin_ctzll(lane_value64(acc, L));
+              const uint32_t sd = s + tL;
+              if (sd == smax && d > dlast) {
+                overflow = true;
+                break;
+              }
+              if (place(pc.dec(rbuf[tL * S + (lane < sz ? lane : 0u)]), d)) {
+                set_pilot(bid, sd * m + d);
+                wave_sync();
+                done = true;
+                break;
+              }
+              bal &= ~uniform64(__ballot(t == tL));
+            }
+            if (done || overflow) break;
+            t0 += q64;
+            r0 += r64;
+            if (r0 >= NW) {
+              r0 -= NW;
+              t0++;
+            }
+          }
+          if (!done && s + G - 1 >= smax) overflow = true;  // every seed up to smax was tried
+          if (overflow) break;
+        }
+      }
+      for (uint32_t s = 1; kMulti && !done; s += G, wl += gstep) {
+        rbuf[lane] = pc.enc(pos_hash(fS, wl, m));
         wave_sync();
         for (uint32_t i = 0; i < G; i++) {
           const uint32_t sd = s + i;
@@ -522,7 +663,7 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
             overflow = true;
             break;
           }
-          if (!place(dec_pos(rb[lane < sz ? lane : 0u]), d)) continue;
+          if (!place(pc.dec(rb[lane < sz ? lane : 0u]), d)) continue;
           set_pilot(bid, sd * m + d);
           wave_sync();
           done = true;
@@ -544,12 +685,10 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       advance();
       const uint32_t r0 = __builtin_amdgcn_readlane(p0w0, o - wbase);
       o += 1;
-      const uint32_t ebase = ((r0 >> 5) << 2);  // byte offset of the word holding bit r0
+      const uint32_t ebase = pc.enc(r0) >> 16;  // byte offset of the load at the word holding bit r0
       uint32_t d_found = 0xFFFFFFFFu;
       auto single_pass = [&](uint32_t d0, uint64_t acc, uint32_t loff) {
-        const uint32_t* wp = (const uint32_t*)(F2b + ebase + loff);
-        const uint32_t w0 = wp[0], w1 = wp[1], w2 = wp[2];
-        acc &= ((uint64_t)__builtin_amdgcn_alignbit(w2, w1, r0) << 32) | __builtin_amdgcn_alignbit(w1, w0, r0);
+        acc &= window(ebase + loff, r0);
         const uint64_t bal = __ballot(acc != 0);
         if (bal) {
           const uint32_t L = (uint32_t)__builtin_ctzll(bal);
@@ -573,10 +712,14 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       }
       uint32_t t = r0 + d_found;
       if (t >= m) t -= m;
-      if (lane < 2) {  // lane 0 the slot's bit, lane 1 its copy m bits further
-        const uint32_t tt = t + lane * m;
-        atomicAnd(&F2[tt >> 5], ~(1u << (tt & 31)));
-        set_pilot(bid, d_found);
+      if (lane < 4) {  // lane 0 the slot's bit, lane 1 its copy m bits further; lanes 2, 3 those of F2s
+        const uint32_t tt = t + (lane & 1) * m;
+        if (lane < 2) {
+          atomicAnd(&F2[tt >> 5], ~(1u << (tt & 31)));
+          set_pilot(bid, d_found);
+        } else if (kShift) {  // F2s, see take_bit
+          atomicAnd(&F2[(tt >> 5) + (f2_words - 1)], ~(1u << (tt & 31)));
+        }
       }
       wave_sync();
     }
@@ -590,8 +733,8 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
       const uint64_t f0 = key_fp(sz);
       o += sz;
       if (sz < 2) continue;
-      bucket_positions(rbuf, keys, f0, sz, kPhi64, m, lane);
-      if (positions_repeat(scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
+      bucket_positions(pc, rbuf, keys, f0, sz, kPhi64, m, lane);
+      if (positions_repeat(pc, scr, rbuf, sz, cm, lane) && equal_fingerprints(keys, rbuf, sz, cm, lane)) {
         if (lane == 0) note_failure(ctx, j, PHOBIC_E_DUPLICATE);
         return;
       }

@@ -82,17 +82,7 @@ int main(int argc, char** argv) {
   sa.limit = limit;
   sa.B = B;
   // the LDS layout the library builds for these sizes
-  const uint32_t mm = std::max<uint32_t>(m, 1);
-  auto up4 = [](uint32_t v) { return (v + 3) & ~3u; };
-  sa.f2_words = up4((2 * mm + 127) / 32 + 1);
-  sa.scr_words = up4((mm + 31) / 32 + 1);
-  sa.rb_cap = std::max<uint32_t>(kSearchMinPositions, up4(maxb) + 4);
-  sa.bl_cap = wide ? 0u : up4(B);
-  sa.cm_cap = (maxb + 63) / 64 + 1;
-  sa.max_m = mm;
-  sa.max_bucket = maxb;
-  sa.wide = wide ? 1u : 0u;
-  sa.wave_lds = ((sa.f2_words + sa.scr_words + sa.rb_cap + 2 * sa.bl_cap) * 4 + sa.cm_cap * 8 + kSearchCtxBytes + 15) & ~15u;
+  size_search_lds(sa, std::max<uint32_t>(m, 1), maxb, B, wide);
   g_lds = (uint32_t*)std::aligned_alloc(16, sa.wave_lds);
   std::memset(g_lds, 0xA5, sa.wave_lds);  // LDS starts with garbage
 

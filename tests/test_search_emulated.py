@@ -129,3 +129,29 @@ def test_pilot_limit_is_reported(emu, tmp_path):
     assert e.value.code == binding.E_PILOT_OVERFLOW
     _, err = _run(emu, tmp_path, 0, hi, lo, hi.size, prm, limit)
     assert err & (1 << binding.E_PILOT_OVERFLOW)
+
+
+@pytest.mark.parametrize("lam,j", [(9.0, 1), (11.0, 0)])
+def test_pilot_limit_boundary_matches_oracle(emu, tmp_path, lam, j):
+    # limits at, just below and just above the largest pilot of a small bucket (2 .. 24 keys): the
+    # seed that reaches the limit and the last displacement allowed with it decide the outcome
+    hi, lo = _partition(2500, lam, j)
+    prm = oracle.params(lam=lam)
+    pil, _ = oracle.search_partition(hi, lo, hi.size, prm)
+    B = oracle.num_buckets(prm.partition_size, lam)
+    sz = np.bincount(oracle.buckets(lo, oracle.bucket_table(lam, 2500), B), minlength=B)
+    small = (sz >= 2) & (sz <= 24)
+    top = int(pil[small].max())
+    assert top >= hi.size  # the bucket needed a seed past 0
+    for limit in (top - 1, top, top + 1):
+        p = oracle.params(lam=lam, pilot_limit=limit)
+        try:
+            want, _ = oracle.search_partition(hi, lo, hi.size, p)
+            code = 0
+        except oracle.OracleError as e:
+            want, code = None, e.code
+        got, err = _run(emu, tmp_path, 0, hi, lo, hi.size, p, limit)
+        if code == 0:
+            assert err == 0 and np.array_equal(got, want), limit
+        else:
+            assert err & (1 << code), (limit, err)
