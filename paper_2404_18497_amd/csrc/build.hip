@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -39,6 +40,16 @@ constexpr int kBlock = 256;
 __global__ void k_fill_u32(uint32_t* __restrict__ p, uint64_t n, uint32_t v) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     p[i] = v;
+}
+
+// The start of a build in one launch: error words (4) and info words (8) cleared, and the n counters at
+// cnt.
+__global__ void k_build_clear(uint32_t* __restrict__ err, uint64_t* __restrict__ d64, uint32_t* __restrict__ cnt,
+                              uint64_t n) {
+  const uint64_t i0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+  if (i0 < 4) err[i0] = 0;
+  if (i0 < 8) d64[i0] = 0;
+  for (uint64_t i = i0; i < n; i += (uint64_t)gridDim.x * blockDim.x) cnt[i] = 0;
 }
 
 __global__ void k_fill_u64(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
@@ -1668,16 +1679,28 @@ struct Scratch {
   }
 };
 
+// Phase timing with events on the build's stream.  Events come from a per-thread, per-device pool
+// and go back to it, so a build creates none once its thread has built before.
 struct Timer {
   hipStream_t st;
+  int dev = 0;
   std::vector<hipEvent_t> ev;
-  explicit Timer(hipStream_t s) : st(s) {}
+  static std::map<int, std::vector<hipEvent_t>>& pool() {
+    static thread_local std::map<int, std::vector<hipEvent_t>> p;
+    return p;
+  }
+  explicit Timer(hipStream_t s) : st(s) { (void)hipGetDevice(&dev); }
   void mark() {
-    hipEvent_t e;
-    if (hipEventCreate(&e) == hipSuccess) {
-      (void)hipEventRecord(e, st);
-      ev.push_back(e);
+    std::vector<hipEvent_t>& free = pool()[dev];
+    hipEvent_t e = nullptr;
+    if (!free.empty()) {
+      e = free.back();
+      free.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      return;
     }
+    (void)hipEventRecord(e, st);
+    ev.push_back(e);
   }
   double ms(size_t a, size_t b) const {
     float t = 0;
@@ -1685,9 +1708,19 @@ struct Timer {
     return b < ev.size() ? t : 0;
   }
   ~Timer() {
-    for (auto e : ev) (void)hipEventDestroy(e);
+    std::vector<hipEvent_t>& free = pool()[dev];
+    free.insert(free.end(), ev.begin(), ev.end());
   }
 };
+
+// Waits for the stream's work by polling it: a blocking wait can wake tens of microseconds after
+// the work ends, and a build pays that at each of its host round trips.
+hipError_t spin_sync(hipStream_t st) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(st);
+    if (e != hipErrorNotReady) return e;
+  }
+}
 
 void configure_pool_once() {
   static std::once_flag once;
@@ -1783,8 +1816,6 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     PHOBIC_HIP(S.get(&pilots_pm, K * B));
   }
   PHOBIC_HIP(S.get(&pilots, K * B));  // encoder-major copy for the encoders
-  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(64), 0, st, err, (uint64_t)4, 0u);
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, d64, (uint64_t)8, (uint64_t)0);
   const uint32_t nbpad = next_pow2(B);
   const bool str = in.src == Src::Str;
 
@@ -1841,9 +1872,9 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     } else {
       PHOBIC_HIP(S.get(&kcodes, n));
     }
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(C)), dim3(kBlock), 0, st, ccnt, C, 0u);
     const size_t hist_lds = C * sizeof(uint32_t);
     tm.mark();  // 0
+    hipLaunchKernelGGL(k_build_clear, dim3(grid_for(std::max<uint64_t>(C, 8))), dim3(kBlock), 0, st, err, d64, ccnt, C);
     if (str)
       hipLaunchKernelGGL(k_coarse_count<true>, dim3(R), dim3(kCoarseThreads), hist_lds, st, in.keys, in.bytes,
                          in.offs, stage, n, per, prm.hash_seed, K, (uint32_t)gshift, (uint32_t)C, dshift, D, ccnt,
@@ -1908,9 +1939,10 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     PHOBIC_HIP(S.get(&dinfo, 8));
     PHOBIC_HIP(S.get(&codes, n));
     if (str) PHOBIC_HIP(S.get(&stage, n));
-    hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(K + 1)), dim3(kBlock), 0, st, cnt, K + 1, 0u);
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, dinfo, (uint64_t)8, (uint64_t)0);
     tm.mark();  // 0
+    hipLaunchKernelGGL(k_build_clear, dim3(grid_for(std::max<uint64_t>(K + 1, 8))), dim3(kBlock), 0, st, err, d64,
+                       cnt, K + 1);
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, st, dinfo, (uint64_t)8, (uint64_t)0);
     const bool lds_parts = K <= kLdsParts;  // few partitions: LDS counts per chunk of keys
     const uint32_t chunks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(2048, (n + 8191) / 8192));
     const uint64_t per = std::max<uint64_t>(1, (n + chunks - 1) / chunks);
@@ -2093,7 +2125,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     else
       (void)hipGetLastError();  // only a hint: a failure here must not surface later
   }
-  PHOBIC_HIP(hipStreamSynchronize(st));
+  PHOBIC_HIP(spin_sync(st));
   const uint64_t* hsh = hstats;
   const long long* hmm = (const long long*)(hstats + (uint64_t)B * 33);
   const uint32_t* hmax = (const uint32_t*)(hstats + (uint64_t)B * 33 + 2);
@@ -2186,7 +2218,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
     PHOBIC_HIP(hipGetLastError());
   }
   tm.mark();  // 7
-  PHOBIC_HIP(hipStreamSynchronize(st));
+  PHOBIC_HIP(spin_sync(st));
   auto t_host1 = std::chrono::steady_clock::now();
 
   h->info.hash_count_ms = tm.ms(0, 1);
@@ -2710,7 +2742,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   tm.mark();  // 1
   uint32_t hinfo[4];
   PHOBIC_HIP(hipMemcpyAsync(hinfo, err, sizeof(hinfo), hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipStreamSynchronize(st));
+  PHOBIC_HIP(spin_sync(st));
   if (hinfo[0] & (1u << PHOBIC_E_CAPACITY))
     return fail(PHOBIC_E_CAPACITY, "a group of partitions exceeds the LDS of the bucket-sort workgroup");
   if (hinfo[2] > kMaxTableSlots)
@@ -2786,7 +2818,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   PHOBIC_HIP(S.host(&herr, 6));
   PHOBIC_HIP(hipMemcpyAsync(hwords, dwords, (size_t)count * 8, hipMemcpyDeviceToHost, st));
   PHOBIC_HIP(hipMemcpyAsync(herr, err, 6 * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipStreamSynchronize(st));
+  PHOBIC_HIP(spin_sync(st));
   if (herr[0] & ((1u << PHOBIC_E_DUPLICATE) | (1u << PHOBIC_E_PILOT_OVERFLOW))) {
     const uint64_t J = (uint64_t)herr[4] | ((uint64_t)herr[5] << 32);
     const uint32_t t = (uint32_t)(std::upper_bound(hKbase.begin(), hKbase.end(), J) - hKbase.begin()) - 1;
@@ -2815,7 +2847,7 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   PHOBIC_HIP(hipGetLastError());
   tm.mark();  // 4
   PHOBIC_HIP(hipMemcpyAsync(hdrs, dh, (size_t)count * kHeaderWords * 8, hipMemcpyDeviceToHost, st));
-  PHOBIC_HIP(hipStreamSynchronize(st));
+  PHOBIC_HIP(spin_sync(st));
   phobic_build_info info{};
   info.bucket_sort_ms = tm.ms(0, 1);  // hashing, partitioning and bucketing of all chunks
   info.search_ms = tm.ms(2, 3);
