@@ -48,8 +48,9 @@ struct SearchArgs {
 hipError_t launch_search(SearchArgs& sa, uint64_t items, hipStream_t st, unsigned long long* queue);
 
 // Orders the K partitions of one MPHF by an estimate of their search cost, largest first, into
-// order[0 .. K) (scratch: 512 words); sets sa.order.  The order changes no result.
+// order[0 .. K) (scratch: order_scratch_words(K) words); sets sa.order.  The order changes no result.
 hipError_t order_partitions(SearchArgs& sa, uint32_t* order, uint32_t* scratch, hipStream_t st);
+inline uint64_t order_scratch_words(uint64_t K) { return 512 + (K + 3) / 4; }  // histogram, cursors, a byte per partition
 
 // The position buffer holds at least one entry per lane (a small bucket's seeds are hashed 64
 // positions at a time), and each wavefront keeps kSearchCtxBytes of argument fields in LDS.

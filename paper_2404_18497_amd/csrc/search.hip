@@ -777,29 +777,54 @@ __device__ void search_partition(const SearchArgs& a, uint64_t j, uint32_t* F2, 
 // counting-sorted by bin, largest first; the order inside a bin is arbitrary.
 // ---------------------------------------------------------------------------------------------
 constexpr uint32_t kOrderBins = 256;
+constexpr uint32_t kOrderThreads = 1024;
+constexpr uint32_t kOrderPer = 4;  // partitions per thread of k_order_scatter
 
-__device__ __forceinline__ uint32_t order_bin(const SearchArgs& a, uint64_t j) {
-  const uint32_t nb = a.nbk[j];
+// The estimate's bin for partition j, computed by the 64 lanes of a wavefront: lane x adds the
+// terms of the buckets x, x + 64, ... of the list (coalesced reads), stopping after the first
+// window of 64 that reaches buckets of fewer than 8 keys (sizes are non-increasing).  Uniform.
+__device__ __forceinline__ uint32_t order_bin(const SearchArgs& a, uint64_t j, uint32_t lane) {
+  const uint32_t nb = __builtin_amdgcn_readfirstlane(a.nbk[j]);
   const uint32_t nj = (uint32_t)(a.off[j + 1] - a.off[j]);
   const float m = (float)max(1u, (uint32_t)(a.toff[j + 1] - a.toff[j]));
-  float cost = 60.0f * (float)nb + 4.0f * (float)nj + 1.0f;
-  for (uint32_t x = 0; x < nb; x++) {
-    const uint32_t k = a.blist[j * a.B + x] >> 16;
-    if (k < 8) break;  // sizes are non-increasing
-    const float e = min((float)k * (float)(k - 1) / (2.0f * m), 40.0f);
-    cost += (60.0f + 4.0f * (float)k) * (__expf(e) - 1.0f);
+  float part = 0.0f;
+  for (uint32_t x0 = 0; x0 < nb; x0 += 64) {
+    const uint32_t x = x0 + lane;
+    const uint32_t k = x < nb ? a.blist[j * a.B + x] >> 16 : 0u;
+    if (k >= 8) {
+      const float e = min((float)k * (float)(k - 1) / (2.0f * m), 40.0f);
+      part += (60.0f + 4.0f * (float)k) * (__expf(e) - 1.0f);
+    }
+    if (__ballot(k >= 8) != ~0ULL) break;
   }
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) part += __shfl_xor(part, w);
+  const float cost = 60.0f * (float)nb + 4.0f * (float)nj + 1.0f + part;
   const int bin = (int)(__log2f(cost) * 16.0f) - 160;
-  return (uint32_t)min(max(bin, 0), (int)kOrderBins - 1);
+  return __builtin_amdgcn_readfirstlane((uint32_t)min(max(bin, 0), (int)kOrderBins - 1));
 }
 
 __global__ void k_order_clear(uint32_t* __restrict__ hist) { hist[threadIdx.x] = 0; }
 
-__global__ void k_order_count(SearchArgs a, uint32_t* __restrict__ hist) {
-  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < a.K; j += (uint64_t)gridDim.x * blockDim.x)
-    atomicAdd(&hist[order_bin(a, j)], 1u);
+// One wavefront per partition: its bin to bins[j], counted in the workgroup's LDS histogram, which
+// is added to hist with one atomic per non-empty bin.
+__global__ __launch_bounds__(kOrderThreads) void k_order_count(SearchArgs a, uint32_t* __restrict__ hist,
+                                                               uint8_t* __restrict__ bins) {
+  __shared__ uint32_t h[kOrderBins];
+  const uint32_t t = threadIdx.x, lane = t & 63;
+  constexpr uint32_t kWaves = kOrderThreads / 64;
+  if (t < kOrderBins) h[t] = 0;
+  __syncthreads();
+  for (uint64_t j = (uint64_t)blockIdx.x * kWaves + (t >> 6); j < a.K; j += (uint64_t)gridDim.x * kWaves) {
+    const uint32_t b = order_bin(a, j, lane);
+    if (lane == 0) {
+      bins[j] = (uint8_t)b;
+      atomicAdd(&h[b], 1u);
+    }
+  }
+  __syncthreads();
+  if (t < kOrderBins && h[t]) atomicAdd(&hist[t], h[t]);
 }
-
 // hist[b] -> start of bin b when the bins run from the largest estimate down; cursor cleared
 __global__ void k_order_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__ cursor) {
   __shared__ uint32_t v[kOrderBins];
@@ -816,11 +841,31 @@ __global__ void k_order_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__
   cursor[t] = 0;
 }
 
-__global__ void k_order_scatter(SearchArgs a, const uint32_t* __restrict__ start, uint32_t* __restrict__ cursor,
-                                uint32_t* __restrict__ order) {
-  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < a.K; j += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t b = order_bin(a, j);
-    order[start[b] + atomicAdd(&cursor[b], 1u)] = (uint32_t)j;
+// Workgroup g places the partitions [g kOrderThreads kOrderPer, ...): ranks within the workgroup
+// from LDS counts, one global atomic per non-empty bin for the workgroup's range in that bin.
+__global__ __launch_bounds__(kOrderThreads) void k_order_scatter(uint64_t K, const uint8_t* __restrict__ bins,
+                                                                 const uint32_t* __restrict__ start,
+                                                                 uint32_t* __restrict__ cursor,
+                                                                 uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[kOrderBins], base[kOrderBins];
+  const uint32_t t = threadIdx.x;
+  if (t < kOrderBins) cnt[t] = 0;
+  __syncthreads();
+  const uint64_t j0 = (uint64_t)blockIdx.x * kOrderThreads * kOrderPer;
+  uint32_t b[kOrderPer], r[kOrderPer];
+#pragma unroll
+  for (uint32_t u = 0; u < kOrderPer; u++) {
+    const uint64_t j = j0 + (uint64_t)u * kOrderThreads + t;
+    b[u] = j < K ? bins[j] : 0u;
+    r[u] = j < K ? atomicAdd(&cnt[b[u]], 1u) : 0u;
+  }
+  __syncthreads();
+  if (t < kOrderBins && cnt[t]) base[t] = start[t] + atomicAdd(&cursor[t], cnt[t]);
+  __syncthreads();
+#pragma unroll
+  for (uint32_t u = 0; u < kOrderPer; u++) {
+    const uint64_t j = j0 + (uint64_t)u * kOrderThreads + t;
+    if (j < K) order[base[b[u]] + r[u]] = (uint32_t)j;
   }
 }
 
@@ -915,12 +960,15 @@ hipError_t launch_search_m(SearchArgs& sa, uint64_t items, const phobic_search_c
 hipError_t order_partitions(SearchArgs& sa, uint32_t* order, uint32_t* scratch, hipStream_t st) {
   uint32_t* hist = scratch;
   uint32_t* cursor = scratch + kOrderBins;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>((sa.K + 255) / 256, 4096);
+  uint8_t* bins = (uint8_t*)(scratch + 2 * kOrderBins);
+  const uint32_t cgrid = (uint32_t)std::min<uint64_t>((sa.K + kOrderThreads / 64 - 1) / (kOrderThreads / 64), 1024);
+  const uint32_t sgrid = (uint32_t)((sa.K + kOrderThreads * kOrderPer - 1) / (kOrderThreads * kOrderPer));
   sa.order = nullptr;
   hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(kOrderBins), 0, st, hist);
-  hipLaunchKernelGGL(k_order_count, dim3(grid), dim3(256), 0, st, sa, hist);
+  hipLaunchKernelGGL(k_order_count, dim3(cgrid), dim3(kOrderThreads), 0, st, sa, hist, bins);
   hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(kOrderBins), 0, st, hist, cursor);
-  hipLaunchKernelGGL(k_order_scatter, dim3(grid), dim3(256), 0, st, sa, (const uint32_t*)hist, cursor, order);
+  hipLaunchKernelGGL(k_order_scatter, dim3(sgrid), dim3(kOrderThreads), 0, st, sa.K, (const uint8_t*)bins,
+                     (const uint32_t*)hist, cursor, order);
   sa.order = order;
   return hipGetLastError();
 }
