@@ -2082,7 +2082,7 @@ phobic_status build_impl(const BuildInput& in, const phobic_params* params, hipS
   if (!wide && K > 1) {  // costly partitions first
     uint32_t *order, *oscr;
     PHOBIC_HIP(S.get(&order, K));
-    PHOBIC_HIP(S.get(&oscr, 512));
+    PHOBIC_HIP(S.get(&oscr, order_scratch_words(K)));
     PHOBIC_HIP(order_partitions(sa, order, oscr, st));
   }
   PHOBIC_HIP(launch_search(sa, K, st, queue));
