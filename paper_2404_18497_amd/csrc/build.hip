@@ -874,6 +874,8 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(4, 
   uint32_t* rec = lds + 2 * span;  // per key: partition << 29 | bucket << 16 | rank
   __shared__ uint32_t part[kSegThreads];
   __shared__ uint32_t psize[kMaxG], nonempty[kMaxG];
+  __shared__ uint64_t Ts[kTableIntervals + 1];  // the bucket-function table: LDS reads instead of
+                                                // 64 scattered cache lines per wavefront load
   const uint32_t tid = threadIdx.x;
   const uint64_t c = blockIdx.x;
   const uint64_t j0 = jbase + (c << gshift);
@@ -891,6 +893,7 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(4, 
   }
   for (uint32_t x = tid; x < span; x += kSegThreads) cnt[x] = 0;
   if (tid < kMaxG) { psize[tid] = 0; nonempty[tid] = 0; }
+  for (uint32_t x = tid; x <= kTableIntervals; x += kSegThreads) Ts[x] = T[x];
   __syncthreads();
   // Items in batches of kSegBatch: the batch's loads are unconditional (the index clamped to the
   // bin), then its hashes and bucket-table reads, so each batch costs one round trip of each
@@ -930,7 +933,7 @@ __global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(4, 
         cd[u] = make_ulonglong2(hi, lo);
       }
       const uint32_t p = kIn == kInRecords ? (uint32_t)(cd[u].y & 7) : (uint32_t)(__umul64hi(cd[u].x, K) - j0);
-      pb[u] = (p << 16) | bucket_of(cd[u].y, T, B);
+      pb[u] = (p << 16) | bucket_of(cd[u].y, Ts, B);
     }
 #pragma unroll
     for (int u = 0; u < kBat; u++) {

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <type_traits>
 
 #include "phobic_internal.h"
 
@@ -122,13 +123,28 @@ __device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, 
   return get_bits(a.img + a.sec_remap, (g - a.n) * a.wremap, a.wremap);
 }
 
+// bucket_of over a table held in 64-bit words, or in 32-bit words where the last point, 2^32, reads
+// as 0: the difference of two points is then still right modulo 2^32, and it is below 2^32.
+__device__ __forceinline__ uint32_t bucket_of_tab(uint64_t lo, const uint64_t* __restrict__ T, uint32_t B) {
+  return bucket_of(lo, T, B);
+}
+__device__ __forceinline__ uint32_t bucket_of_tab(uint64_t lo, const uint32_t* __restrict__ T, uint32_t B) {
+  const uint32_t k = (uint32_t)(lo >> 53);
+  const uint64_t f = (lo >> 21) & 0xFFFFFFFFULL;
+  const uint32_t t0 = T[k], t1 = T[k + 1];
+  const uint64_t y = (uint64_t)t0 + (((uint64_t)(uint32_t)(t1 - t0) * f) >> 32);
+  const uint32_t b = (uint32_t)((y * B) >> 32);
+  return b < B - 1 ? b : B - 1;
+}
+
 // kN lookups per thread in lockstep: every stage issues the reads of all kN lookups before any of
 // them is consumed, so one wavefront keeps kN times as many independent cache-line reads in flight
 // (the query is bound by the latency of its chain of dependent reads, not by bandwidth).  Same
 // arithmetic as query_code.
-template <int kN>
-__device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (&hi)[kN], const uint64_t (&lo)[kN],
-                                            uint64_t (&res)[kN]) {
+template <int kN, typename TabT>
+__device__ __forceinline__ void query_codes(const QueryArgs& a, const TabT* __restrict__ T,
+                                            const uint64_t* __restrict__ E, const uint64_t (&hi)[kN],
+                                            const uint64_t (&lo)[kN], uint64_t (&res)[kN]) {
   const uint64_t* __restrict__ offs = a.img + a.sec_off;
   const uint64_t* __restrict__ un = a.img + a.sec_unary;
   const uint64_t* __restrict__ sel = a.img + a.sec_sel;
@@ -138,10 +154,10 @@ __device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (
 #pragma unroll
   for (int q = 0; q < kN; q++) {
     j[q] = __umul64hi(hi[q], a.K);
-    i[q] = bucket_of(lo[q], a.table, a.B);
+    i[q] = bucket_of_tab(lo[q], T, a.B);
   }
 #pragma unroll
-  for (int q = 0; q < kN; q++) e[q] = a.img[a.sec_enc + i[q]];
+  for (int q = 0; q < kN; q++) e[q] = E[i[q]];
   // offsets, low bits and select samples: independent of each other.  A lookup whose encoder is
   // Rice (u) reads the unary stream at its value t = (i - ncompact) K + j; one of a Compact encoder
   // (all of a Compact image, the first ncompact of a mixed one) is done with its field.
@@ -233,15 +249,30 @@ __device__ __forceinline__ void query_codes(const QueryArgs& a, const uint64_t (
 }
 
 constexpr int kQN = 4;
+constexpr uint32_t kQEncLds = 1024;  // encoders the LDS-staged query holds
 
-// Thread x handles keys x, x + stride, ..., kQN of them per round.
+// Thread x handles keys x, x + stride, ..., kQN of them per round.  kLds: the bucket-function table
+// (as 32-bit words) and the encoder words (B <= kQEncLds) are read from LDS, where the workgroup
+// copies them first: a wavefront's read of either touches dozens of cache lines, and the lookup is
+// bound by its cache requests (10.9 KB per workgroup at B = 358, 7% off the query time at 10^8 keys).
+template <bool kLds, typename TabT = typename std::conditional<kLds, uint32_t, uint64_t>::type>
 __global__ __launch_bounds__(kQBlock) void k_query_u64(QueryArgs a, const uint64_t* __restrict__ keys, uint64_t n,
-                                                       uint64_t* __restrict__ out) {
+                                                        uint64_t* __restrict__ out) {
   if (a.n == 0) {
     for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < n; x += (uint64_t)gridDim.x * blockDim.x)
       out[x] = 0;
     return;
   }
+  __shared__ TabT sT[kLds ? kTableIntervals + 1 : 1];
+  __shared__ uint64_t sE[kLds ? kQEncLds : 1];
+  const uint64_t* E = a.img + a.sec_enc;
+  if (kLds) {
+    for (uint32_t x = threadIdx.x; x <= kTableIntervals; x += kQBlock) sT[x] = (TabT)a.table[x];
+    for (uint32_t x = threadIdx.x; x < a.B; x += kQBlock) sE[x] = E[x];
+    __syncthreads();
+    E = sE;
+  }
+  const TabT* T = kLds ? (const TabT*)sT : (const TabT*)a.table;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t x0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x0 < n; x0 += stride * kQN) {
     uint64_t hi[kQN], lo[kQN], res[kQN];
@@ -250,7 +281,7 @@ __global__ __launch_bounds__(kQBlock) void k_query_u64(QueryArgs a, const uint64
       const uint64_t x = x0 + q * stride;
       hash_key_u64(keys[x < n ? x : x0], a.seed, hi[q], lo[q]);
     }
-    query_codes<kQN>(a, hi, lo, res);
+    query_codes<kQN, TabT>(a, T, E, hi, lo, res);
 #pragma unroll
     for (int q = 0; q < kQN; q++) {
       const uint64_t x = x0 + q * stride;
@@ -335,8 +366,12 @@ extern "C" phobic_status phobic_query_u64(const phobic_mphf* h, const uint64_t* 
   if (!h) return fail(PHOBIC_E_INVALID, "null handle");
   if (n == 0) return PHOBIC_OK;
   if (!d_keys || !d_pos) return fail(PHOBIC_E_INVALID, "null key or output pointer");
-  hipLaunchKernelGGL(k_query_u64, dim3(query_grid(n, kQN)), dim3(kQBlock), 0, (hipStream_t)hip_stream, h->qa, d_keys, n,
-                     d_pos);
+  if (h->qa.B <= kQEncLds)
+    hipLaunchKernelGGL((k_query_u64<true>), dim3(query_grid(n, kQN)), dim3(kQBlock), 0, (hipStream_t)hip_stream,
+                       h->qa, d_keys, n, d_pos);
+  else
+    hipLaunchKernelGGL((k_query_u64<false>), dim3(query_grid(n, kQN)), dim3(kQBlock), 0, (hipStream_t)hip_stream,
+                       h->qa, d_keys, n, d_pos);
   PHOBIC_HIP(hipGetLastError());
   return PHOBIC_OK;
 }
