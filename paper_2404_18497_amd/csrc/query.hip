@@ -124,7 +124,8 @@ __device__ __forceinline__ uint64_t query_code(const QueryArgs& a, uint64_t hi, 
 }
 
 // bucket_of over a table held in 64-bit words, or in 32-bit words where the last point, 2^32, reads
-// as 0: the difference of two points is then still right modulo 2^32, and it is below 2^32.
+// as 0: the difference of two points is then still right modulo 2^32, and it is below 2^32.  Every
+// other point is below 2^32 (the bucket functions stay below 1 short of x = 1 by far more than 2^-32).
 __device__ __forceinline__ uint32_t bucket_of_tab(uint64_t lo, const uint64_t* __restrict__ T, uint32_t B) {
   return bucket_of(lo, T, B);
 }
