@@ -11,8 +11,8 @@
     ns/query (lower is better). The same line then carries the rest of the metric, each after the
     timed region: lambda 5 and 9 on the same keys and lookups; the mixed-coding curve (query ns/key
     and bits/key for several counts of leading Compact encoders); 100M random strings (lengths 10-50,
-    [a-z0-9]) at alpha 1 and 0.99 with 100M lookups; a short serving trace (p50/p99 per request kind,
-    plain vs served); the bucket assignment functions compared in Sec. 3.1 (beta_*, PTHash's skewed,
+    [a-z0-9]) at alpha 1 and 0.99 with 100M lookups; a short serving trace at 0.5, 0.8 and 0.95 of the
+    plain capacity (``--loads``; p50/p99 per request kind, throughput and mean batch, plain vs served); the bucket assignment functions compared in Sec. 3.1 (beta_*, PTHash's skewed,
     CHD's uniform) on the same keys; and the oracle on the host cores (``cpu_baseline``).
     ``--no-extras`` skips all but the last.
 --workload batch: 4096 MPHFs, key counts lognormal(median 50K, sigma 1.5) clipped to [1K, 10M]
@@ -326,7 +326,8 @@ def headline(args):
     if not args.no_extras:
         out["strings"] = strings_rows(args, qstreams)
         log("serving (short trace)")
-        out["serving"] = serve_run(args.requests, [args.load])
+        loads = [float(x) for x in args.loads.split(",")] if args.loads else [0.5, 0.8, 0.95]
+        out["serving"] = serve_run(args.requests, loads)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args)
