@@ -2773,6 +2773,12 @@ phobic_status build_batch_impl(const uint64_t* const* keys, const uint64_t* coun
   sa.fail_part = (unsigned long long*)(err + 4);
   sa.order = nullptr;
   tm.mark();  // 2
+  if (Ktot > 1) {  // costly partitions of all MPHFs first
+    uint32_t *order, *oscr;
+    PHOBIC_HIP(S.get(&order, Ktot));
+    PHOBIC_HIP(S.get(&oscr, order_scratch_words(Ktot)));
+    PHOBIC_HIP(order_partitions(sa, order, oscr, st));
+  }
   PHOBIC_HIP(launch_search(sa, Ktot, st, queue));
   tm.mark();  // 3
 
