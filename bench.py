@@ -399,14 +399,17 @@ def batch_mode(args):
     total = int(sizes.sum())
     tuned, table = None, None
     if not args.no_tune:
-        log("autotuning the search shape on the first 512 key sets")
-        tuned, table = autotune.tune_batch(dev[:512], prm, repeats=1, log=log)
+        # on the whole batch: a sample of 512 key sets (a eighth of the partitions) favoured one wavefront
+        # per partition, while the whole batch runs faster on a persistent grid
+        log("autotuning the search shape on the whole batch")
+        tuned, table = autotune.tune_batch(binding.BatchKeys(dev), prm, repeats=1, log=log)
     cfg = binding.get_search_config()
     log("batched build")
-    binding.build_batch_u64(dev, prm)  # warm-up
+    bkeys = binding.BatchKeys(dev)  # the key sets' pointer arrays, checked once like the resident keys
+    binding.build_batch_u64(bkeys, prm)  # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    hs = binding.build_batch_u64(dev, prm)
+    hs = binding.build_batch_u64(bkeys, prm)
     torch.cuda.synchronize()
     t_batch = time.perf_counter() - t0
     info = hs[0].build_info()

@@ -27,7 +27,7 @@ def _time_search(build, repeats: int) -> float:
     best = float("inf")
     for _ in range(repeats):
         handles = build()
-        hs = handles if isinstance(handles, list) else [handles]
+        hs = [handles] if isinstance(handles, binding.MPHF) else handles
         best = min(best, hs[0].build_info()["search_ms"])
         for h in hs:
             h.close()

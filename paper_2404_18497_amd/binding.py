@@ -250,16 +250,65 @@ def build_str(data, offsets, prm: Params, stream=None) -> MPHF:
     return MPHF(h)
 
 
-def build_batch_u64(key_tensors, prm: Params, stream=None) -> list:
-    """Builds one MPHF per tensor of keys in a single batched pass; returns the handles in order."""
-    count = len(key_tensors)
-    for t in key_tensors:
-        _dptr(t)
-    ptrs = (C.c_void_p * max(count, 1))(*[t.data_ptr() if t.numel() else None for t in key_tensors])
-    counts = (C.c_uint64 * max(count, 1))(*[t.numel() for t in key_tensors])
-    outs = (C.c_void_p * max(count, 1))()
-    _check(lib().phobic_build_batch_u64(ptrs, counts, count, C.byref(prm), _stream(stream), outs))
-    return [MPHF(C.c_void_p(outs[t])) for t in range(count)]
+class BatchKeys:
+    """The key sets of a batched build, checked once, with the host arrays the C-ABI takes (device
+    pointers and counts); reusable across builds of the same tensors, which it keeps alive."""
+
+    def __init__(self, key_tensors):
+        self.tensors = list(key_tensors)
+        self.count = len(self.tensors)
+        for t in self.tensors:
+            _dptr(t)
+        n = max(self.count, 1)
+        self.ptrs = (C.c_void_p * n)(*[t.data_ptr() if t.numel() else None for t in self.tensors])
+        self.counts = (C.c_uint64 * n)(*[t.numel() for t in self.tensors])
+
+
+class BatchMPHFs:
+    """The handles of a batched build, in order.  Member t's MPHF wrapper is made when it is first
+    read and owns its handle from then on; the handles never read are freed with this object."""
+
+    def __init__(self, outs, count: int):
+        self._outs = outs
+        self._count = count
+        self._made = [None] * count
+
+    def __len__(self) -> int:
+        return self._count
+
+    def __getitem__(self, t):
+        if isinstance(t, slice):
+            return [self[i] for i in range(*t.indices(self._count))]
+        if t < 0:
+            t += self._count
+        if not 0 <= t < self._count:
+            raise IndexError(t)
+        if self._made[t] is None:
+            self._made[t] = MPHF(C.c_void_p(self._outs[t]))
+        return self._made[t]
+
+    def __iter__(self):
+        return (self[t] for t in range(self._count))
+
+    def close(self):
+        made = getattr(self, "_made", None)
+        if made is None or _lib is None:
+            return
+        for t, m in enumerate(made):  # wrappers already made free their own handles
+            if m is None and self._outs[t]:
+                _lib.phobic_free(C.c_void_p(self._outs[t]))
+        self._made = None
+
+    __del__ = close
+
+
+def build_batch_u64(key_tensors, prm: Params, stream=None) -> BatchMPHFs:
+    """Builds one MPHF per key set in a single batched pass; returns the handles in order.
+    key_tensors: a list of device tensors or a BatchKeys made from one (checked once, reusable)."""
+    bk = key_tensors if isinstance(key_tensors, BatchKeys) else BatchKeys(key_tensors)
+    outs = (C.c_void_p * max(bk.count, 1))()
+    _check(lib().phobic_build_batch_u64(bk.ptrs, bk.counts, bk.count, C.byref(prm), _stream(stream), outs))
+    return BatchMPHFs(outs, bk.count)
 
 
 def query_multi_u64(handles, key_tensors, out_tensors, stream=None, noalloc=False):
