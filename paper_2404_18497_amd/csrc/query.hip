@@ -311,9 +311,32 @@ struct QueryJob {
 };
 constexpr uint32_t kMultiItems = 4;
 
+// Lookups first + t kQBlock + threadIdx.x (t < kMultiItems) of request jb, in lockstep (query_codes).
+// The block exists for the request, so its first lookup is in range and stands in for those past the
+// end.
+template <typename TabT>
+__device__ __forceinline__ void multi_items(const QueryJob& jb, const TabT* T, const uint64_t* E, uint64_t first) {
+  uint64_t hi[kMultiItems], lo[kMultiItems], res[kMultiItems];
+#pragma unroll
+  for (uint32_t t = 0; t < kMultiItems; t++) {
+    const uint64_t x = first + t * kQBlock + threadIdx.x;
+    hash_key_u64(jb.keys[x < jb.n ? x : first], jb.qa.seed, hi[t], lo[t]);
+  }
+  query_codes<(int)kMultiItems, TabT>(jb.qa, T, E, hi, lo, res);
+#pragma unroll
+  for (uint32_t t = 0; t < kMultiItems; t++) {
+    const uint64_t x = first + t * kQBlock + threadIdx.x;
+    if (x < jb.n) jb.out[x] = res[t];
+  }
+}
+
+// As k_query_u64 (the bucket table and encoder words staged in LDS when B <= kQEncLds), one request
+// per block.
 __global__ __launch_bounds__(kQBlock) void k_query_multi(const QueryJob* __restrict__ jobs,
                                                          const uint64_t* __restrict__ bstart, uint32_t count) {
   __shared__ uint32_t sj;
+  __shared__ uint32_t sT[kTableIntervals + 1];
+  __shared__ uint64_t sE[kQEncLds];
   if (threadIdx.x == 0) {
     uint32_t lo = 0, hi = count;
     while (hi - lo > 1) {
@@ -325,14 +348,21 @@ __global__ __launch_bounds__(kQBlock) void k_query_multi(const QueryJob* __restr
   __syncthreads();
   const QueryJob& jb = jobs[sj];
   const uint64_t first = (uint64_t)(blockIdx.x - bstart[sj]) * kQBlock * kMultiItems;
-#pragma unroll
-  for (uint32_t t = 0; t < kMultiItems; t++) {
-    const uint64_t x = first + t * kQBlock + threadIdx.x;
-    if (x < jb.n) {
-      uint64_t hi, lo;
-      hash_key_u64(jb.keys[x], jb.qa.seed, hi, lo);
-      jb.out[x] = query_code(jb.qa, hi, lo);
+  if (jb.qa.n == 0) {  // an empty MPHF: every key maps to 0
+    for (uint32_t t = 0; t < kMultiItems; t++) {
+      const uint64_t x = first + t * kQBlock + threadIdx.x;
+      if (x < jb.n) jb.out[x] = 0;
     }
+    return;
+  }
+  const uint64_t* E = jb.qa.img + jb.qa.sec_enc;
+  if (jb.qa.B <= kQEncLds) {
+    for (uint32_t x = threadIdx.x; x <= kTableIntervals; x += kQBlock) sT[x] = (uint32_t)jb.qa.table[x];
+    for (uint32_t x = threadIdx.x; x < jb.qa.B; x += kQBlock) sE[x] = E[x];
+    __syncthreads();
+    multi_items<uint32_t>(jb, sT, sE, first);
+  } else {
+    multi_items<uint64_t>(jb, jb.qa.table, E, first);
   }
 }
 
