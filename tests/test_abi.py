@@ -110,3 +110,32 @@ def test_server_config_rejected_on_host():
         assert e.value.code == binding.E_INVALID
     with pytest.raises(binding.PhobicError):
         binding.Server(p, budget_bytes=0)
+
+
+def test_batch_handles_are_made_on_first_use(monkeypatch):
+    """The batch result makes a member's wrapper when it is first read, keeps it, and frees only the
+    handles never handed out (here stand-in handle values and a recording free, no device work)."""
+    from paper_2404_18497_amd import binding
+
+    freed = []
+
+    class FakeLib:
+        def phobic_free(self, h):
+            freed.append(h.value)
+
+    monkeypatch.setattr(binding, "_lib", FakeLib())
+    outs = (C.c_void_p * 4)(0x1000, 0x2000, 0x3000, 0x4000)
+    b = binding.BatchMPHFs(outs, 4)
+    assert len(b) == 4
+    m1 = b[1]
+    assert b[1] is m1 and m1.h.value == 0x2000
+    assert [m.h.value for m in b[-2:]] == [0x3000, 0x4000]
+    with pytest.raises(IndexError):
+        b[4]
+    m1.owned = False  # keep the stand-in handle away from the recording free at garbage collection
+    for t in (2, 3):
+        b[t].owned = False
+    b.close()
+    assert freed == [0x1000]  # only member 0 was never handed out
+    b.close()  # a second close frees nothing more
+    assert freed == [0x1000]
