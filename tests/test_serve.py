@@ -33,21 +33,30 @@ def _dev(torch, a):
 
 
 def test_query_multi_matches_single_queries(torch):
-    prm = binding.params(lam=6.0)
-    sets = [synth.u64_keys(n, 40 + n) for n in (1000, 50_000, 7, 250_000)]
-    hs = [binding.build_u64(_dev(torch, k), prm) for k in sets]
+    # the last MPHF has 1667 buckets per partition (P = 10000), beyond what a workgroup stages in LDS
+    prms = [(2500, 6.0)] * 4 + [(10_000, 6.0)]
+    sets = [synth.u64_keys(n, 40 + n) for n in (1000, 50_000, 7, 250_000, 30_000)]
+    hs = [binding.build_u64(_dev(torch, k), binding.params(partition_size=P, lam=lam))
+          for k, (P, lam) in zip(sets, prms)]
+    assert hs[-1].B > 1024
+    empty = binding.build_u64(_dev(torch, np.zeros(0, np.uint64)), binding.params(lam=6.0))
     rng = np.random.default_rng(3)
     reqs = []
-    for r in range(12):
+    for r in range(16):
         t = int(rng.integers(0, len(sets)))
         q = sets[t][rng.integers(0, sets[t].size, int(rng.integers(0, 30_000)))]
         reqs.append((t, _dev(torch, q)))
-    outs = [torch.empty(q.numel(), dtype=torch.int64, device="cuda") for _, q in reqs]
-    binding.query_multi_u64([hs[t] for t, _ in reqs], [q for _, q in reqs], outs)
-    for (t, q), o in zip(reqs, outs):
-        assert torch.equal(o, hs[t].query_u64(q))
+    # keys of a non-empty set against the empty MPHF: every position is 0, as for a single query
+    stray = _dev(torch, sets[1][:5000])
+    handles = [hs[t] for t, _ in reqs] + [empty]
+    keys = [q for _, q in reqs] + [stray]
+    outs = [torch.empty(q.numel(), dtype=torch.int64, device="cuda") for q in keys]
+    binding.query_multi_u64(handles, keys, outs)
+    for h, q, o in zip(handles, keys, outs):
+        assert torch.equal(o, h.query_u64(q))
+    assert int(outs[-1].abs().sum()) == 0
     # and against the oracle's positions for the same key sets
-    refs = [oracle.build_u64(k, oracle.params(lam=6.0), threads=8) for k in sets]
+    refs = [oracle.build_u64(k, oracle.params(partition_size=P, lam=lam), threads=8) for k, (P, lam) in zip(sets, prms)]
     for (t, q), o in zip(reqs, outs):
         qh = q.cpu().numpy().view(np.uint64)
         assert np.array_equal(o.cpu().numpy().view(np.uint64), refs[t].query_u64(qh))
