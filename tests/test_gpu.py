@@ -222,6 +222,10 @@ def test_nonminimal_remap_parity(torch, alpha):
     _say("alpha", alpha)
     g, r = _both(torch, keys, lam=6.0, alpha=alpha)
     _check_same(torch, g, r, keys)
+    # non-members, some of which land in table slots past n and go through the remap table
+    other = synth.u64_keys(50_000, 98)
+    pos = g.query_u64(_dev(torch, other)).cpu().numpy().view(np.uint64)
+    assert np.array_equal(pos, r.query_u64(other)) and int(pos.max()) < keys.size
 
 
 def test_strings_parity(torch):
@@ -284,10 +288,11 @@ def test_serialize_roundtrip_and_oracle_reads_gpu_image(torch):
     assert np.array_equal(a, b)
     assert np.array_equal(oracle.query_image_u64(img, keys), a.view(np.uint64))
     assert g.size_bits() == 64 * img.size
-    # non-members land somewhere in [0, n)
+    # non-members land somewhere in [0, n), at the position the oracle's query gives them
     other = synth.u64_keys(100_000, 99)
     pos = g.query_u64(_dev(torch, other)).cpu().numpy()
     assert pos.min() >= 0 and pos.max() < keys.size
+    assert np.array_equal(oracle.query_image_u64(img, other), pos.view(np.uint64))
     # corruptions that would let a query read outside the image are refused on the host
     sec_unary, sec_sel = int(img[15]), int(img[16])
     for word, bit in [(0, 3), (sec_unary + 2, 17), (sec_sel, 40), (21, 1)]:
