@@ -241,6 +241,11 @@ def test_strings_parity(torch):
         pos = g.query_str(torch.from_numpy(buf).cuda(), _dev(torch, offs)).cpu().numpy().view(np.uint64)
         assert np.array_equal(pos, r.query_str(buf, offs))
         assert np.array_equal(np.sort(pos), np.arange(offs.size - 1, dtype=np.uint64))
+        # strings outside the set (another seed; the empty string among them) go where the oracle sends them
+        obuf, ooffs = synth.ascii_strings(20_000, 31)
+        ooffs = np.concatenate([ooffs[:1], ooffs])  # string 0 is empty
+        opos = g.query_str(torch.from_numpy(obuf).cuda(), _dev(torch, ooffs)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(opos, r.query_str(obuf, ooffs)) and int(opos.max()) < offs.size - 1
 
 
 def test_errors(torch):
