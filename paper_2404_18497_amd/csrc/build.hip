@@ -2279,25 +2279,38 @@ __global__ __launch_bounds__(kCoarseThreads) void k_batch_coarse(const BatchDesc
   }
   __syncthreads();
   const uint64_t a = (uint64_t)blockIdx.x * per, b = min(nchunk, a + per);
+  // the thread's keys only move forward, and so does their MPHF t: its fields stay in registers and
+  // are reloaded only where the next MPHF starts (empty MPHFs share nbase with their successor), so
+  // that a key's load does not wait on loads of its descriptor
   uint32_t t = a + tid < b ? batch_owner(d, t0, t1, nb0 + a + tid) : t0;
+  uint64_t tnb = d[t].nbase, tK = d[t].K, tKb = d[t].Kbase;
+  uint64_t tnext = t + 1 < t1 ? d[t + 1].nbase : ~0ULL;
+  const uint64_t* tkeys = d[t].keys;
   const uint64_t gmask = (1ULL << gshift) - 1;
-  // four keys per thread and round: owners found (they only move forward) and keys loaded for all
-  // four before any is hashed, so that the loads are in flight together
+  // four keys per thread and round, loaded before any is hashed, so that the loads are in flight
+  // together
   constexpr int kU = 4;
   for (uint64_t i0 = a + tid; i0 < b; i0 += (uint64_t)kU * kCoarseThreads) {
-    uint64_t key[kU];
-    uint32_t tt[kU];
+    uint64_t key[kU], kK[kU], kKb[kU];
 #pragma unroll
     for (int u = 0; u < kU; u++) {
       const uint64_t gi = nb0 + min(i0 + (uint64_t)u * kCoarseThreads, b - 1);
-      while (t + 1 < t1 && d[t + 1].nbase <= gi) t++;
-      tt[u] = t;
-      key[u] = d[t].keys[gi - d[t].nbase];
+      while (gi >= tnext) {
+        t++;
+        tnb = tnext;
+        tK = d[t].K;
+        tKb = d[t].Kbase;
+        tkeys = d[t].keys;
+        tnext = t + 1 < t1 ? d[t + 1].nbase : ~0ULL;
+      }
+      key[u] = tkeys[gi - tnb];
+      kK[u] = tK;
+      kKb[u] = tKb;
     }
 #pragma unroll
     for (int u = 0; u < kU; u++) {
       if (i0 + (uint64_t)u * kCoarseThreads >= b) break;
-      const uint64_t J = d[tt[u]].Kbase + __umul64hi(mix_a(key[u] ^ seed), d[tt[u]].K);
+      const uint64_t J = kKb[u] + __umul64hi(mix_a(key[u] ^ seed), kK[u]);
       const uint32_t bin = (uint32_t)((J - Jc0) >> gshift);
       if (kScatter) {
         uint64_t hi, lo;
